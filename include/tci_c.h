@@ -1,0 +1,346 @@
+/*
+ * tci_c.h -- C ABI of the MI355X (gfx950) two-site MPS update library.
+ *
+ * The calls follow the problem statement of the Tensor Computing Interface
+ * (TCI, arXiv:2512.23917): a typed tensor with shape and bond labels,
+ * transpose/reshape, label-based contraction, QR, (truncated) SVD, norms.
+ * "Spec" below is the paper's appendix that specifies the TCI API; the
+ * subsection and function named after it is the passage each call follows.
+ *
+ * Conventions for every function:
+ *   - Return value: tci_status, TCI_OK (0) on success.  On failure the
+ *     message of the last error is available from tci_last_error() (per
+ *     thread) and outputs of out-of-place calls are left unchanged.
+ *   - Tensors are dense and row-major (last index fastest); the reshape
+ *     passage of the Spec fixes that reshaping keeps the memory order.
+ *   - Element types: TCI_F32, TCI_F64, TCI_C64 (2 x float), TCI_C128
+ *     (2 x double, the layout of C99 double complex).
+ *   - Device memory: tensor data lives in the context's GPU memory.  A
+ *     tensor created by tci_allocate / tci_zeros / tci_copy owns it; one
+ *     created by tci_wrap borrows memory the caller keeps alive.
+ *   - Output tensors are handles created by the caller (any shape, e.g. by
+ *     tci_allocate with order 0); the library sets their shape and, for
+ *     owning handles, re-allocates their storage when it is too small.  A
+ *     wrapped (borrowing) output must already be large enough, otherwise
+ *     TCI_ERR_SHAPE.
+ *   - All work is ordered on the context's HIP stream.  Calls that return
+ *     host scalars or data-dependent shapes (norm, trunc_svd, qr, close,
+ *     the update composites) synchronise that stream before returning.
+ *   - Using a handle after it was destroyed is undefined (Spec, context
+ *     routines: a destroyed context must not be used again).
+ */
+#ifndef TCI_C_H
+#define TCI_C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tci_status;
+#define TCI_OK 0
+#define TCI_ERR_INVALID_ARGUMENT 1  /* null handle, bad k_rows, chi_min > chi_max, ... */
+#define TCI_ERR_SHAPE 2             /* dimension mismatch, output too small */
+#define TCI_ERR_LABEL 3             /* bad label lists in contract */
+#define TCI_ERR_DTYPE 4             /* unsupported or mismatched element type */
+#define TCI_ERR_OUT_OF_MEMORY 5     /* device allocation failed */
+#define TCI_ERR_DEVICE 6            /* any HIP runtime error (message has hipGetErrorString) */
+#define TCI_ERR_NOT_CONVERGED 7
+#define TCI_ERR_NUMERIC 8           /* NaN / Inf where a finite value is required */
+#define TCI_ERR_UNSUPPORTED 9
+
+typedef enum { TCI_F32 = 0, TCI_F64 = 1, TCI_C64 = 2, TCI_C128 = 3 } tci_dtype;
+
+/* Arithmetic of contractions: FP64 matrix cores; FP32 matrix cores with FP32
+ * accumulation; split-BF16 x3 (x = hi + lo, three bf16 products, FP32
+ * accumulation).  FP64 requires F64/C128 tensors, the others F32/C64. */
+typedef enum { TCI_PREC_FP64 = 0, TCI_PREC_FP32 = 1, TCI_PREC_BF16X3 = 2 } tci_precision;
+
+/* Truncated-SVD method inside the update composites. */
+typedef enum {
+  TCI_SVD_PLAIN = 0,       /* Gram matrix + Householder tridiagonal eigensolver, all FP64 */
+  TCI_SVD_RANDOMIZED = 1,  /* sketch of rank params.sketch_rank, plain SVD as fallback */
+  TCI_SVD_LEARNED = 2      /* sketch rank predicted by a tci_sketch_model, plain as fallback */
+} tci_svd_mode;
+
+/* Write-back of the factors after the two-site update. */
+typedef enum {
+  TCI_DIR_LEFT = 0,   /* A' = U,            B' = diag(s) V^dagger  (centre moves right) */
+  TCI_DIR_RIGHT = 1   /* A' = U diag(s),    B' = V^dagger          (centre moves left)  */
+} tci_direction;
+
+typedef struct tci_context_s* tci_context;
+typedef struct tci_tensor_s* tci_tensor;
+
+/* ------------------------------------------------------------------ */
+/* Version and errors (Spec, miscellaneous routines: version)          */
+/* ------------------------------------------------------------------ */
+
+/* Returns the interface version "1.0" (static string, never NULL). */
+const char* tci_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Static
+ * per-thread storage, valid until the next failing call on the thread. */
+const char* tci_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Context (Spec, miscellaneous routines: create_context,               */
+/* destroy_context)                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device_id` whose work is ordered on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The
+ * stream is borrowed.  The environment variable TCI_VERBOSE (0, 1, 2;
+ * Spec, environment variables) selects per-call logging to stderr; level 2
+ * adds wall time and synchronises after each call.
+ * Errors: TCI_ERR_INVALID_ARGUMENT (out NULL), TCI_ERR_DEVICE. */
+tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream);
+
+/* Release the context, its workspace and every cached resource.  Tensors
+ * must be destroyed before their context. */
+tci_status tci_destroy_context(tci_context ctx);
+
+/* Change the stream used by later calls (borrowed). */
+tci_status tci_set_stream(tci_context ctx, void* hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Tensor life (Spec, construction and destruction: allocate, zeros,    */
+/* copy, move, clear)                                                   */
+/* ------------------------------------------------------------------ */
+
+/* New owning tensor of the given shape, contents uninitialised.
+ * order in [0, 8]; shape[i] >= 0 (order 0 is a scalar with one element).
+ * Errors: TCI_ERR_INVALID_ARGUMENT, TCI_ERR_DTYPE, TCI_ERR_OUT_OF_MEMORY. */
+tci_status tci_allocate(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape,
+                        tci_tensor* out);
+
+/* As tci_allocate, zero-filled. */
+tci_status tci_zeros(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape,
+                     tci_tensor* out);
+
+/* Borrowing tensor over caller-owned device memory `dev_ptr`, which must
+ * hold prod(shape) elements of `dtype` and outlive the handle. */
+tci_status tci_wrap(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape,
+                    void* dev_ptr, tci_tensor* out);
+
+/* Deep copy into a new owning tensor. */
+tci_status tci_copy(tci_context ctx, tci_tensor in, tci_tensor* out);
+
+/* Transfer contents and ownership of *from into a new handle *out; *from
+ * becomes an empty (order 0, no storage) handle that must still be
+ * destroyed. */
+tci_status tci_move(tci_context ctx, tci_tensor* from, tci_tensor* out);
+
+/* Release a tensor handle (and its storage if owning).  NULL is allowed. */
+tci_status tci_destroy(tci_context ctx, tci_tensor t);
+
+/* ------------------------------------------------------------------ */
+/* Read-only queries (Spec, read-only queries: order, shape, size,      */
+/* size_bytes, get_elem)                                                */
+/* ------------------------------------------------------------------ */
+tci_status tci_order(tci_context ctx, tci_tensor t, int* out);
+/* Writes min(order, cap) dimensions. */
+tci_status tci_shape(tci_context ctx, tci_tensor t, int64_t* shape_out, int cap);
+tci_status tci_size(tci_context ctx, tci_tensor t, int64_t* out);
+/* Bytes of the elements, e.g. 96 for a {3,4,2} F32 tensor (Spec, size_bytes example). */
+tci_status tci_size_bytes(tci_context ctx, tci_tensor t, int64_t* out);
+tci_status tci_dtype_of(tci_context ctx, tci_tensor t, tci_dtype* out);
+/* Device address of element 0 (NULL for an empty handle). */
+tci_status tci_data_ptr(tci_context ctx, tci_tensor t, void** out);
+
+/* One element at coordinates `coors` (order entries) copied to host `out`
+ * (elem_bytes of dtype).  Synchronous.  Errors: TCI_ERR_SHAPE (out of range). */
+tci_status tci_get_elem(tci_context ctx, tci_tensor t, const int64_t* coors, void* out);
+/* Spec, manipulation: set_elem.  Synchronous. */
+tci_status tci_set_elem(tci_context ctx, tci_tensor t, const int64_t* coors, const void* val);
+
+/* Bond labels (optional metadata used by tci_contract_labeled). */
+tci_status tci_set_labels(tci_context ctx, tci_tensor t, const int32_t* labels, int n);
+tci_status tci_get_labels(tci_context ctx, tci_tensor t, int32_t* labels, int cap);
+
+/* ------------------------------------------------------------------ */
+/* Host I/O (Spec: assign_from_range / to_range with the row-major      */
+/* coordinate map; convert)                                             */
+/* ------------------------------------------------------------------ */
+
+/* Copy `bytes` (must equal size_bytes) from host memory, row-major. */
+tci_status tci_from_host(tci_context ctx, tci_tensor t, const void* host, size_t bytes);
+/* Copy the tensor to host memory (row-major), synchronous. */
+tci_status tci_to_host(tci_context ctx, tci_tensor t, void* host, size_t bytes);
+/* Spec, miscellaneous: convert.  New owning tensor `out` with element type
+ * `dtype` (C128 <-> C64, F64 <-> F32, real -> complex). */
+tci_status tci_convert(tci_context ctx, tci_tensor in, tci_dtype dtype, tci_tensor* out);
+
+/* ------------------------------------------------------------------ */
+/* Manipulation (Spec, manipulation: reshape, transpose, cplx_conj,      */
+/* scale; linear algebra: linear_combine)                               */
+/* ------------------------------------------------------------------ */
+
+/* Metadata only; memory order kept.  out == in reshapes in place,
+ * otherwise `out` receives a copy.  Errors: TCI_ERR_SHAPE (size differs). */
+tci_status tci_reshape(tci_context ctx, tci_tensor in, int order, const int64_t* shape,
+                       tci_tensor out);
+
+/* Sec. II.B transpose: out.shape[b] = in.shape[perm[b]],
+ * out[c] = in[c'] with c'[perm[b]] = c[b] (numpy transpose).  out == in
+ * is allowed (a temporary is used). */
+tci_status tci_transpose(tci_context ctx, tci_tensor in, const int32_t* perm, tci_tensor out);
+
+/* Elementwise complex conjugate (identity copy for real types). */
+tci_status tci_cplx_conj(tci_context ctx, tci_tensor in, tci_tensor out);
+
+/* inout *= s.  `s` points to one host scalar of the tensor's dtype. */
+tci_status tci_scale(tci_context ctx, tci_tensor inout, const void* s);
+
+/* out = sum_i coefs[i] * ins[i] (coefs: n host scalars of the dtype, NULL =
+ * all ones).  All inputs same shape and dtype; out may alias one input. */
+tci_status tci_linear_combine(tci_context ctx, int n, const tci_tensor* ins, const void* coefs,
+                              tci_tensor out);
+
+/* ------------------------------------------------------------------ */
+/* Reductions (Spec, linear algebra: norm, normalize)                   */
+/* ------------------------------------------------------------------ */
+
+/* Frobenius norm (square root of the sum of squared moduli, FP64
+ * accumulation).  Synchronous. */
+tci_status tci_norm(tci_context ctx, tci_tensor t, double* out);
+/* Scale to unit Frobenius norm in place; *old_norm receives the norm
+ * before scaling (may be NULL).  A zero tensor is left unchanged. */
+tci_status tci_normalize(tci_context ctx, tci_tensor inout, double* old_norm);
+
+/* ------------------------------------------------------------------ */
+/* Contraction (Sec. II.B contraction equations; Spec, linear algebra:   */
+/* contract)                                                            */
+/* ------------------------------------------------------------------ */
+
+/* Labels shared by a (la, na entries) and b (lb, nb) and absent from c (lc,
+ * nc) are summed; lc fixes the bonds of c and their order; nc == 0 gives a
+ * scalar (order 0).  c may alias a and/or b.  A label repeated inside one
+ * list, a label of c found in neither or both operands, and a label found
+ * in one operand only but not in c give TCI_ERR_LABEL; dimensions of equal
+ * labels must agree (TCI_ERR_SHAPE); a and b must have the same dtype.
+ * Runs as transpose + one GEMM on the matrix cores in the context's
+ * precision for that dtype (tci_set_precision). */
+tci_status tci_contract(tci_context ctx, tci_tensor a, const int32_t* la, int na, tci_tensor b,
+                        const int32_t* lb, int nb, tci_tensor c, const int32_t* lc, int nc);
+
+/* String form: every character is one label ("ijk"). */
+tci_status tci_contract_str(tci_context ctx, tci_tensor a, const char* la, tci_tensor b,
+                            const char* lb, tci_tensor c, const char* lc);
+
+/* Precision used by contractions on F32/C64 tensors (default TCI_PREC_FP32). */
+tci_status tci_set_precision(tci_context ctx, tci_precision prec);
+
+/* ------------------------------------------------------------------ */
+/* Decompositions (Spec, linear algebra: svd, trunc_svd, qr, eigh)      */
+/* ------------------------------------------------------------------ */
+
+/* Matricise `a` with its first k_rows bonds as rows (1 <= k_rows < order)
+ * and compute a thin SVD: u {d_0..d_{k-1}, kappa}, s {kappa} (real, FP64 for
+ * double types, non-increasing, >= 0), vdag {kappa, d_k..}.  Gauge: each
+ * column of u has its largest-modulus entry (first on ties) real positive.
+ * Implemented as trunc_svd keeping every value.  Synchronous. */
+tci_status tci_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s,
+                   tci_tensor vdag);
+
+/* Spec, trunc_svd form (2): discard s_i < s_min; keep at least chi_min (or
+ * all that survive when fewer); grow chi until the relative truncation
+ * error eps = sum_{i>=chi} s_i^2 / sum_i s_i^2 <= target_trunc_err or chi
+ * = chi_max.  chi >= 1.  Form (1) is chi_min = 1, target 0.  The kept s is
+ * NOT renormalised.  *trunc_err (may be NULL) receives eps.
+ * Errors: TCI_ERR_INVALID_ARGUMENT (k_rows, chi_min < 1, chi_min > chi_max). */
+tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s,
+                         tci_tensor vdag, double* trunc_err, int64_t chi_min, int64_t chi_max,
+                         double target_trunc_err, double s_min);
+
+/* Spec, qr: thin QR of the matricised tensor, q {d_0..d_{k-1}, rho},
+ * r {rho, d_k..}, rho = min(I, J); r upper triangular with a real positive
+ * diagonal.  Cholesky-QR2 in FP64; a rank-deficient column gives a zero
+ * column of q and a zero row of r.  Synchronous. */
+tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r);
+
+/* Spec, eigh: Hermitian matrix (order 2, square; only the values are read
+ * as given, no symmetrisation) -> w (ascending, real FP64) and v (columns =
+ * eigenvectors, gauge as in tci_svd).  Double types only.  Synchronous. */
+tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v);
+
+/* Spec, close: *result = 1 iff max |a - b| <= eps elementwise (same shape
+ * and dtype), else 0.  Synchronous. */
+tci_status tci_close(tci_context ctx, tci_tensor a, tci_tensor b, double eps, int* result);
+
+/* ------------------------------------------------------------------ */
+/* Two-site update composites (the hot path of the paper's applications, */
+/* Application A listing: theta = contract(A, B), gate, trunc_svd,       */
+/* normalize)                                                            */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t chi_min;          /* trunc_svd form (2) parameters */
+  int64_t chi_max;
+  double target_trunc_err;
+  double s_min;
+  int32_t direction;        /* tci_direction */
+  int32_t precision;        /* tci_precision of the contractions */
+  int32_t svd_mode;         /* tci_svd_mode */
+  int32_t sketch_rank;      /* TCI_SVD_RANDOMIZED: sketch columns k (0: chi_max + 64) */
+  int32_t power_iters;      /* randomized: power iterations q (default 2 when < 0) */
+  int32_t max_batch;        /* problems per internal launch (0: all) */
+  uint64_t seed;            /* Philox key of the sketch */
+  double cert_tol;          /* randomized acceptance: max residual <= cert_tol * s_1 (0: 1e-7) */
+  void* sketch_model;       /* tci_sketch_model for TCI_SVD_LEARNED */
+} tci_update_params;
+
+typedef struct {
+  int64_t chi;              /* kept bond dimension */
+  double trunc_err;         /* relative truncation error eps */
+  double discarded_abs;     /* sum of the squares of the cut values (eps * ||theta||_F^2) */
+  double norm2;             /* ||theta||_F^2 after the gate */
+  int32_t used_fallback;    /* randomized/learned: 1 if the plain SVD decided */
+  int32_t sketch_rank;      /* sketch columns used (0 for plain) */
+  double max_residual;      /* randomized: max ||theta v_i - s_i u_i|| / s_1 of the kept i */
+} tci_update_info;
+
+/* Fill `p` with defaults: chi_min 1, chi_max INT64_MAX, target 0, s_min 0,
+ * RIGHT, FP64, PLAIN, sketch 0, q 2, max_batch 0, seed 0, cert 1e-7. */
+void tci_update_params_default(tci_update_params* p);
+
+/* n independent two-site updates.  A[i] has shape (chi_l, d, chi_m), B[i]
+ * (chi_m, d, chi_r), all i the same shapes and dtype (C128/F64 for FP64,
+ * C64/F32 for the mixed precisions).  gates (nullable; entries nullable)
+ * are (d*d, d*d) or (d, d, d, d) with rows = outgoing (s1', s2'):
+ * theta'(a,s1',s2',b) = sum G[(s1' s2'),(s1 s2)] theta(a,s1,s2,b).
+ * Then trunc_svd of theta' with k_rows = 2 under params, s renormalised
+ * to unit 2-norm, and the write-back chosen by params->direction:
+ * A_out[i] (chi_l, d, chi_i), s_out[i] (chi_i) real FP64, B_out[i]
+ * (chi_i, d, chi_r).  infos (nullable) receives per-update results.
+ * Supports d = 2.  Synchronous. */
+tci_status tci_two_site_update_batched(tci_context ctx, int n, const tci_tensor* A,
+                                       const tci_tensor* B, const tci_tensor* gates,
+                                       const tci_update_params* params, tci_tensor* A_out,
+                                       tci_tensor* s_out, tci_tensor* B_out,
+                                       tci_update_info* infos);
+
+/* Effective-Hamiltonian matvec of the two-site DMRG update:
+ * y[a,s1,s2,b] = sum L[a,w,a'] W1[w,w',s1,s1'] W2[w',w'',s2,s2'] R[b,w'',b']
+ *                    x[a',s1',s2',b'].
+ * L (chi_l, w, chi_l), W1 (w, w, d, d), W2 (w, w, d, d), R (chi_r, w, chi_r),
+ * x, y (chi_l, d, d, chi_r); all one dtype.  y must not alias x. */
+tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
+                           tci_tensor R, tci_tensor x, tci_tensor y);
+
+/* Lowest Ritz pair after at most n_matvec matvecs of Lanczos with full
+ * re-orthogonalisation (FP64 basis and scalars), started at theta_inout,
+ * which receives the normalised Ritz vector (phase: <theta_in, psi> real
+ * positive).  *energy receives the Ritz value.  For F32/C64 operands the
+ * matvecs run in the context's mixed precision and the Krylov vectors are
+ * kept in FP64.  Synchronous. */
+tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
+                              tci_tensor R, tci_tensor theta_inout, int n_matvec, double* energy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCI_C_H */

@@ -1,0 +1,242 @@
+// Two-site DMRG pieces: the effective-Hamiltonian matvec and the Lanczos
+// ground-state step.  The matvec is three matrix-core GEMMs:
+//   X1[(a,w),(s1',s2',b')]  = sum_a'   L[(a,w),a'] x[a',(s1',s2',b')]
+//   X2[a][(s1,s2,w''),b']   = sum_{w,s1',s2'} W12[(w,s1',s2'),(s1,s2,w'')] X1[a][(w,s1',s2'),b']
+//   y[(a,s1,s2),b]          = sum_{w'',b'} X2[(a,s1,s2),(w'',b')] R[b,(w'',b')]
+// with W12 = sum_w' W1[w,w',s1,s1'] W2[w',w'',s2,s2'] formed once per call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tci_c.h"
+#include "common.hpp"
+#include "eig.hpp"
+#include "gemm.hpp"
+#include "linalg.hpp"
+#include "runtime.hpp"
+#include "vecops.hpp"
+
+namespace tci {
+
+struct HeffPlan {
+  int dt, prec;
+  int chil, chir, w, d;
+  const void *L, *R;
+  void* W12;  // (w d d) x (d d w)
+  void* X1;   // chil * w * d * d * chir
+  void* X2;   // chil * d * d * w * chir
+};
+
+static tci_status heff_check(tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, tci_tensor x, int& chil,
+                             int& chir, int& wd, int& d) {
+  for (tci_tensor t : {L, W1, W2, R, x})
+    if (!t || t->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null tensor");
+  if (L->order != 3 || W1->order != 4 || W2->order != 4 || R->order != 3 || x->order != 4)
+    TCI_RET(TCI_ERR_SHAPE, "heff operand orders must be 3, 4, 4, 3, 4");
+  const int dt = L->dtype;
+  for (tci_tensor t : {W1, W2, R, x})
+    if (t->dtype != dt) TCI_RET(TCI_ERR_DTYPE, "heff operands must share one dtype");
+  chil = (int)L->shape[0];
+  wd = (int)L->shape[1];
+  d = (int)W1->shape[2];
+  chir = (int)R->shape[0];
+  if (L->shape[2] != chil || R->shape[2] != chir || R->shape[1] != wd) TCI_RET(TCI_ERR_SHAPE, "environment shapes");
+  for (tci_tensor t : {W1, W2})
+    if (t->shape[0] != wd || t->shape[1] != wd || t->shape[2] != d || t->shape[3] != d)
+      TCI_RET(TCI_ERR_SHAPE, "MPO shapes");
+  if (x->shape[0] != chil || x->shape[1] != d || x->shape[2] != d || x->shape[3] != chir)
+    TCI_RET(TCI_ERR_SHAPE, "theta shape");
+  return TCI_OK;
+}
+
+static tci_status heff_prepare(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, int chil,
+                               int chir, int wd, int d, HeffPlan& p) {
+  p.dt = L->dtype;
+  p.prec = is_double(p.dt) ? PREC_FP64 : ctx->precision;
+  p.chil = chil; p.chir = chir; p.w = wd; p.d = d;
+  p.L = L->data; p.R = R->data;
+  const size_t es = elem_bytes(p.dt);
+  const int kw = wd * d * d;
+  p.W12 = ctx->arena.get(es * (size_t)kw * kw);
+  p.X1 = ctx->arena.get(es * (size_t)chil * kw * chir);
+  p.X2 = ctx->arena.get(es * (size_t)chil * kw * chir);
+  if (!p.W12 || !p.X1 || !p.X2) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "heff workspace");
+  TCI_CHECK_HIP(mpo_pair(p.dt, W1->data, W2->data, p.W12, wd, d, ctx->stream));
+  return TCI_OK;
+}
+
+static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, void* y) {
+  const int kw = p.w * p.d * p.d;
+  hipStream_t s = ctx->stream;
+  // X1 = L' x'
+  GemmArgs g1 = gemm_args(p.chil * p.w, p.d * p.d * p.chir, p.chil, OP_N, OP_N, p.L, p.chil, x, p.d * p.d * p.chir,
+                          p.X1, p.d * p.d * p.chir);
+  TCI_CHECK_HIP(gemm(p.dt, p.prec, g1, s));
+  // X2[a] = W12^T X1[a]
+  GemmArgs g2 = gemm_args(kw, p.chir, kw, OP_T, OP_N, p.W12, kw, p.X1, p.chir, p.X2, p.chir);
+  g2.sA = 0; g2.sB = (long long)kw * p.chir; g2.sC = (long long)kw * p.chir; g2.batch = p.chil;
+  TCI_CHECK_HIP(gemm(p.dt, p.prec, g2, s));
+  // y = X2' R'^T
+  GemmArgs g3 = gemm_args(p.chil * p.d * p.d, p.chir, p.w * p.chir, OP_N, OP_T, p.X2, (long long)p.w * p.chir, p.R,
+                          (long long)p.w * p.chir, y, p.chir);
+  TCI_CHECK_HIP(gemm(p.dt, p.prec, g3, s));
+  return TCI_OK;
+}
+
+}  // namespace tci
+
+using namespace tci;
+
+extern "C" {
+
+tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, tci_tensor x,
+                           tci_tensor y) {
+  if (!ctx || !y) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int chil, chir, wd, d;
+  TCI_TRY(heff_check(L, W1, W2, R, x, chil, chir, wd, d));
+  if (y == x) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "y must not alias x");
+  Trace tr(ctx, "heff_matvec", std::to_string(chil) + "," + std::to_string(wd) + "," + std::to_string(chir));
+  ctx->arena.reset();
+  HeffPlan p{};
+  TCI_TRY(heff_prepare(ctx, L, W1, W2, R, chil, chir, wd, d, p));
+  const int64_t ysh[4] = {chil, d, d, chir};
+  TCI_TRY(ensure_shape(ctx, y, L->dtype, 4, ysh));
+  TCI_TRY(heff_apply(ctx, p, x->data, y->data));
+  return TCI_OK;
+}
+
+tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R,
+                              tci_tensor theta, int n_matvec, double* energy) {
+  if (!ctx || !theta || !energy) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (n_matvec < 1 || n_matvec > 32) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "n_matvec must be in [1, 32]");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int chil, chir, wd, d;
+  TCI_TRY(heff_check(L, W1, W2, R, theta, chil, chir, wd, d));
+  Trace tr(ctx, "lanczos_ground", std::to_string(chil) + "," + std::to_string(chir) + " m=" + std::to_string(n_matvec));
+  ctx->arena.reset();
+  hipStream_t s = ctx->stream;
+  HeffPlan p{};
+  TCI_TRY(heff_prepare(ctx, L, W1, W2, R, chil, chir, wd, d, p));
+  const int dt = L->dtype;
+  const long long N = (long long)chil * d * d * chir;
+  const size_t es = elem_bytes(dt);
+  // Krylov basis and scalars in complex128
+  cd* basis = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N * (n_matvec + 1)));
+  cd* w = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N));
+  cd* th = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N));
+  void* xin = ctx->arena.get(es * (size_t)N);
+  void* yout = ctx->arena.get(es * (size_t)N);
+  double* part = static_cast<double*>(ctx->arena.get(sizeof(double) * MULTIDOT_PARTIAL_DOUBLES));
+  double* coef = static_cast<double*>(ctx->arena.get(sizeof(double) * 2 * 64));
+  double* nrm = static_cast<double*>(ctx->arena.get(sizeof(double) * (SUMSQ_PARTIALS + 1)));
+  if (!basis || !w || !th || !xin || !yout || !part || !coef || !nrm) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(convert(dt, theta->data, C128, th, N, s));
+  auto norm2 = [&](const cd* v, double& out) -> tci_status {
+    TCI_CHECK_HIP(sumsq_batched(C128, v, N, 0, nrm + SUMSQ_PARTIALS, nrm, 1, s));
+    TCI_CHECK_HIP(hipMemcpyAsync(&out, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
+    TCI_CHECK_HIP(hipStreamSynchronize(s));
+    return TCI_OK;
+  };
+  double n0 = 0.0;
+  TCI_TRY(norm2(th, n0));
+  n0 = std::sqrt(n0);
+  if (!(n0 > 0.0) || !std::isfinite(n0)) TCI_RET(TCI_ERR_NUMERIC, "starting vector has zero or non-finite norm");
+  TCI_CHECK_HIP(scale_copy(th, 1.0 / n0, 0.0, basis, N, s));
+  std::vector<double> alpha, beta;
+  double tmax = 0.0;
+  for (int j = 0; j < n_matvec; ++j) {
+    cd* vj = basis + (size_t)N * j;
+    // w = H v_j (in the operands' dtype / precision)
+    const void* xv = vj;
+    if (dt != C128) {
+      TCI_CHECK_HIP(convert(C128, vj, dt, xin, N, s));
+      xv = xin;
+    }
+    TCI_TRY(heff_apply(ctx, p, xv, dt == C128 ? (void*)w : yout));
+    if (dt != C128) TCI_CHECK_HIP(convert(dt, yout, C128, w, N, s));
+    // alpha_j = Re <v_j, w>
+    double hc[2];
+    TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
+    TCI_CHECK_HIP(hipMemcpyAsync(hc, coef, sizeof(hc), hipMemcpyDeviceToHost, s));
+    TCI_CHECK_HIP(hipStreamSynchronize(s));
+    const double a = hc[0];
+    alpha.push_back(a);
+    // w -= alpha v_j + beta_{j-1} v_{j-1}
+    double c3[4] = {a, 0.0, j > 0 ? beta[j - 1] : 0.0, 0.0};
+    if (j > 0) {
+      double cc[4] = {c3[2], 0.0, a, 0.0};  // basis rows j-1, j
+      TCI_CHECK_HIP(hipMemcpyAsync(coef, cc, sizeof(cc), hipMemcpyHostToDevice, s));
+      TCI_CHECK_HIP(multiaxpy(basis + (size_t)N * (j - 1), 2, coef, -1.0, w, N, s));
+    } else {
+      TCI_CHECK_HIP(hipMemcpyAsync(coef, c3, sizeof(double) * 2, hipMemcpyHostToDevice, s));
+      TCI_CHECK_HIP(multiaxpy(vj, 1, coef, -1.0, w, N, s));
+    }
+    // two passes of classical Gram-Schmidt against v_0..v_j
+    for (int pass = 0; pass < 2; ++pass) {
+      TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
+      TCI_CHECK_HIP(multiaxpy(basis, j + 1, coef, -1.0, w, N, s));
+    }
+    double b2 = 0.0;
+    TCI_TRY(norm2(w, b2));
+    const double b = std::sqrt(b2);
+    tmax = std::max({tmax, std::fabs(a), b});
+    if (j == n_matvec - 1) break;
+    if (b <= 1e-13 * tmax) break;
+    beta.push_back(b);
+    TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, basis + (size_t)N * (j + 1), N, s));
+  }
+  const int m = (int)alpha.size();
+  // lowest eigenpair of T = tridiag(alpha, beta): top eigenpair of -T on the device
+  double* dd = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
+  double* ee = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
+  double* e2 = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
+  double* lam = static_cast<double*>(ctx->arena.get(sizeof(double) * 8));
+  double* z = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
+  double* iw = static_cast<double*>(ctx->arena.get(sizeof(double) * 4 * 64));
+  if (!dd || !ee || !e2 || !lam || !z || !iw) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  std::vector<double> hd(m), he(std::max(m, 1), 0.0);
+  for (int i = 0; i < m; ++i) hd[i] = -alpha[i];
+  for (int i = 0; i + 1 < m; ++i) he[i] = -beta[i];
+  TCI_CHECK_HIP(hipMemcpyAsync(dd, hd.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(ee, he.data(), sizeof(double) * he.size(), hipMemcpyHostToDevice, s));
+  TCI_CHECK_HIP(tridiag_eigvals_top(dd, ee, e2, m, m, 1, lam, 1, 1, s));
+  TCI_CHECK_HIP(hipMemsetAsync(z, 0, sizeof(double) * m, s));
+  TCI_CHECK_HIP(tridiag_invit(dd, ee, m, m, lam, 1, nullptr, 1, z, 1, 0, iw, 1, s));
+  std::vector<double> hz(m);
+  double hl = 0.0;
+  TCI_CHECK_HIP(hipMemcpyAsync(hz.data(), z, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(&hl, lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  // psi = sum_i y_i v_i
+  std::vector<double> cy(2 * m, 0.0);
+  for (int i = 0; i < m; ++i) cy[2 * i] = hz[i];
+  TCI_CHECK_HIP(hipMemsetAsync(w, 0, sizeof(cd) * (size_t)N, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(coef, cy.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, s));
+  TCI_CHECK_HIP(multiaxpy(basis, m, coef, 1.0, w, N, s));
+  double pn2 = 0.0;
+  TCI_TRY(norm2(w, pn2));
+  const double pn = std::sqrt(pn2);
+  // phase: <theta, psi> real positive
+  double ov[2];
+  TCI_CHECK_HIP(multidot(th, 1, w, N, part, coef, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(ov, coef, sizeof(ov), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  const double om = std::hypot(ov[0], ov[1]);
+  double pr = 1.0 / pn, pi = 0.0;
+  if (om > 0.0) {
+    pr = ov[0] / om / pn;
+    pi = -ov[1] / om / pn;
+  }
+  TCI_CHECK_HIP(scale_copy(w, pr, pi, basis, N, s));
+  TCI_CHECK_HIP(convert(C128, basis, dt, theta->data, N, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  *energy = -hl;
+  return TCI_OK;
+}
+
+}  // extern "C"

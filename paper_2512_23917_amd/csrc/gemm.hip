@@ -1,0 +1,591 @@
+// Batched GEMM on the CDNA4 matrix cores: C = alpha * op(A) op(B) (* diag scales) + beta * C.
+//
+// The contraction of two site tensors, the Gram matrices and every
+// back-multiplication of the truncated SVD reduce to this one primitive after
+// the label planner has permuted operands into matrix form (Sec. II.B
+// contraction equations: C_IJ = sum_S A_IS B_SJ).
+//
+// Three arithmetic modes share the tiling:
+//   * FP64:   v_mfma_f64_16x16x4f64, double accumulate (complex by four real products);
+//   * FP32:   v_mfma_f32_16x16x4f32, float accumulate;
+//   * BF16X3: each float operand is split x = hi + lo with hi = rne_bf16(x),
+//             lo = rne_bf16(x - hi); three v_mfma_f32_16x16x32_bf16 products
+//             hi*hi + hi*lo + lo*hi accumulate in float.
+// Operands are row-major with leading dimensions; op() may transpose or
+// conjugate-transpose either side.  A batch may carry its own (m, n, k) per
+// problem in device memory so ragged batches run in one launch.
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace tci {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Workgroup -> tile mapping.  Dispatch places workgroup i on XCD (i mod 8);
+// re-number so the tiles that one XCD receives are contiguous in (batch,
+// tile_m, tile_n) order and share operand panels in that XCD's L2.
+// ---------------------------------------------------------------------------
+__device__ inline void tile_coords(int& tm, int& tn, int& b) {
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const long total = (long)gx * gy * gz;
+  long lin = blockIdx.x + (long)gx * (blockIdx.y + (long)gy * blockIdx.z);
+  if ((total & 7) == 0) {
+    const long per = total >> 3;
+    lin = (lin & 7) * per + (lin >> 3);
+  }
+  tn = (int)(lin % gx);
+  lin /= gx;
+  tm = (int)(lin % gy);
+  b = (int)(lin / gy);
+}
+
+template <typename T> struct Elem;
+template <> struct Elem<double> { static constexpr bool cplx = false; };
+template <> struct Elem<float> { static constexpr bool cplx = false; };
+template <> struct Elem<cd> { static constexpr bool cplx = true; };
+template <> struct Elem<cf> { static constexpr bool cplx = true; };
+
+__device__ inline void ld(const double* p, double& re, double& im) { re = *p; im = 0.0; }
+__device__ inline void ld(const cd* p, double& re, double& im) { cd v = *p; re = v.x; im = v.y; }
+__device__ inline void ld(const float* p, float& re, float& im) { re = *p; im = 0.f; }
+__device__ inline void ld(const cf* p, float& re, float& im) { cf v = *p; re = v.x; im = v.y; }
+__device__ inline void st(double* p, double re, double) { *p = re; }
+__device__ inline void st(cd* p, double re, double im) { *p = cd{re, im}; }
+__device__ inline void st(float* p, float re, float) { *p = re; }
+__device__ inline void st(cf* p, float re, float im) { *p = cf{re, im}; }
+
+// ---------------------------------------------------------------------------
+// Staging: a BM x BK tile of op(A) and a BK x BN tile of op(B) are read from
+// global memory (each thread 8 consecutive elements along the contiguous
+// dimension) and written k-major into LDS planes (re, im).
+// ---------------------------------------------------------------------------
+template <typename T, typename R, int ROWS, int BK>
+__device__ inline void stage_rows_tile(const T* __restrict__ A, long lda, int op, int M, int K,
+                                       int m0, int k0, R (*re)[ROWS + 2], R (*im)[ROWS + 2]) {
+  // Tile element (r, kk) of op(A) (r < ROWS, kk < BK) goes to re[kk][r].
+  const int t = threadIdx.x;
+  constexpr int PER = ROWS * BK / 256;  // elements per thread (8 for 128x16)
+  if (op == OP_N || op == OP_R) {
+    // A stored M x K: contiguous along k.
+    constexpr int TPR = BK / PER;  // threads per row
+    const int r = t / TPR, kk0 = (t % TPR) * PER;
+    const int gm = m0 + r;
+    const R sgn = (op == OP_R) ? R(-1) : R(1);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int gk = k0 + kk0 + e;
+      R vr = 0, vi = 0;
+      if (gm < M && gk < K) ld(A + (long)gm * lda + gk, vr, vi);
+      re[kk0 + e][r] = vr;
+      im[kk0 + e][r] = sgn * vi;
+    }
+  } else {
+    // A stored K x M: contiguous along m.
+    constexpr int TPK = ROWS / PER;  // threads per k-row
+    const int kk = t / TPK, r0 = (t % TPK) * PER;
+    const int gk = k0 + kk;
+    const R sgn = (op == OP_C) ? R(-1) : R(1);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int gm = m0 + r0 + e;
+      R vr = 0, vi = 0;
+      if (gm < M && gk < K) ld(A + (long)gk * lda + gm, vr, vi);
+      re[kk][r0 + e] = vr;
+      im[kk][r0 + e] = sgn * vi;
+    }
+  }
+}
+
+template <typename T, typename R, int COLS, int BK>
+__device__ inline void stage_cols_tile(const T* __restrict__ B, long ldb, int op, int N, int K,
+                                       int n0, int k0, R (*re)[COLS + 2], R (*im)[COLS + 2]) {
+  // Tile element (kk, c) of op(B) goes to re[kk][c].
+  const int t = threadIdx.x;
+  constexpr int PER = COLS * BK / 256;
+  if (op == OP_N || op == OP_R) {
+    // B stored K x N: contiguous along n.
+    constexpr int TPK = COLS / PER;
+    const int kk = t / TPK, c0 = (t % TPK) * PER;
+    const int gk = k0 + kk;
+    const R sgn = (op == OP_R) ? R(-1) : R(1);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int gn = n0 + c0 + e;
+      R vr = 0, vi = 0;
+      if (gn < N && gk < K) ld(B + (long)gk * ldb + gn, vr, vi);
+      re[kk][c0 + e] = vr;
+      im[kk][c0 + e] = sgn * vi;
+    }
+  } else {
+    // B stored N x K: contiguous along k.
+    constexpr int TPC = BK / PER;
+    const int c = t / TPC, kk0 = (t % TPC) * PER;
+    const int gn = n0 + c;
+    const R sgn = (op == OP_C) ? R(-1) : R(1);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int gk = k0 + kk0 + e;
+      R vr = 0, vi = 0;
+      if (gn < N && gk < K) ld(B + (long)gn * ldb + gk, vr, vi);
+      re[kk0 + e][c] = vr;
+      im[kk0 + e][c] = sgn * vi;
+    }
+  }
+}
+
+__device__ inline void problem_dims(const GemmArgs& a, int b, int& M, int& N, int& K) {
+  if (a.dims) {
+    M = min(a.dims[3 * b + 0], a.m);
+    N = min(a.dims[3 * b + 1], a.n);
+    K = min(a.dims[3 * b + 2], a.k);
+  } else {
+    M = a.m; N = a.n; K = a.k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 matrix-core GEMM.  256 threads = 4 waves in a 2 x 2 grid; each wave
+// owns a (BM/2) x (BN/2) sub-tile made of 16x16 MFMA blocks.  For complex T
+// the product uses four real MFMAs per block and k-step (re*re - im*im,
+// re*im + im*re).  f64 16x16x4 output layout: lane l, register r holds
+// row (l/16) + 4r, column l%16 of the block.
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
+  constexpr bool CPLX = Elem<T>::cplx;
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FI = WM / 16, FJ = WN / 16;
+  __shared__ double As_re[BK][BM + 2], As_im[BK][BM + 2];
+  __shared__ double Bs_re[BK][BN + 2], Bs_im[BK][BN + 2];
+
+  int tm, tn, b;
+  tile_coords(tm, tn, b);
+  int M, N, K;
+  problem_dims(a, b, M, N, K);
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+
+  const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
+  const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
+  T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  d4 acc_re[FI][FJ], acc_im[CPLX ? FI : 1][CPLX ? FJ : 1];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+      acc_re[i][j] = d4{0, 0, 0, 0};
+      if constexpr (CPLX) acc_im[i][j] = d4{0, 0, 0, 0};
+    }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    stage_rows_tile<T, double, BM, BK>(A, a.lda, a.opA, M, K, m0, k0, As_re, As_im);
+    stage_cols_tile<T, double, BN, BK>(B, a.ldb, a.opB, N, K, n0, k0, Bs_re, Bs_im);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double fa_re[FI], fa_im[FI], fb_re[FJ], fb_im[FJ];
+#pragma unroll
+      for (int i = 0; i < FI; ++i) {
+        fa_re[i] = As_re[ks + lk][wm * WM + i * 16 + lr];
+        if constexpr (CPLX) fa_im[i] = As_im[ks + lk][wm * WM + i * 16 + lr];
+      }
+#pragma unroll
+      for (int j = 0; j < FJ; ++j) {
+        fb_re[j] = Bs_re[ks + lk][wn * WN + j * 16 + lr];
+        if constexpr (CPLX) fb_im[j] = Bs_im[ks + lk][wn * WN + j * 16 + lr];
+      }
+#pragma unroll
+      for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa_re[i], fb_re[j], acc_re[i][j], 0, 0, 0);
+          if constexpr (CPLX) {
+            acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fa_im[i], fb_im[j], acc_re[i][j], 0, 0, 0);
+            acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa_re[i], fb_im[j], acc_im[i][j], 0, 0, 0);
+            acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa_im[i], fb_re[j], acc_im[i][j], 0, 0, 0);
+          }
+        }
+    }
+  }
+
+  const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
+  const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
+  const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
+        const int col = n0 + wn * WN + j * 16 + lr;
+        if (row < M && col < N) {
+          double vr = acc_re[i][j][r], vi = 0.0;
+          if constexpr (CPLX) vi = acc_im[i][j][r];
+          double sc = 1.0;
+          if (rs) sc *= rs[row];
+          if (cs) sc *= cs[col];
+          vr *= sc; vi *= sc;
+          double outr = a.alpha_re * vr - a.alpha_im * vi;
+          double outi = a.alpha_re * vi + a.alpha_im * vr;
+          T* p = C + (long)row * a.ldc + col;
+          if (!beta0) {
+            double cr, ci;
+            ld(p, cr, ci);
+            outr += a.beta_re * cr - a.beta_im * ci;
+            outi += a.beta_re * ci + a.beta_im * cr;
+          }
+          st(p, outr, outi);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 matrix-core GEMM (float or complex-float storage), float accumulate.
+// f32 16x16x4 output layout: lane l, register r holds row 4*(l/16) + r.
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs a) {
+  constexpr bool CPLX = Elem<T>::cplx;
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FI = WM / 16, FJ = WN / 16;
+  __shared__ float As_re[BK][BM + 2], As_im[BK][BM + 2];
+  __shared__ float Bs_re[BK][BN + 2], Bs_im[BK][BN + 2];
+
+  int tm, tn, b;
+  tile_coords(tm, tn, b);
+  int M, N, K;
+  problem_dims(a, b, M, N, K);
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+  const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
+  const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
+  T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  f4 acc_re[FI][FJ], acc_im[FI][FJ];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) { acc_re[i][j] = f4{0, 0, 0, 0}; acc_im[i][j] = f4{0, 0, 0, 0}; }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    stage_rows_tile<T, float, BM, BK>(A, a.lda, a.opA, M, K, m0, k0, As_re, As_im);
+    stage_cols_tile<T, float, BN, BK>(B, a.ldb, a.opB, N, K, n0, k0, Bs_re, Bs_im);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      float fa_re[FI], fa_im[FI], fb_re[FJ], fb_im[FJ];
+#pragma unroll
+      for (int i = 0; i < FI; ++i) {
+        fa_re[i] = As_re[ks + lk][wm * WM + i * 16 + lr];
+        fa_im[i] = As_im[ks + lk][wm * WM + i * 16 + lr];
+      }
+#pragma unroll
+      for (int j = 0; j < FJ; ++j) {
+        fb_re[j] = Bs_re[ks + lk][wn * WN + j * 16 + lr];
+        fb_im[j] = Bs_im[ks + lk][wn * WN + j * 16 + lr];
+      }
+#pragma unroll
+      for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa_re[i], fb_re[j], acc_re[i][j], 0, 0, 0);
+          if constexpr (CPLX) {
+            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa_im[i], fb_im[j], acc_re[i][j], 0, 0, 0);
+            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa_re[i], fb_im[j], acc_im[i][j], 0, 0, 0);
+            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa_im[i], fb_re[j], acc_im[i][j], 0, 0, 0);
+          }
+        }
+    }
+  }
+
+  const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
+  const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
+  const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + 4 * lk + r;
+        const int col = n0 + wn * WN + j * 16 + lr;
+        if (row < M && col < N) {
+          float vr = acc_re[i][j][r], vi = CPLX ? acc_im[i][j][r] : 0.f;
+          float sc = 1.f;
+          if (rs) sc *= (float)rs[row];
+          if (cs) sc *= (float)cs[col];
+          vr *= sc; vi *= sc;
+          const float ar = (float)a.alpha_re, ai = (float)a.alpha_im;
+          float outr = ar * vr - ai * vi, outi = ar * vi + ai * vr;
+          T* p = C + (long)row * a.ldc + col;
+          if (!beta0) {
+            float cr, ci;
+            ld(p, cr, ci);
+            outr += (float)a.beta_re * cr - (float)a.beta_im * ci;
+            outi += (float)a.beta_re * ci + (float)a.beta_im * cr;
+          }
+          st(p, outr, outi);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 x3 GEMM (float or complex-float storage), float accumulate.
+// LDS holds four bf16 planes per operand (re_hi, re_lo, im_hi, im_lo), k
+// contiguous, so one lane fetches its 8 consecutive k values with one read.
+// bf16 16x16x32 operand layout: lane l supplies row l%16, k 8*(l/16)..+7.
+// ---------------------------------------------------------------------------
+__device__ inline __bf16 rne_bf16(float x) { return (__bf16)x; }
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = rne_bf16(x);
+  lo = rne_bf16(x - (float)hi);
+}
+
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs a) {
+  constexpr bool CPLX = Elem<T>::cplx;
+  constexpr int BK = 32;
+  constexpr int KP = BK + 8;  // padded k extent (bf16 elements)
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FI = WM / 16, FJ = WN / 16;
+  constexpr int NPL = CPLX ? 4 : 2;  // planes: re_hi, re_lo, (im_hi, im_lo)
+  __shared__ __attribute__((aligned(16))) __bf16 As[NPL][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NPL][BN][KP];
+
+  int tm, tn, b;
+  tile_coords(tm, tn, b);
+  int M, N, K;
+  problem_dims(a, b, M, N, K);
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+  const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
+  const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
+  T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int t = threadIdx.x;
+
+  f4 acc_re[FI][FJ], acc_im[FI][FJ];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) { acc_re[i][j] = f4{0, 0, 0, 0}; acc_im[i][j] = f4{0, 0, 0, 0}; }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    // stage op(A): tile (r, kk) -> As[plane][r][kk]
+    {
+      constexpr int PER = BM * BK / 256;
+      if (a.opA == OP_N || a.opA == OP_R) {
+        constexpr int TPR = BK / PER;
+        const int r = t / TPR, kk0 = (t % TPR) * PER;
+        const int gm = m0 + r;
+        const float sgn = (a.opA == OP_R) ? -1.f : 1.f;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int gk = k0 + kk0 + e;
+          float vr = 0.f, vi = 0.f;
+          if (gm < M && gk < K) ld(A + (long)gm * a.lda + gk, vr, vi);
+          split_bf16(vr, As[0][r][kk0 + e], As[1][r][kk0 + e]);
+          if constexpr (CPLX) split_bf16(sgn * vi, As[2][r][kk0 + e], As[3][r][kk0 + e]);
+        }
+      } else {
+        constexpr int TPK = BM / PER;
+        const int kk = t / TPK, r0 = (t % TPK) * PER;
+        const int gk = k0 + kk;
+        const float sgn = (a.opA == OP_C) ? -1.f : 1.f;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int gm = m0 + r0 + e;
+          float vr = 0.f, vi = 0.f;
+          if (gm < M && gk < K) ld(A + (long)gk * a.lda + gm, vr, vi);
+          split_bf16(vr, As[0][r0 + e][kk], As[1][r0 + e][kk]);
+          if constexpr (CPLX) split_bf16(sgn * vi, As[2][r0 + e][kk], As[3][r0 + e][kk]);
+        }
+      }
+    }
+    // stage op(B): tile (kk, c) -> Bs[plane][c][kk]
+    {
+      constexpr int PER = BN * BK / 256;
+      if (a.opB == OP_N || a.opB == OP_R) {
+        constexpr int TPK = BN / PER;
+        const int kk = t / TPK, c0 = (t % TPK) * PER;
+        const int gk = k0 + kk;
+        const float sgn = (a.opB == OP_R) ? -1.f : 1.f;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int gn = n0 + c0 + e;
+          float vr = 0.f, vi = 0.f;
+          if (gn < N && gk < K) ld(B + (long)gk * a.ldb + gn, vr, vi);
+          split_bf16(vr, Bs[0][c0 + e][kk], Bs[1][c0 + e][kk]);
+          if constexpr (CPLX) split_bf16(sgn * vi, Bs[2][c0 + e][kk], Bs[3][c0 + e][kk]);
+        }
+      } else {
+        constexpr int TPC = BK / PER;
+        const int c = t / TPC, kk0 = (t % TPC) * PER;
+        const int gn = n0 + c;
+        const float sgn = (a.opB == OP_C) ? -1.f : 1.f;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int gk = k0 + kk0 + e;
+          float vr = 0.f, vi = 0.f;
+          if (gn < N && gk < K) ld(B + (long)gn * a.ldb + gk, vr, vi);
+          split_bf16(vr, Bs[0][c][kk0 + e], Bs[1][c][kk0 + e]);
+          if constexpr (CPLX) split_bf16(sgn * vi, Bs[2][c][kk0 + e], Bs[3][c][kk0 + e]);
+        }
+      }
+    }
+    __syncthreads();
+
+    bf8 fa[NPL][FI], fb[NPL][FJ];
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) {
+#pragma unroll
+      for (int i = 0; i < FI; ++i)
+        fa[p][i] = *reinterpret_cast<const bf8*>(&As[p][wm * WM + i * 16 + lr][8 * lk]);
+#pragma unroll
+      for (int j = 0; j < FJ; ++j)
+        fb[p][j] = *reinterpret_cast<const bf8*>(&Bs[p][wn * WN + j * 16 + lr][8 * lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+      for (int j = 0; j < FJ; ++j) {
+        // re += Are*Bre (3 terms)
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], acc_re[i][j], 0, 0, 0);
+        if constexpr (CPLX) {
+          // re -= Aim*Bim ; im += Are*Bim + Aim*Bre
+          bf8 nh = -fa[2][i], nl = -fa[3][i];
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[2][j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[3][j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nl, fb[2][j], acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[2][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[3][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[2][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[0][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[1][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[3][i], fb[0][j], acc_im[i][j], 0, 0, 0);
+        }
+      }
+  }
+
+  const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
+  const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
+  const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + 4 * lk + r;
+        const int col = n0 + wn * WN + j * 16 + lr;
+        if (row < M && col < N) {
+          float vr = acc_re[i][j][r], vi = CPLX ? acc_im[i][j][r] : 0.f;
+          float sc = 1.f;
+          if (rs) sc *= (float)rs[row];
+          if (cs) sc *= (float)cs[col];
+          vr *= sc; vi *= sc;
+          const float ar = (float)a.alpha_re, ai = (float)a.alpha_im;
+          float outr = ar * vr - ai * vi, outi = ar * vi + ai * vr;
+          T* p = C + (long)row * a.ldc + col;
+          if (!beta0) {
+            float cr, ci;
+            ld(p, cr, ci);
+            outr += (float)a.beta_re * cr - (float)a.beta_im * ci;
+            outi += (float)a.beta_re * ci + (float)a.beta_im * cr;
+          }
+          st(p, outr, outi);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Launcher
+// ---------------------------------------------------------------------------
+template <typename K>
+static hipError_t launch(K kern, const GemmArgs& a, int BM, int BN, hipStream_t s) {
+  dim3 grid((a.n + BN - 1) / BN, (a.m + BM - 1) / BM, a.batch);
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t gemm(int dtype, int prec, const GemmArgs& a, hipStream_t s) {
+  if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return hipSuccess;
+  if (a.k <= 0) {
+    // empty sum: C = beta * C
+    return gemm_scale_c(dtype, a, s);
+  }
+  switch (dtype) {
+    case C128:
+      return launch(gemm_f64_kernel<cd, 128, 64>, a, 128, 64, s);
+    case F64:
+      return launch(gemm_f64_kernel<double, 128, 128>, a, 128, 128, s);
+    case C64:
+      if (prec == PREC_BF16X3) return launch(gemm_bf16x3_kernel<cf, 64, 64>, a, 64, 64, s);
+      return launch(gemm_f32_kernel<cf, 128, 64>, a, 128, 64, s);
+    case F32:
+      if (prec == PREC_BF16X3) return launch(gemm_bf16x3_kernel<float, 128, 64>, a, 128, 64, s);
+      return launch(gemm_f32_kernel<float, 128, 128>, a, 128, 128, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// C = beta * C for an empty contraction dimension.
+template <typename T> struct RealOf;
+template <> struct RealOf<double> { typedef double type; };
+template <> struct RealOf<cd> { typedef double type; };
+template <> struct RealOf<float> { typedef float type; };
+template <> struct RealOf<cf> { typedef float type; };
+
+template <typename T>
+__global__ void scale_c_kernel(GemmArgs a) {
+  typedef typename RealOf<T>::type R;
+  const int b = blockIdx.y;
+  int M, N, K;
+  problem_dims(a, b, M, N, K);
+  T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)M * N;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(idx / N), col = (int)(idx % N);
+    T* p = C + (long)row * a.ldc + col;
+    R cr = 0, ci = 0;
+    if (a.beta_re != 0.0 || a.beta_im != 0.0) ld(p, cr, ci);
+    st(p, (R)(a.beta_re * cr - a.beta_im * ci), (R)(a.beta_re * ci + a.beta_im * cr));
+  }
+}
+
+hipError_t gemm_scale_c(int dtype, const GemmArgs& a, hipStream_t s) {
+  dim3 grid(256, a.batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(scale_c_kernel<cd>, grid, dim3(256), 0, s, a); break;
+    case F64: hipLaunchKernelGGL(scale_c_kernel<double>, grid, dim3(256), 0, s, a); break;
+    case C64: hipLaunchKernelGGL(scale_c_kernel<cf>, grid, dim3(256), 0, s, a); break;
+    case F32: hipLaunchKernelGGL(scale_c_kernel<float>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tci

@@ -1,0 +1,603 @@
+// Batched linear-algebra and elementwise kernels of the two-site update:
+// Frobenius norms (TCI-spec appendix, norm: sum of squared moduli), the
+// two-site gate, the truncation rule (trunc_svd rules a-c), gauge fixing,
+// write-back of the site tensors with renormalisation (normalize), transpose
+// (Sec. II.B transpose equation) and Cholesky-QR with column dropping.
+#include "common.hpp"
+#include "gemm.hpp"
+#include "linalg.hpp"
+
+namespace tci {
+
+template <typename T> struct LT;
+template <> struct LT<double> { static constexpr int dtype = F64; };
+template <> struct LT<cd> { static constexpr int dtype = C128; };
+template <> struct LT<float> { static constexpr int dtype = F32; };
+template <> struct LT<cf> { static constexpr int dtype = C64; };
+
+__device__ inline double sqmod(double a) { return a * a; }
+__device__ inline double sqmod(float a) { return (double)a * a; }
+__device__ inline double sqmod(cd a) { return a.x * a.x + a.y * a.y; }
+__device__ inline double sqmod(cf a) { return (double)a.x * a.x + (double)a.y * a.y; }
+
+// ---------------------------------------------------------------------------
+// Sum of squared moduli per problem, FP64 accumulation, deterministic
+// two-pass reduction (fixed partial order).
+// ---------------------------------------------------------------------------
+constexpr int NORM_BLOCKS = 128;
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* x, long long n, long long sx,
+                                                            double* partial) {
+  __shared__ double sh[16];
+  const int b = blockIdx.y;
+  const T* xb = x + b * sx;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    acc += sqmod(xb[i]);
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[b * NORM_BLOCKS + blockIdx.x] = acc;
+}
+
+__global__ void sumsq_final_kernel(const double* partial, double* out, int nparts) {
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += partial[b * NORM_BLOCKS + i];
+    out[b] = s;
+  }
+}
+
+hipError_t sumsq_batched(int dtype, const void* x, long long n, long long sx, double* out,
+                         double* partial /* batch * NORM_BLOCKS */, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int nb = (int)std::min<long long>(NORM_BLOCKS, std::max<long long>(1, (n + 255) / 256));
+  dim3 grid(nb, batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(sumsq_partial_kernel<cd>, grid, dim3(256), 0, s, (const cd*)x, n, sx, partial); break;
+    case F64: hipLaunchKernelGGL(sumsq_partial_kernel<double>, grid, dim3(256), 0, s, (const double*)x, n, sx, partial); break;
+    case C64: hipLaunchKernelGGL(sumsq_partial_kernel<cf>, grid, dim3(256), 0, s, (const cf*)x, n, sx, partial); break;
+    case F32: hipLaunchKernelGGL(sumsq_partial_kernel<float>, grid, dim3(256), 0, s, (const float*)x, n, sx, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(sumsq_final_kernel, dim3(batch), dim3(64), 0, s, partial, out, nb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Two-site gate: theta'(a, u, v, b) = sum_{s,t} G[(u v), (s t)] theta(a, s, t, b)
+// for theta of shape (chi_l, d, d, chi_r), in place.  One thread per (a, b).
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(256) void gate_kernel(T* theta, long long stheta, const T* gate,
+                                                   long long sgate, int chi_l, int chi_r) {
+  const int bidx = blockIdx.y;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= (long long)chi_l * chi_r) return;
+  const int a = (int)(idx / chi_r), bb = (int)(idx % chi_r);
+  T* th = theta + bidx * stheta;
+  const T* g = gate + bidx * sgate;
+  T in[D * D];
+#pragma unroll
+  for (int p = 0; p < D * D; ++p) in[p] = th[((long long)a * D * D + p) * chi_r + bb];
+#pragma unroll
+  for (int o = 0; o < D * D; ++o) {
+    T acc{};
+#pragma unroll
+    for (int p = 0; p < D * D; ++p) acc = acc + g[o * D * D + p] * in[p];
+    th[((long long)a * D * D + o) * chi_r + bb] = acc;
+  }
+}
+
+__device__ inline cf operator*(cf a, cd b) { return cf{(float)(a.x * b.x - a.y * b.y), (float)(a.x * b.y + a.y * b.x)}; }
+
+hipError_t gate_apply(int dtype, void* theta, long long stheta, const void* gate, long long sgate,
+                      int chi_l, int d, int chi_r, int batch, hipStream_t s) {
+  if (d != 2) return hipErrorInvalidValue;
+  const long long n = (long long)chi_l * chi_r;
+  dim3 grid((unsigned)((n + 255) / 256), batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL((gate_kernel<cd, 2>), grid, dim3(256), 0, s, (cd*)theta, stheta, (const cd*)gate, sgate, chi_l, chi_r); break;
+    case F64: hipLaunchKernelGGL((gate_kernel<double, 2>), grid, dim3(256), 0, s, (double*)theta, stheta, (const double*)gate, sgate, chi_l, chi_r); break;
+    case C64: hipLaunchKernelGGL((gate_kernel<cf, 2>), grid, dim3(256), 0, s, (cf*)theta, stheta, (const cf*)gate, sgate, chi_l, chi_r); break;
+    case F32: hipLaunchKernelGGL((gate_kernel<float, 2>), grid, dim3(256), 0, s, (float*)theta, stheta, (const float*)gate, sgate, chi_l, chi_r); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Truncation rule (trunc_svd rules a-c) on the top kmax eigenvalues lam
+// (descending) of theta theta^dagger, with the total weight W = ||theta||_F^2:
+//   s_j = sqrt(max(lam_j, 0));  n_a = #{j : s_j >= s_min}
+//   chi = n_a if n_a <= chi_min, else the smallest chi >= chi_min with
+//   eps(chi) <= target, capped at min(chi_max, n_a);  chi >= 1;
+//   eps(chi) = max(W - sum_{j<chi} s_j^2, 0) / W  (0 when W = 0).
+// Outputs per problem: chi, eps, discarded weight eps*W, the kept s_j,
+// 1/s_j (0 for s_j = 0) and s_j / ||s_kept||_2.
+// ---------------------------------------------------------------------------
+__global__ void trunc_select_kernel(const double* lam, long long slam, int kmax, const double* total,
+                                    TruncParams p, int* chi_out, double* err_out, double* disc_out,
+                                    double* s_out, double* sinv_out, double* sn_out, long long ss,
+                                    int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double* l = lam + b * slam;
+  const double W = total[b];
+  int n_a = 0;
+  while (n_a < kmax && sqrt(fmax(l[n_a], 0.0)) >= p.s_min) ++n_a;
+  double kept = 0.0;
+  int chi;
+  auto eps_of = [&](double kept_w) { return W > 0.0 ? fmax(W - kept_w, 0.0) / W : 0.0; };
+  if (n_a <= p.chi_min) {
+    chi = n_a;
+    for (int j = 0; j < chi; ++j) kept += fmax(l[j], 0.0);
+  } else {
+    const int lim = min(p.chi_max, n_a);
+    chi = p.chi_min;
+    for (int j = 0; j < chi; ++j) kept += fmax(l[j], 0.0);
+    while (chi < lim && eps_of(kept) > p.target) {
+      kept += fmax(l[chi], 0.0);
+      ++chi;
+    }
+  }
+  if (chi < 1) {
+    chi = 1;
+    kept = fmax(l[0], 0.0);
+  }
+  const double eps = eps_of(kept);
+  chi_out[b] = chi;
+  err_out[b] = eps;
+  disc_out[b] = eps * W;
+  double nrm = 0.0;
+  for (int j = 0; j < chi; ++j) nrm += fmax(l[j], 0.0);
+  nrm = sqrt(nrm);
+  for (int j = 0; j < kmax; ++j) {
+    const double sj = j < chi ? sqrt(fmax(l[j], 0.0)) : 0.0;
+    s_out[b * ss + j] = sj;
+    sinv_out[b * ss + j] = sj > 0.0 ? 1.0 / sj : 0.0;
+    sn_out[b * ss + j] = nrm > 0.0 ? sj / nrm : 0.0;
+  }
+}
+
+hipError_t trunc_select(const double* lam, long long slam, int kmax, const double* total,
+                        const TruncParams& p, int* chi, double* err, double* disc, double* s,
+                        double* sinv, double* sn, long long ss, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(trunc_select_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, lam, slam, kmax,
+                     total, p, chi, err, disc, s, sinv, sn, ss, batch);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gauge: multiply column j < chi of U (m x ncol, ld ldu) by the phase that
+// makes its largest-modulus entry (first on ties) real and positive.
+// One wave per column.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void gauge_cols_kernel(T* U, long long ldu, long long sU, int m,
+                                                        int ncol, const int* chi) {
+  const int j = blockIdx.x, b = blockIdx.y;
+  if (j >= ncol || (chi && j >= chi[b])) return;
+  T* u = U + b * sU;
+  const int lane = threadIdx.x;
+  double best = -1.0;
+  int bi = 0;
+  for (int r = lane; r < m; r += 64) {
+    const double v = sqmod(u[(long long)r * ldu + j]);
+    if (v > best) { best = v; bi = r; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const T piv = u[(long long)bi * ldu + j];
+  if constexpr (sizeof(T) == 16) {
+    const double md = sqrt(piv.x * piv.x + piv.y * piv.y);
+    if (md == 0.0) return;
+    const cd ph{piv.x / md, -piv.y / md};
+    for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = u[(long long)r * ldu + j] * ph;
+  } else if constexpr (sizeof(T) == 8 && !std::is_same<T, double>::value) {
+    const double md = sqrt((double)piv.x * piv.x + (double)piv.y * piv.y);
+    if (md == 0.0) return;
+    const cf ph{(float)(piv.x / md), (float)(-piv.y / md)};
+    for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = u[(long long)r * ldu + j] * ph;
+  } else {
+    if (piv < 0) for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = -u[(long long)r * ldu + j];
+  }
+}
+
+hipError_t gauge_columns(int dtype, void* U, long long ldu, long long sU, int m, int ncol,
+                         const int* chi, int batch, hipStream_t s) {
+  dim3 grid(ncol, batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(gauge_cols_kernel<cd>, grid, dim3(64), 0, s, (cd*)U, ldu, sU, m, ncol, chi); break;
+    case F64: hipLaunchKernelGGL(gauge_cols_kernel<double>, grid, dim3(64), 0, s, (double*)U, ldu, sU, m, ncol, chi); break;
+    case C64: hipLaunchKernelGGL(gauge_cols_kernel<cf>, grid, dim3(64), 0, s, (cf*)U, ldu, sU, m, ncol, chi); break;
+    case F32: hipLaunchKernelGGL(gauge_cols_kernel<float>, grid, dim3(64), 0, s, (float*)U, ldu, sU, m, ncol, chi); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Real -> complex copy (Z of the tridiagonal problem into the complex U).
+// ---------------------------------------------------------------------------
+__global__ void real_to_cplx_kernel(const double* z, cd* u, long long n, long long sz, long long su) {
+  const int b = blockIdx.y;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    u[b * su + i] = cd{z[b * sz + i], 0.0};
+}
+
+hipError_t real_to_complex(const double* z, void* u, long long n, long long sz, long long su, int batch,
+                           hipStream_t s) {
+  dim3 grid((unsigned)std::min<long long>(1024, (n + 255) / 256), batch);
+  hipLaunchKernelGGL(real_to_cplx_kernel, grid, dim3(256), 0, s, z, (cd*)u, n, sz, su);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Write-back: out[b] (rows x chi[b], dense, ld chi[b]) = in[b] (rows x ldin)
+// columns 0..chi-1, each column j scaled by colscale[b][j] (optional);
+// or rows variant: out rows 0..chi-1 (dense, ncols wide) scaled by rowscale.
+// Also works in place when out == in and ld matches.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T mul_scalar(T v, double s);
+template <> __device__ inline cd mul_scalar(cd v, double s) { return cd{v.x * s, v.y * s}; }
+template <> __device__ inline double mul_scalar(double v, double s) { return v * s; }
+template <> __device__ inline cf mul_scalar(cf v, double s) { return cf{(float)(v.x * s), (float)(v.y * s)}; }
+template <> __device__ inline float mul_scalar(float v, double s) { return (float)(v * s); }
+
+template <typename T>
+__global__ void compact_cols_kernel(const T* in, long long ldin, long long sin_, T* out, long long sout,
+                                    int rows, const int* chi, const double* cs, long long scs) {
+  const int b = blockIdx.y;
+  const int c = chi[b];
+  const T* src = in + b * sin_;
+  T* dst = out + b * sout;
+  const long long total = (long long)rows * c;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const int r = (int)(idx / c), j = (int)(idx % c);
+    T v = src[(long long)r * ldin + j];
+    if (cs) v = mul_scalar(v, cs[b * scs + j]);
+    dst[idx] = v;
+  }
+}
+
+template <typename T>
+__global__ void scale_rows_kernel(const T* in, long long sin_, T* out, long long sout, long long ncols,
+                                  const int* chi, const double* rs, long long srs) {
+  const int b = blockIdx.y;
+  const int c = chi[b];
+  const T* src = in + b * sin_;
+  T* dst = out + b * sout;
+  const long long total = (long long)c * ncols;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const int r = (int)(idx / ncols);
+    T v = src[idx];
+    if (rs) v = mul_scalar(v, rs[b * srs + r]);
+    dst[idx] = v;
+  }
+}
+
+hipError_t compact_columns(int dtype, const void* in, long long ldin, long long sin_, void* out,
+                           long long sout, int rows, int maxchi, const int* chi, const double* cs,
+                           long long scs, int batch, hipStream_t s) {
+  dim3 grid((unsigned)std::min<long long>(2048, ((long long)rows * maxchi + 255) / 256), batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(compact_cols_kernel<cd>, grid, dim3(256), 0, s, (const cd*)in, ldin, sin_, (cd*)out, sout, rows, chi, cs, scs); break;
+    case F64: hipLaunchKernelGGL(compact_cols_kernel<double>, grid, dim3(256), 0, s, (const double*)in, ldin, sin_, (double*)out, sout, rows, chi, cs, scs); break;
+    case C64: hipLaunchKernelGGL(compact_cols_kernel<cf>, grid, dim3(256), 0, s, (const cf*)in, ldin, sin_, (cf*)out, sout, rows, chi, cs, scs); break;
+    case F32: hipLaunchKernelGGL(compact_cols_kernel<float>, grid, dim3(256), 0, s, (const float*)in, ldin, sin_, (float*)out, sout, rows, chi, cs, scs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t scale_rows(int dtype, const void* in, long long sin_, void* out, long long sout, long long ncols,
+                      int maxchi, const int* chi, const double* rs, long long srs, int batch, hipStream_t s) {
+  dim3 grid((unsigned)std::min<long long>(2048, ((long long)maxchi * ncols + 255) / 256), batch);
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(scale_rows_kernel<cd>, grid, dim3(256), 0, s, (const cd*)in, sin_, (cd*)out, sout, ncols, chi, rs, srs); break;
+    case F64: hipLaunchKernelGGL(scale_rows_kernel<double>, grid, dim3(256), 0, s, (const double*)in, sin_, (double*)out, sout, ncols, chi, rs, srs); break;
+    case C64: hipLaunchKernelGGL(scale_rows_kernel<cf>, grid, dim3(256), 0, s, (const cf*)in, sin_, (cf*)out, sout, ncols, chi, rs, srs); break;
+    case F32: hipLaunchKernelGGL(scale_rows_kernel<float>, grid, dim3(256), 0, s, (const float*)in, sin_, (float*)out, sout, ncols, chi, rs, srs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of an order-r tensor (r <= 8): out[c] = in[c'] with
+// c'[perm[b]] = c[b].  When the last bond stays last, consecutive threads
+// read and write consecutive elements; otherwise the innermost output index
+// is split into 64-wide chunks staged through LDS so that both the read
+// (along the input's last bond) and the write stay coalesced.
+// ---------------------------------------------------------------------------
+struct PermArgs {
+  int order;
+  long long out_shape[8];
+  long long in_stride_of_out[8];  // input stride of output bond b (= in_stride[perm[b]])
+  long long total;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void permute_kernel(const T* in, T* out, PermArgs p) {
+  for (long long lin = blockIdx.x * 256LL + threadIdx.x; lin < p.total; lin += (long long)gridDim.x * 256) {
+    long long rem = lin, src = 0;
+    for (int b = p.order - 1; b >= 0; --b) {
+      const long long cb = rem % p.out_shape[b];
+      rem /= p.out_shape[b];
+      src += cb * p.in_stride_of_out[b];
+    }
+    out[lin] = in[src];
+  }
+}
+
+// Tiled variant for permutations that move the input's last bond: treat the
+// tensor as in[..., x, ..., y] with y the input's contiguous bond and x the
+// output's contiguous bond; 64 x 64 tiles are transposed through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void permute_tiled_kernel(const T* in, T* out, PermArgs p, int bx,
+                                                            int by, long long ntile_x, long long ntile_y) {
+  __shared__ T tile[64][65];
+  // bx: output bond index that is contiguous in the output (order-1);
+  // by: output bond index whose input stride is 1.
+  const long long nx = p.out_shape[bx], ny = p.out_shape[by];
+  long long rest = blockIdx.x;
+  const long long tx = rest % ntile_x; rest /= ntile_x;
+  const long long ty = rest % ntile_y; rest /= ntile_y;
+  // decode the remaining bonds (all except bx, by) from `rest`
+  long long src_base = 0, dst_base = 0, dst_stride[8];
+  {
+    long long acc = 1;
+    for (int b = p.order - 1; b >= 0; --b) { dst_stride[b] = acc; acc *= p.out_shape[b]; }
+  }
+  for (int b = p.order - 1; b >= 0; --b) {
+    if (b == bx || b == by) continue;
+    const long long cb = rest % p.out_shape[b];
+    rest /= p.out_shape[b];
+    src_base += cb * p.in_stride_of_out[b];
+    dst_base += cb * dst_stride[b];
+  }
+  const int t = threadIdx.x;
+  // read: rows along x (input stride sx), columns along y (input stride 1)
+  for (int k = t; k < 64 * 64; k += 256) {
+    const int ix = k / 64, iy = k % 64;
+    const long long gx = tx * 64 + ix, gy = ty * 64 + iy;
+    if (gx < nx && gy < ny) tile[ix][iy] = in[src_base + gx * p.in_stride_of_out[bx] + gy];
+  }
+  __syncthreads();
+  for (int k = t; k < 64 * 64; k += 256) {
+    const int iy = k / 64, ix = k % 64;
+    const long long gx = tx * 64 + ix, gy = ty * 64 + iy;
+    if (gx < nx && gy < ny) out[dst_base + gy * dst_stride[by] + gx] = tile[ix][iy];
+  }
+}
+
+hipError_t permute(int dtype, const void* in, void* out, int order, const long long* shape,
+                   const int* perm, hipStream_t s) {
+  if (order < 0 || order > 8) return hipErrorInvalidValue;
+  PermArgs p{};
+  p.order = order;
+  long long in_stride[8];
+  long long acc = 1;
+  for (int b = order - 1; b >= 0; --b) { in_stride[b] = acc; acc *= shape[b]; }
+  p.total = acc;
+  if (p.total == 0) return hipSuccess;
+  for (int b = 0; b < order; ++b) {
+    p.out_shape[b] = shape[perm[b]];
+    p.in_stride_of_out[b] = in_stride[perm[b]];
+  }
+  int by = -1;
+  for (int b = 0; b < order; ++b) if (perm[b] == order - 1) by = b;
+  const bool tiled = order >= 2 && by != order - 1 && p.out_shape[order - 1] >= 16 &&
+                     p.out_shape[by] >= 16;
+  const size_t es = elem_bytes(dtype);
+  if (tiled) {
+    const int bx = order - 1;
+    const long long ntx = (p.out_shape[bx] + 63) / 64, nty = (p.out_shape[by] + 63) / 64;
+    const long long others = p.total / (p.out_shape[bx] * p.out_shape[by]);
+    const long long blocks = ntx * nty * others;
+    if (blocks < (1LL << 31)) {
+#define PT(T) hipLaunchKernelGGL(permute_tiled_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T*)in, (T*)out, p, bx, by, ntx, nty)
+      if (es == 16) PT(cd); else if (es == 8) PT(double); else PT(float);
+#undef PT
+      return hipGetLastError();
+    }
+  }
+  const unsigned grid = (unsigned)std::min<long long>(65536, (p.total + 255) / 256);
+  if (es == 16) hipLaunchKernelGGL(permute_kernel<cd>, dim3(grid), dim3(256), 0, s, (const cd*)in, (cd*)out, p);
+  else if (es == 8) hipLaunchKernelGGL(permute_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)in, (double*)out, p);
+  else hipLaunchKernelGGL(permute_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)in, (float*)out, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky-QR with column dropping (batched).
+//   column mode:  Y (m x k):  G = Y^H Y = R^H R,  Q = Y R^-1
+//   row mode:     X (k x m):  G = X X^H = R^H R,  Q = R^-H X
+// Column j is dropped when its Cholesky pivot is <= tau * G_jj(original) or
+// not positive (it lies numerically in the span of the earlier columns); R
+// keeps a unit diagonal and a zero row there and Q a zero column (row).
+// Blocked right-looking factorisation with CB x CB diagonal blocks factored
+// in LDS, panels and trailing updates on the matrix cores.
+// ---------------------------------------------------------------------------
+constexpr int CB = 32;
+
+template <typename T> __device__ inline T czero();
+template <> __device__ inline cd czero<cd>() { return cd{0, 0}; }
+template <> __device__ inline double czero<double>() { return 0.0; }
+__device__ inline cd cconj(cd a) { return conjg(a); }
+__device__ inline double cconj(double a) { return a; }
+__device__ inline double creal_(cd a) { return a.x; }
+__device__ inline double creal_(double a) { return a; }
+__device__ inline cd cdiv_real(cd a, double r) { return cd{a.x / r, a.y / r}; }
+__device__ inline double cdiv_real(double a, double r) { return a / r; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void chol_diag_kernel(T* G, long long ldg, long long sG, int jb, int k,
+                                                        const double* diag0, long long sdiag,
+                                                        T* RI, long long sRI, double* mask, long long smask,
+                                                        double tau) {
+  __shared__ T A[CB][CB + 1];
+  __shared__ T Ri[CB][CB + 1];
+  __shared__ double s_keep[CB];
+  const int b = blockIdx.x;
+  const int cb = min(CB, k - jb);
+  T* Gb = G + b * sG;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < CB * CB; idx += 256) {
+    const int r = idx / CB, c = idx % CB;
+    T v = czero<T>();
+    if (r < cb && c < cb && r <= c) v = Gb[(long long)(jb + r) * ldg + jb + c];
+    A[r][c] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < cb; ++j) {
+    if (t == 0) {
+      const double piv = creal_(A[j][j]);
+      const double orig = diag0[b * sdiag + jb + j];
+      const bool keep = (piv > tau * orig) && (piv > 0.0);
+      s_keep[j] = keep ? 1.0 : 0.0;
+      if constexpr (sizeof(T) == 16) A[j][j] = cd{keep ? sqrt(piv) : 1.0, 0.0};
+      else A[j][j] = keep ? sqrt(piv) : 1.0;
+    }
+    __syncthreads();
+    const bool keep = s_keep[j] != 0.0;
+    const double rjj = creal_(A[j][j]);
+    for (int c = j + 1 + t; c < cb; c += 256) A[j][c] = keep ? cdiv_real(A[j][c], rjj) : czero<T>();
+    __syncthreads();
+    for (int idx = t; idx < cb * cb; idx += 256) {
+      const int r = idx / cb, c = idx % cb;
+      if (r > j && c >= r) A[r][c] = A[r][c] - cconj(A[j][r]) * A[j][c];
+    }
+    __syncthreads();
+  }
+  // inverse of the upper-triangular block (one column per thread)
+  if (t < cb) {
+    const int c = t;
+    for (int r = 0; r < CB; ++r) Ri[r][c] = czero<T>();
+    if constexpr (sizeof(T) == 16) Ri[c][c] = cd{1.0 / creal_(A[c][c]), 0.0};
+    else Ri[c][c] = 1.0 / creal_(A[c][c]);
+    for (int r = c - 1; r >= 0; --r) {
+      T acc = czero<T>();
+      for (int q = r + 1; q <= c; ++q) acc = acc + A[r][q] * Ri[q][c];
+      Ri[r][c] = cdiv_real(acc, -creal_(A[r][r]));
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < cb * cb; idx += 256) {
+    const int r = idx / cb, c = idx % cb;
+    Gb[(long long)(jb + r) * ldg + jb + c] = (r <= c) ? A[r][c] : czero<T>();
+    RI[b * sRI + (long long)r * CB + c] = Ri[r][c];
+  }
+  if (t < cb) mask[b * smask + jb + t] = s_keep[t];
+}
+
+template <typename T>
+__global__ void diag_copy_kernel(const T* G, long long ldg, long long sG, int k, double* diag0, long long sdiag) {
+  const int b = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < k; j += gridDim.x * 256)
+    diag0[b * sdiag + j] = creal_(G[b * sG + (long long)j * ldg + j]);
+}
+
+template <typename T>
+static hipError_t cholqr_impl(int mode, void* Y, long long ldy, long long sY, int m, int k, void* Q,
+                              long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s) {
+  const int dt = LT<T>::dtype;
+  const size_t es = sizeof(T);
+  char* G = reinterpret_cast<char*>(w.G);
+  const long long ldg = k, sG = (long long)k * k;
+  // G = Y^H Y (column mode) or X X^H (row mode)
+  GemmArgs g = mode == 0 ? gemm_args(k, k, m, OP_C, OP_N, Y, ldy, Y, ldy, G, ldg)
+                         : gemm_args(k, k, m, OP_N, OP_C, Y, ldy, Y, ldy, G, ldg);
+  g.sA = sY; g.sB = sY; g.sC = sG; g.batch = batch;
+  hipError_t err = gemm(dt, PREC_FP64, g, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(diag_copy_kernel<T>, dim3((k + 255) / 256, batch), dim3(256), 0, s, (const T*)G, ldg, sG,
+                     k, w.diag0, (long long)k);
+  const int nblk = (k + CB - 1) / CB;
+  char* RI = reinterpret_cast<char*>(w.RI);
+  const long long sRI = (long long)nblk * CB * CB;
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int jb = ib * CB, cb = std::min(CB, k - jb), rest = k - jb - cb;
+    hipLaunchKernelGGL(chol_diag_kernel<T>, dim3(batch), dim3(256), 0, s, (T*)G, ldg, sG, jb, k, w.diag0,
+                       (long long)k, (T*)(RI + (size_t)ib * CB * CB * es), sRI, w.mask, (long long)k, tau);
+    if (rest > 0) {
+      // R(jb, jb+cb:) = Rjj^-H G(jb, jb+cb:), dropped rows zeroed
+      GemmArgs p = gemm_args(cb, rest, cb, OP_C, OP_N, RI + (size_t)ib * CB * CB * es, CB,
+                             G + ((long long)jb * ldg + jb + cb) * es, ldg,
+                             G + ((long long)jb * ldg + jb + cb) * es, ldg);
+      p.sA = sRI; p.sB = sG; p.sC = sG; p.batch = batch;
+      p.rs = w.mask + jb; p.s_rs = k;
+      err = gemm(dt, PREC_FP64, p, s);
+      if (err != hipSuccess) return err;
+      // trailing: G(jb+cb:, jb+cb:) -= R(jb, jb+cb:)^H R(jb, jb+cb:)
+      GemmArgs t = gemm_args(rest, rest, cb, OP_C, OP_N, G + ((long long)jb * ldg + jb + cb) * es, ldg,
+                             G + ((long long)jb * ldg + jb + cb) * es, ldg,
+                             G + ((long long)(jb + cb) * ldg + jb + cb) * es, ldg);
+      t.sA = sG; t.sB = sG; t.sC = sG; t.batch = batch;
+      t.alpha_re = -1.0; t.beta_re = 1.0;
+      err = gemm(dt, PREC_FP64, t, s);
+      if (err != hipSuccess) return err;
+    }
+  }
+  // triangular solve, block by block; Y is consumed as workspace
+  char* Yc = reinterpret_cast<char*>(Y);
+  char* Qc = reinterpret_cast<char*>(Q);
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int jb = ib * CB, cb = std::min(CB, k - jb);
+    if (mode == 0) {
+      if (jb > 0) {
+        // Y(:, jb) -= Q(:, :jb) R(:jb, jb)
+        GemmArgs a1 = gemm_args(m, cb, jb, OP_N, OP_N, Qc, ldq, G + (long long)jb * es, ldg, Yc + (long long)jb * es, ldy);
+        a1.sA = sQ; a1.sB = sG; a1.sC = sY; a1.batch = batch;
+        a1.alpha_re = -1.0; a1.beta_re = 1.0;
+        err = gemm(dt, PREC_FP64, a1, s);
+        if (err != hipSuccess) return err;
+      }
+      // Q(:, jb) = Y(:, jb) Rjj^-1, dropped columns zeroed
+      GemmArgs a2 = gemm_args(m, cb, cb, OP_N, OP_N, Yc + (long long)jb * es, ldy, RI + (size_t)ib * CB * CB * es, CB,
+                              Qc + (long long)jb * es, ldq);
+      a2.sA = sY; a2.sB = sRI; a2.sC = sQ; a2.batch = batch;
+      a2.cs = w.mask + jb; a2.s_cs = k;
+      err = gemm(dt, PREC_FP64, a2, s);
+      if (err != hipSuccess) return err;
+    } else {
+      if (jb > 0) {
+        // X(jb, :) -= R(:jb, jb)^H Q(:jb, :)
+        GemmArgs a1 = gemm_args(cb, m, jb, OP_C, OP_N, G + (long long)jb * es, ldg, Qc, ldq,
+                                Yc + (long long)jb * ldy * es, ldy);
+        a1.sA = sG; a1.sB = sQ; a1.sC = sY; a1.batch = batch;
+        a1.alpha_re = -1.0; a1.beta_re = 1.0;
+        err = gemm(dt, PREC_FP64, a1, s);
+        if (err != hipSuccess) return err;
+      }
+      // Q(jb, :) = Rjj^-H X(jb, :), dropped rows zeroed
+      GemmArgs a2 = gemm_args(cb, m, cb, OP_C, OP_N, RI + (size_t)ib * CB * CB * es, CB,
+                              Yc + (long long)jb * ldy * es, ldy, Qc + (long long)jb * ldq * es, ldq);
+      a2.sA = sRI; a2.sB = sY; a2.sC = sQ; a2.batch = batch;
+      a2.rs = w.mask + jb; a2.s_rs = k;
+      err = gemm(dt, PREC_FP64, a2, s);
+      if (err != hipSuccess) return err;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t cholqr(int dtype, int mode, void* Y, long long ldy, long long sY, int m, int k, void* Q,
+                  long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s) {
+  if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
+  if (dtype == C128) return cholqr_impl<cd>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s);
+  if (dtype == F64) return cholqr_impl<double>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s);
+  return hipErrorInvalidValue;
+}
+
+size_t cholqr_work_elems(int k) {
+  const int nblk = (k + CB - 1) / CB;
+  return (size_t)k * k + (size_t)nblk * CB * CB;
+}
+
+}  // namespace tci

@@ -1,0 +1,108 @@
+// Host runtime of the library: context, tensor handles, workspace arena,
+// error reporting and the TCI_VERBOSE tracer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <chrono>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/tci_c.h"
+#include "common.hpp"
+
+namespace tci {
+
+constexpr int MAX_ORDER = 8;
+
+// Per-thread message of the last failed call.
+void set_error(const std::string& msg);
+
+struct Chunk {
+  void* ptr = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+// Grow-only device arena.  Regions handed out during one API call stay valid
+// until reset() at the start of the next call; all work is ordered on the
+// context stream, so re-use by a later call is safe.
+struct Arena {
+  std::vector<Chunk> chunks;
+  int device = 0;
+  void reset() {
+    for (auto& c : chunks) c.used = 0;
+  }
+  void* get(size_t bytes);
+  void release();
+};
+
+}  // namespace tci
+
+struct tci_context_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int verbose = 0;
+  int precision = TCI_PREC_FP32;  // mixed precision for F32 / C64 contractions
+  tci::Arena arena;
+  uint32_t magic = 0x7C1C0DE1u;
+};
+
+struct tci_tensor_s {
+  int dtype = TCI_F64;
+  int order = 0;
+  int64_t shape[tci::MAX_ORDER] = {0};
+  int32_t labels[tci::MAX_ORDER] = {0};
+  int nlabels = 0;
+  void* data = nullptr;
+  size_t cap = 0;   // bytes of storage
+  bool owns = false;
+  bool empty = false;  // moved-from
+};
+
+namespace tci {
+
+inline int64_t tsize(const tci_tensor_s* t) {
+  int64_t n = 1;
+  for (int i = 0; i < t->order; ++i) n *= t->shape[i];
+  return n;
+}
+inline size_t tbytes(const tci_tensor_s* t) { return (size_t)tsize(t) * elem_bytes(t->dtype); }
+
+// RAII-free status helpers.
+#define TCI_CHECK_HIP(expr)                                                         \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      ::tci::set_error(std::string("HIP error: ") + hipGetErrorString(_e) + " at " + \
+                       __FILE__ + ":" + std::to_string(__LINE__));                  \
+      return _e == hipErrorOutOfMemory ? TCI_ERR_OUT_OF_MEMORY : TCI_ERR_DEVICE;    \
+    }                                                                               \
+  } while (0)
+
+#define TCI_RET(code, msg)      \
+  do {                          \
+    ::tci::set_error(msg);      \
+    return (code);              \
+  } while (0)
+
+#define TCI_TRY(expr)                 \
+  do {                                \
+    tci_status _s = (expr);           \
+    if (_s != TCI_OK) return _s;      \
+  } while (0)
+
+// Make `t` an owning (or adequately sized) tensor of the given shape/dtype.
+tci_status ensure_shape(tci_context ctx, tci_tensor t, int dtype, int order, const int64_t* shape);
+
+// Tracer for TCI_VERBOSE (Spec, environment variables).
+struct Trace {
+  tci_context ctx;
+  const char* name;
+  std::chrono::steady_clock::time_point t0;
+  std::string info;
+  Trace(tci_context c, const char* n, std::string i = "");
+  ~Trace();
+};
+
+}  // namespace tci

@@ -1,0 +1,505 @@
+// Truncated SVD, QR, eigh and the two-site update composites.
+//
+// Plain truncated SVD of theta (m x n), TCI-spec appendix "trunc_svd":
+//   W = ||theta||_F^2; G = theta theta^H (m <= n) or theta^H theta (m > n);
+//   G = Q T Q^H (Householder, FP64); top eigenvalues of T by bisection;
+//   truncation rule a-c on s_j = sqrt(lambda_j) with eps measured against W;
+//   eigenvectors by inverse iteration, Cholesky-QR2 (FP64), U = Q Z;
+//   V^H = diag(1/s) U^H theta re-orthonormalised by row Cholesky-QR2.
+// The two-site update wraps it (Application A listing): theta = A.B, gate,
+// trunc_svd, renormalise s, write the new site tensors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tci_c.h"
+#include "common.hpp"
+#include "eig.hpp"
+#include "gemm.hpp"
+#include "linalg.hpp"
+#include "runtime.hpp"
+#include "tsvd.hpp"
+#include "vecops.hpp"
+
+namespace tci {
+
+static constexpr double CHOL_DROP_TAU = 1e-12;
+
+static int work_dtype(int dt) { return dt == C64 ? C128 : dt == F32 ? F64 : dt; }
+
+#define ARENA(ptr, type, count)                                                        \
+  type* ptr = static_cast<type*>(ctx->arena.get(sizeof(type) * (size_t)(count)));      \
+  if (!ptr) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace allocation failed: " #ptr)
+
+static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long ldx, long long sX, int m,
+                          int k, void* tmp, int nb) {
+  // X (column mode m x k, or row mode k x m) is orthonormalised in place; tmp is
+  // a buffer of the same size.  Two Cholesky-QR passes.
+  const size_t es = elem_bytes(wdt);
+  CholWork w{};
+  w.G = ctx->arena.get(es * cholqr_work_elems(k) * nb);
+  w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
+  w.diag0 = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
+  w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
+  if (!w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
+  // the RI region is addressed per problem with stride nblk*32*32 from w.RI;
+  // G with stride k*k from w.G (see cholqr_impl)
+  TCI_CHECK_HIP(cholqr(wdt, mode, X, ldx, sX, m, k, tmp, ldx, sX, w, CHOL_DROP_TAU, nb, ctx->stream));
+  TCI_CHECK_HIP(cholqr(wdt, mode, tmp, ldx, sX, m, k, X, ldx, sX, w, CHOL_DROP_TAU, nb, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, const TruncParams& tp,
+                    TsvdOut& out) {
+  hipStream_t s = ctx->stream;
+  const size_t es = elem_bytes(wdt);
+  const bool cplx = is_complex(wdt);
+  const int ng = std::min(m, n);
+  const bool left = (m <= n);
+  const int kmax = std::max(1, std::min(tp.chi_max, ng));
+  const long long smn = (long long)m * n;
+  out.kmax = kmax;
+
+  // total weight
+  ARENA(total, double, nb);
+  ARENA(partial, double, (size_t)nb * SUMSQ_PARTIALS);
+  TCI_CHECK_HIP(sumsq_batched(wdt, theta, smn, smn, total, partial, nb, s));
+  out.total = total;
+
+  // Gram matrix
+  ARENA(Gm, char, es * (size_t)ng * ng * nb);
+  const long long sG = (long long)ng * ng;
+  {
+    GemmArgs g = left ? gemm_args(ng, ng, n, OP_N, OP_C, theta, n, theta, n, Gm, ng)
+                      : gemm_args(ng, ng, m, OP_C, OP_N, theta, n, theta, n, Gm, ng);
+    g.sA = smn; g.sB = smn; g.sC = sG; g.batch = nb;
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
+  }
+  // tridiagonal reduction
+  ARENA(d, double, (size_t)ng * nb);
+  ARENA(e, double, (size_t)ng * nb);
+  ARENA(e2, double, (size_t)ng * nb);
+  ARENA(tau, char, es * (size_t)ng * nb);
+  ARENA(Vt, char, es * (size_t)ng * ng * nb);
+  ARENA(Wp, char, es * (size_t)ng * TRIDIAG_NB * nb);
+  ARENA(y, char, es * (size_t)ng * nb);
+  TriArgs ta{};
+  ta.n = ng;
+  ta.G = Gm; ta.ldg = ng; ta.sG = sG;
+  ta.d = d; ta.e = e; ta.sde = ng;
+  ta.tau = tau; ta.stau = ng;
+  ta.Vt = Vt; ta.sVt = sG;
+  ta.Wp = Wp; ta.sWp = (long long)ng * TRIDIAG_NB;
+  ta.y = y; ta.sy = ng;
+  TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * (size_t)ng * nb, s));
+  TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
+  // top eigenvalues and the truncation rule
+  ARENA(lam, double, (size_t)kmax * nb);
+  TCI_CHECK_HIP(tridiag_eigvals_top(d, e, e2, ng, ng, kmax, lam, kmax, nb, s));
+  ARENA(chi, int, nb);
+  ARENA(err, double, nb);
+  ARENA(disc, double, nb);
+  ARENA(sv, double, (size_t)kmax * nb);
+  ARENA(sinv, double, (size_t)kmax * nb);
+  ARENA(sn, double, (size_t)kmax * nb);
+  TCI_CHECK_HIP(trunc_select(lam, kmax, kmax, total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
+  out.chi = chi; out.s = sv; out.sn = sn;
+  out.chi_h.resize(nb); out.err_h.resize(nb); out.disc_h.resize(nb); out.total_h.resize(nb);
+  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), total, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(out.total_h[b])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in theta");
+  int kz = 1;
+  for (int b = 0; b < nb; ++b) kz = std::max(kz, out.chi_h[b]);
+  out.kz = kz;
+
+  // eigenvectors of T (real), orthonormalised
+  ARENA(Z, double, (size_t)ng * kz * nb);
+  ARENA(Z2, double, (size_t)ng * kz * nb);
+  ARENA(iw, double, (size_t)4 * ng * kz * nb);
+  const long long sZ = (long long)ng * kz;
+  TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)sZ * nb, s));
+  TCI_CHECK_HIP(tridiag_invit(d, e, ng, ng, lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
+  TCI_TRY(cholqr2(ctx, F64, 0, Z, kz, sZ, ng, kz, Z2, nb));
+  // back-transformation to eigenvectors of G
+  void* Ev;
+  if (cplx) {
+    Ev = ctx->arena.get(es * (size_t)sZ * nb);
+    if (!Ev) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+    TCI_CHECK_HIP(real_to_complex(Z, Ev, sZ, sZ, sZ, nb, s));
+  } else {
+    Ev = Z;
+  }
+  const int npan = (ng - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB;
+  ARENA(Tf, char, es * (size_t)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB * nb);
+  ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * kz * nb);
+  TCI_CHECK_HIP(tridiag_backtransform(wdt, ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
+                                      kz, sZ, kz, btw, nb, s));
+  // left factor U (m x kz)
+  const long long sU = (long long)m * kz;
+  void* U;
+  if (left) {
+    U = Ev;  // m == ng
+  } else {
+    // U = theta V diag(1/s), then orthonormalise its columns
+    U = ctx->arena.get(es * (size_t)sU * nb);
+    void* Ut = ctx->arena.get(es * (size_t)sU * nb);
+    if (!U || !Ut) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+    GemmArgs g = gemm_args(m, kz, n, OP_N, OP_N, theta, n, Ev, kz, U, kz);
+    g.sA = smn; g.sB = sZ; g.sC = sU; g.batch = nb;
+    g.cs = sinv; g.s_cs = kmax;
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
+    TCI_TRY(cholqr2(ctx, wdt, 0, U, kz, sU, m, kz, Ut, nb));
+  }
+  TCI_CHECK_HIP(gauge_columns(wdt, U, kz, sU, m, kz, chi, nb, s));
+  // V^H = diag(1/s) U^H theta, rows orthonormalised
+  const long long sV = (long long)kz * n;
+  void* Vh = ctx->arena.get(es * (size_t)sV * nb);
+  void* Vt2 = ctx->arena.get(es * (size_t)sV * nb);
+  if (!Vh || !Vt2) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  {
+    GemmArgs g = gemm_args(kz, n, m, OP_C, OP_N, U, kz, theta, n, Vh, n);
+    g.sA = sU; g.sB = smn; g.sC = sV; g.batch = nb;
+    g.rs = sinv; g.s_rs = kmax;
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
+  }
+  TCI_TRY(cholqr2(ctx, wdt, 1, Vh, n, sV, n, kz, Vt2, nb));
+  out.U = U;
+  out.Vh = Vh;
+  return TCI_OK;
+}
+
+static tci_status matricize(tci_tensor a, int k_rows, int64_t& rows, int64_t& cols) {
+  if (k_rows < 1 || k_rows >= a->order) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= k_rows < order");
+  rows = 1;
+  cols = 1;
+  for (int i = 0; i < k_rows; ++i) rows *= a->shape[i];
+  for (int i = k_rows; i < a->order; ++i) cols *= a->shape[i];
+  if (rows > (1LL << 30) || cols > (1LL << 30)) TCI_RET(TCI_ERR_UNSUPPORTED, "matrix too large");
+  return TCI_OK;
+}
+
+// Working copy of a tensor in FP64 (promoting F32/C64).
+static tci_status working_copy(tci_context ctx, tci_tensor a, int& wdt, const void*& w) {
+  wdt = a->dtype == C64 ? C128 : a->dtype == F32 ? F64 : a->dtype;
+  if (wdt == a->dtype) {
+    w = a->data;
+    return TCI_OK;
+  }
+  void* p = ctx->arena.get(elem_bytes(wdt) * (size_t)tsize(a));
+  if (!p) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(convert(a->dtype, a->data, wdt, p, tsize(a), ctx->stream));
+  w = p;
+  return TCI_OK;
+}
+
+// Copy device data of working type into an output tensor of dtype odt.
+static tci_status store_as(tci_context ctx, int wdt, const void* src, tci_tensor out) {
+  const long long n = tsize(out);
+  if (n == 0) return TCI_OK;
+  if (out->dtype == wdt)
+    TCI_CHECK_HIP(hipMemcpyAsync(out->data, src, (size_t)n * elem_bytes(wdt), hipMemcpyDeviceToDevice, ctx->stream));
+  else
+    TCI_CHECK_HIP(convert(wdt, src, out->dtype, out->data, n, ctx->stream));
+  return TCI_OK;
+}
+
+}  // namespace tci
+
+using namespace tci;
+
+extern "C" {
+
+tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s, tci_tensor vdag,
+                         double* trunc_err, int64_t chi_min, int64_t chi_max, double target_trunc_err,
+                         double s_min) {
+  if (!ctx || !a || !u || !s || !vdag) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (a->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "moved-from tensor");
+  if (chi_min < 1 || chi_max < 1 || chi_min > chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  Trace tr(ctx, "trunc_svd", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, a, wdt, w));
+  const int64_t kap = std::min(rows, cols);
+  TruncParams tp{(int)std::min<int64_t>(chi_min, kap), (int)std::min<int64_t>(chi_max, kap), target_trunc_err, s_min};
+  if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
+  TsvdOut o;
+  TCI_TRY(tsvd_run(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
+  const int chi = o.chi_h[0];
+  // outputs
+  int64_t ushape[MAX_ORDER + 1];
+  for (int i = 0; i < k_rows; ++i) ushape[i] = a->shape[i];
+  ushape[k_rows] = chi;
+  int64_t vshape[MAX_ORDER + 1];
+  vshape[0] = chi;
+  for (int i = k_rows; i < a->order; ++i) vshape[1 + i - k_rows] = a->shape[i];
+  const int odt = a->dtype;
+  const int rdt = is_double(odt) ? F64 : F32;
+  const int order_a = a->order;
+  TCI_TRY(ensure_shape(ctx, u, odt, k_rows + 1, ushape));
+  TCI_TRY(ensure_shape(ctx, vdag, odt, order_a - k_rows + 1, vshape));
+  int64_t sshape[1] = {chi};
+  TCI_TRY(ensure_shape(ctx, s, rdt, 1, sshape));
+  const size_t es = elem_bytes(wdt);
+  void* ucmp = ctx->arena.get(es * (size_t)rows * chi);
+  if (!ucmp) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(compact_columns(wdt, o.U, o.kz, (long long)rows * o.kz, ucmp, (long long)rows * chi, (int)rows, chi,
+                                o.chi, nullptr, 0, 1, ctx->stream));
+  TCI_TRY(store_as(ctx, wdt, ucmp, u));
+  TCI_TRY(store_as(ctx, wdt, o.Vh, vdag));  // first chi rows are contiguous
+  TCI_TRY(store_as(ctx, F64, o.s, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  if (trunc_err) *trunc_err = o.err_h[0];
+  return TCI_OK;
+}
+
+tci_status tci_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s, tci_tensor vdag) {
+  if (!a) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  const int64_t kap = std::min(rows, cols);
+  return tci_trunc_svd(ctx, a, k_rows, u, s, vdag, nullptr, kap, kap, 0.0, 0.0);
+}
+
+tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r) {
+  if (!ctx || !a || !q || !r) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  if (rows < cols) TCI_RET(TCI_ERR_UNSUPPORTED, "qr of a wide matrix (rows < cols) is not supported");
+  Trace tr(ctx, "qr", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, a, wdt, w));
+  const size_t es = elem_bytes(wdt);
+  const int m = (int)rows, k = (int)cols;
+  hipStream_t st = ctx->stream;
+  void* Y = ctx->arena.get(es * (size_t)m * k);
+  void* Q1 = ctx->arena.get(es * (size_t)m * k);
+  if (!Y || !Q1) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(hipMemcpyAsync(Y, w, es * (size_t)m * k, hipMemcpyDeviceToDevice, st));
+  CholWork w1{}, w2{};
+  for (CholWork* cw : {&w1, &w2}) {
+    cw->G = ctx->arena.get(es * cholqr_work_elems(k));
+    cw->RI = static_cast<char*>(cw->G) + es * (size_t)k * k;
+    cw->diag0 = static_cast<double*>(ctx->arena.get(sizeof(double) * k));
+    cw->mask = static_cast<double*>(ctx->arena.get(sizeof(double) * k));
+    if (!cw->G || !cw->diag0 || !cw->mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  }
+  TCI_CHECK_HIP(cholqr(wdt, 0, Y, k, 0, m, k, Q1, k, 0, w1, CHOL_DROP_TAU, 1, st));
+  TCI_CHECK_HIP(cholqr(wdt, 0, Q1, k, 0, m, k, Y, k, 0, w2, CHOL_DROP_TAU, 1, st));
+  // R = triu(R2) triu(R1) with dropped diagonals zeroed
+  TCI_CHECK_HIP(triu_mask(wdt, w1.G, k, 0, k, w1.mask, 0, 1, st));
+  TCI_CHECK_HIP(triu_mask(wdt, w2.G, k, 0, k, w2.mask, 0, 1, st));
+  void* R = ctx->arena.get(es * (size_t)k * k);
+  if (!R) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  GemmArgs g = gemm_args(k, k, k, OP_N, OP_N, w2.G, k, w1.G, k, R, k);
+  TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, st));
+  int64_t qshape[MAX_ORDER + 1], rshape[MAX_ORDER + 1];
+  for (int i = 0; i < k_rows; ++i) qshape[i] = a->shape[i];
+  qshape[k_rows] = k;
+  rshape[0] = k;
+  for (int i = k_rows; i < a->order; ++i) rshape[1 + i - k_rows] = a->shape[i];
+  const int odt = a->dtype, ord = a->order;
+  TCI_TRY(ensure_shape(ctx, q, odt, k_rows + 1, qshape));
+  TCI_TRY(ensure_shape(ctx, r, odt, ord - k_rows + 1, rshape));
+  TCI_TRY(store_as(ctx, wdt, Y, q));
+  TCI_TRY(store_as(ctx, wdt, R, r));
+  TCI_CHECK_HIP(hipStreamSynchronize(st));
+  return TCI_OK;
+}
+
+tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v) {
+  if (!ctx || !a || !w || !v) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  if (a->order != 2 || a->shape[0] != a->shape[1]) TCI_RET(TCI_ERR_SHAPE, "eigh needs a square matrix");
+  if (!is_double(a->dtype)) TCI_RET(TCI_ERR_DTYPE, "eigh supports F64 / C128");
+  Trace tr(ctx, "eigh", std::to_string(a->shape[0]));
+  ctx->arena.reset();
+  const int n = (int)a->shape[0], dt = a->dtype;
+  const size_t es = elem_bytes(dt);
+  hipStream_t s = ctx->stream;
+  ARENA(G, char, es * (size_t)n * n);
+  TCI_CHECK_HIP(hipMemcpyAsync(G, a->data, es * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  ARENA(d, double, n);
+  ARENA(e, double, n);
+  ARENA(e2, double, n);
+  ARENA(tau, char, es * n);
+  ARENA(Vt, char, es * (size_t)n * n);
+  ARENA(Wp, char, es * (size_t)n * TRIDIAG_NB);
+  ARENA(y, char, es * n);
+  TriArgs ta{};
+  ta.n = n; ta.G = G; ta.ldg = n; ta.d = d; ta.e = e; ta.tau = tau; ta.Vt = Vt; ta.Wp = Wp; ta.y = y;
+  TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
+  TCI_CHECK_HIP(tridiagonalize(dt, ta, 1, s));
+  ARENA(lam, double, n);
+  TCI_CHECK_HIP(tridiag_eigvals_top(d, e, e2, n, n, n, lam, n, 1, s));
+  ARENA(Z, double, (size_t)n * n);
+  ARENA(Z2, double, (size_t)n * n);
+  ARENA(iw, double, (size_t)4 * n * n);
+  TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)n * n, s));
+  TCI_CHECK_HIP(tridiag_invit(d, e, n, n, lam, n, nullptr, n, Z, n, 0, iw, 1, s));
+  TCI_TRY(cholqr2(ctx, F64, 0, Z, n, 0, n, n, Z2, 1));
+  void* Ev = Z;
+  if (is_complex(dt)) {
+    Ev = ctx->arena.get(es * (size_t)n * n);
+    if (!Ev) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+    TCI_CHECK_HIP(real_to_complex(Z, Ev, (long long)n * n, 0, 0, 1, s));
+  }
+  const int npan = std::max(1, (n - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB);
+  ARENA(Tf, char, es * (size_t)npan * TRIDIAG_NB * TRIDIAG_NB);
+  ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * n);
+  TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, 0, Ev, n, 0, n, btw, 1, s));
+  // ascending order: reverse the descending bisection order
+  TCI_CHECK_HIP(reverse_columns(dt, Ev, n, n, n, s));
+  TCI_CHECK_HIP(gauge_columns(dt, Ev, n, 0, n, n, nullptr, 1, s));
+  std::vector<double> lh(n);
+  TCI_CHECK_HIP(hipMemcpyAsync(lh.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  std::reverse(lh.begin(), lh.end());
+  int64_t wshape[1] = {n}, vshape[2] = {n, n};
+  TCI_TRY(ensure_shape(ctx, w, F64, 1, wshape));
+  TCI_TRY(ensure_shape(ctx, v, dt, 2, vshape));
+  TCI_CHECK_HIP(hipMemcpyAsync(w->data, lh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(v->data, Ev, es * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  return TCI_OK;
+}
+
+// ----------------------------------------------------------------- two-site update
+tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tensor* A, const tci_tensor* B,
+                                       const tci_tensor* gates, const tci_update_params* params,
+                                       tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out,
+                                       tci_update_info* infos) {
+  if (!ctx || nupd < 1 || !A || !B || !A_out || !s_out || !B_out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  tci_update_params p;
+  if (params) p = *params;
+  else tci_update_params_default(&p);
+  if (p.chi_min < 1 || p.chi_max < 1 || p.chi_min > p.chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
+  const tci_tensor a0 = A[0], b0 = B[0];
+  if (!a0 || !b0 || a0->order != 3 || b0->order != 3) TCI_RET(TCI_ERR_SHAPE, "A and B must be order 3");
+  const int dt = a0->dtype;
+  const int64_t chil = a0->shape[0], d = a0->shape[1], chim = a0->shape[2], chir = b0->shape[2];
+  if (b0->shape[0] != chim || b0->shape[1] != d) TCI_RET(TCI_ERR_SHAPE, "A and B bond mismatch");
+  for (int i = 0; i < nupd; ++i) {
+    if (!A[i] || !B[i] || !A_out[i] || !s_out[i] || !B_out[i]) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null tensor");
+    if (A[i]->dtype != dt || B[i]->dtype != dt) TCI_RET(TCI_ERR_DTYPE, "mixed dtypes in the batch");
+    for (int k = 0; k < 3; ++k)
+      if (A[i]->shape[k] != a0->shape[k] || B[i]->shape[k] != b0->shape[k])
+        TCI_RET(TCI_ERR_SHAPE, "all updates of a batch must have the same shapes");
+    if (gates && gates[i]) {
+      if (gates[i]->dtype != dt) TCI_RET(TCI_ERR_DTYPE, "gate dtype");
+      if (tsize(gates[i]) != d * d * d * d) TCI_RET(TCI_ERR_SHAPE, "gate must have d^4 elements");
+    }
+  }
+  if (gates && d != 2) TCI_RET(TCI_ERR_UNSUPPORTED, "gates are supported for d = 2");
+  const int prec = p.precision;
+  if (is_double(dt) != (prec == TCI_PREC_FP64))
+    TCI_RET(TCI_ERR_DTYPE, "FP64 precision needs F64/C128 tensors, mixed precisions F32/C64");
+  if (p.svd_mode != TCI_SVD_PLAIN) return tci_two_site_update_sketched(ctx, nupd, A, B, gates, &p, A_out, s_out, B_out, infos);
+  Trace tr(ctx, "two_site_update_batched", std::to_string(nupd) + " x " + std::to_string(chil) + "," +
+                                               std::to_string(d) + "," + std::to_string(chir));
+  const int m = (int)(chil * d), n = (int)(d * chir), K = (int)chim;
+  const int wdt = work_dtype(dt);
+  const size_t es = elem_bytes(dt), wes = elem_bytes(wdt);
+  hipStream_t s = ctx->stream;
+  const int maxb = p.max_batch > 0 ? p.max_batch : 64;
+  for (int c0 = 0; c0 < nupd; c0 += maxb) {
+    const int nb = std::min(maxb, nupd - c0);
+    ctx->arena.reset();
+    // gather operands into strided batches
+    const size_t szA = (size_t)chil * d * chim, szB = (size_t)chim * d * chir;
+    ARENA(Ab, char, es * szA * nb);
+    ARENA(Bb, char, es * szB * nb);
+    for (int i = 0; i < nb; ++i) {
+      TCI_CHECK_HIP(hipMemcpyAsync(Ab + es * szA * i, A[c0 + i]->data, es * szA, hipMemcpyDeviceToDevice, s));
+      TCI_CHECK_HIP(hipMemcpyAsync(Bb + es * szB * i, B[c0 + i]->data, es * szB, hipMemcpyDeviceToDevice, s));
+    }
+    // theta = A . B  (contraction over the shared bond)
+    const long long smn = (long long)m * n;
+    ARENA(th, char, es * (size_t)smn * nb);
+    {
+      GemmArgs g = gemm_args(m, n, K, OP_N, OP_N, Ab, K, Bb, n, th, n);
+      g.sA = (long long)szA; g.sB = (long long)szB; g.sC = smn; g.batch = nb;
+      TCI_CHECK_HIP(gemm(dt, prec, g, s));
+    }
+    // gate
+    if (gates) {
+      const int g2 = (int)(d * d * d * d);
+      ARENA(Gb, char, es * (size_t)g2 * nb);
+      std::vector<double> eye(2 * 16, 0.0);
+      for (int i = 0; i < nb; ++i) {
+        if (gates[c0 + i]) {
+          TCI_CHECK_HIP(hipMemcpyAsync(Gb + es * g2 * i, gates[c0 + i]->data, es * g2, hipMemcpyDeviceToDevice, s));
+        } else {
+          // identity in the batch's dtype
+          std::vector<char> host(es * g2, 0);
+          for (int q = 0; q < 4; ++q) {
+            char* p0 = host.data() + es * (q * 4 + q);
+            if (dt == C128 || dt == F64) { const double one = 1.0; std::memcpy(p0, &one, 8); }
+            else { const float one = 1.0f; std::memcpy(p0, &one, 4); }
+          }
+          TCI_CHECK_HIP(hipMemcpy(Gb + es * g2 * i, host.data(), es * g2, hipMemcpyHostToDevice));
+        }
+      }
+      TCI_CHECK_HIP(gate_apply(dt, th, smn, Gb, g2, (int)chil, (int)d, (int)chir, nb, s));
+    }
+    // FP64 working copy for the decomposition
+    const void* thw = th;
+    if (wdt != dt) {
+      ARENA(tw, char, wes * (size_t)smn * nb);
+      TCI_CHECK_HIP(convert(dt, th, wdt, tw, smn * nb, s));
+      thw = tw;
+    }
+    TruncParams tp{(int)std::min<int64_t>(p.chi_min, std::min(m, n)), (int)std::min<int64_t>(p.chi_max, std::min(m, n)),
+                   p.target_trunc_err, p.s_min};
+    if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
+    TsvdOut o;
+    TCI_TRY(tsvd_run(ctx, wdt, nb, m, n, thw, tp, o));
+    // write-back
+    const int kz = o.kz;
+    ARENA(Ucmp, char, wes * (size_t)m * kz * nb);
+    ARENA(Vcmp, char, wes * (size_t)kz * n * nb);
+    const bool right = p.direction == TCI_DIR_RIGHT;
+    TCI_CHECK_HIP(compact_columns(wdt, o.U, kz, (long long)m * kz, Ucmp, (long long)m * kz, m, kz, o.chi,
+                                  right ? o.sn : nullptr, o.kmax, nb, s));
+    TCI_CHECK_HIP(scale_rows(wdt, o.Vh, (long long)kz * n, Vcmp, (long long)kz * n, n, kz, o.chi,
+                             right ? nullptr : o.sn, o.kmax, nb, s));
+    for (int i = 0; i < nb; ++i) {
+      const int64_t chi = o.chi_h[i];
+      const int64_t ash[3] = {chil, d, chi}, bsh[3] = {chi, d, chir}, ssh[1] = {chi};
+      TCI_TRY(ensure_shape(ctx, A_out[c0 + i], dt, 3, ash));
+      TCI_TRY(ensure_shape(ctx, B_out[c0 + i], dt, 3, bsh));
+      TCI_TRY(ensure_shape(ctx, s_out[c0 + i], F64, 1, ssh));
+      TCI_TRY(store_as(ctx, wdt, Ucmp + wes * (size_t)m * kz * i, A_out[c0 + i]));
+      TCI_TRY(store_as(ctx, wdt, Vcmp + wes * (size_t)kz * n * i, B_out[c0 + i]));
+      TCI_CHECK_HIP(hipMemcpyAsync(s_out[c0 + i]->data, o.sn + (size_t)o.kmax * i, sizeof(double) * chi,
+                                   hipMemcpyDeviceToDevice, s));
+      if (infos) {
+        tci_update_info& inf = infos[c0 + i];
+        std::memset(&inf, 0, sizeof(inf));
+        inf.chi = chi;
+        inf.trunc_err = o.err_h[i];
+        inf.discarded_abs = o.disc_h[i];
+        inf.norm2 = o.total_h[i];
+      }
+    }
+    TCI_CHECK_HIP(hipStreamSynchronize(s));
+  }
+  return TCI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,343 @@
+// Elementwise and vector kernels: dtype conversion, conjugation, scaling,
+// linear combinations (TCI-spec appendix: convert, cplx_conj, scale,
+// linear_combine), elementwise closeness (close), the Lanczos multi-dot /
+// multi-axpy with FP64 accumulation, and the two-site MPO product W12.
+#include "common.hpp"
+#include "vecops.hpp"
+
+namespace tci {
+
+template <typename T> struct VT;
+template <> struct VT<double> { typedef double R; static constexpr bool c = false; };
+template <> struct VT<float> { typedef float R; static constexpr bool c = false; };
+template <> struct VT<cd> { typedef double R; static constexpr bool c = true; };
+template <> struct VT<cf> { typedef float R; static constexpr bool c = true; };
+
+__device__ inline void get2(const double* p, long long i, double& r, double& im) { r = p[i]; im = 0; }
+__device__ inline void get2(const float* p, long long i, double& r, double& im) { r = p[i]; im = 0; }
+__device__ inline void get2(const cd* p, long long i, double& r, double& im) { r = p[i].x; im = p[i].y; }
+__device__ inline void get2(const cf* p, long long i, double& r, double& im) { r = p[i].x; im = p[i].y; }
+__device__ inline void put2(double* p, long long i, double r, double) { p[i] = r; }
+__device__ inline void put2(float* p, long long i, double r, double) { p[i] = (float)r; }
+__device__ inline void put2(cd* p, long long i, double r, double im) { p[i] = cd{r, im}; }
+__device__ inline void put2(cf* p, long long i, double r, double im) { p[i] = cf{(float)r, (float)im}; }
+
+template <typename S, typename D>
+__global__ void convert_kernel(const S* in, D* out, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double r, im;
+    get2(in, i, r, im);
+    put2(out, i, r, im);
+  }
+}
+
+static unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256)); }
+
+template <typename S>
+static hipError_t convert_from(const S* in, int dst, void* out, long long n, hipStream_t s) {
+  switch (dst) {
+    case F32: hipLaunchKernelGGL((convert_kernel<S, float>), dim3(grid_for(n)), dim3(256), 0, s, in, (float*)out, n); break;
+    case F64: hipLaunchKernelGGL((convert_kernel<S, double>), dim3(grid_for(n)), dim3(256), 0, s, in, (double*)out, n); break;
+    case C64: hipLaunchKernelGGL((convert_kernel<S, cf>), dim3(grid_for(n)), dim3(256), 0, s, in, (cf*)out, n); break;
+    case C128: hipLaunchKernelGGL((convert_kernel<S, cd>), dim3(grid_for(n)), dim3(256), 0, s, in, (cd*)out, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t convert(int src, const void* in, int dst, void* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (src) {
+    case F32: return convert_from((const float*)in, dst, out, n, s);
+    case F64: return convert_from((const double*)in, dst, out, n, s);
+    case C64: return convert_from((const cf*)in, dst, out, n, s);
+    case C128: return convert_from((const cd*)in, dst, out, n, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// out = conj(in) (plain copy for real types)
+template <typename T>
+__global__ void conj_kernel(const T* in, T* out, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double r, im;
+    get2(in, i, r, im);
+    put2(out, i, r, -im);
+  }
+}
+
+hipError_t conjugate(int dt, const void* in, void* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (dt) {
+    case F32: hipLaunchKernelGGL(conj_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)in, (float*)out, n); break;
+    case F64: hipLaunchKernelGGL(conj_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)in, (double*)out, n); break;
+    case C64: hipLaunchKernelGGL(conj_kernel<cf>, dim3(grid_for(n)), dim3(256), 0, s, (const cf*)in, (cf*)out, n); break;
+    case C128: hipLaunchKernelGGL(conj_kernel<cd>, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)in, (cd*)out, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// out = sum_q c_q in_q, c_q complex (re, im) in double, q < nin; in pointers
+// and coefficients passed through a small device array.
+template <typename T>
+__global__ void lincomb_kernel(const LinCombArgs a, T* out, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double ar = 0, ai = 0;
+    for (int q = 0; q < a.nin; ++q) {
+      double r, im;
+      get2(reinterpret_cast<const T*>(a.in[q]), i, r, im);
+      ar += a.cre[q] * r - a.cim[q] * im;
+      ai += a.cre[q] * im + a.cim[q] * r;
+    }
+    put2(out, i, ar, ai);
+  }
+}
+
+hipError_t linear_combine(int dt, const LinCombArgs& a, void* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (dt) {
+    case F32: hipLaunchKernelGGL(lincomb_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, a, (float*)out, n); break;
+    case F64: hipLaunchKernelGGL(lincomb_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, a, (double*)out, n); break;
+    case C64: hipLaunchKernelGGL(lincomb_kernel<cf>, dim3(grid_for(n)), dim3(256), 0, s, a, (cf*)out, n); break;
+    case C128: hipLaunchKernelGGL(lincomb_kernel<cd>, dim3(grid_for(n)), dim3(256), 0, s, a, (cd*)out, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Per-block maximum of |a_i - b_i| (modulus for complex), final max over blocks.
+template <typename T>
+__global__ __launch_bounds__(256) void maxdiff_kernel(const T* a, const T* b, long long n, double* partial) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double ar, ai, br, bi;
+    get2(a, i, ar, ai);
+    get2(b, i, br, bi);
+    const double dr = ar - br, di = ai - bi;
+    const double v = sqrt(dr * dr + di * di);
+    m = (v > m || v != v) ? v : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double o = sh[threadIdx.x + off];
+      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+hipError_t max_abs_diff(int dt, const void* a, const void* b, long long n, double* partial, int nparts,
+                        hipStream_t s) {
+  const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(nparts, (n + 255) / 256));
+  switch (dt) {
+    case F32: hipLaunchKernelGGL(maxdiff_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)a, (const float*)b, n, partial); break;
+    case F64: hipLaunchKernelGGL(maxdiff_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)a, (const double*)b, n, partial); break;
+    case C64: hipLaunchKernelGGL(maxdiff_kernel<cf>, dim3(g), dim3(256), 0, s, (const cf*)a, (const cf*)b, n, partial); break;
+    case C128: hipLaunchKernelGGL(maxdiff_kernel<cd>, dim3(g), dim3(256), 0, s, (const cd*)a, (const cd*)b, n, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos vector kernels on complex128 vectors of length n.
+//   multidot: c_q = <v_q, w> = sum_i conj(v_q[i]) w[i], q < nv (basis rows of
+//             length n, ld n), two-pass deterministic reduction;
+//   multiaxpy: w[i] += sum_q c_q v_q[i]  (c given as (re, im) on the device).
+// ---------------------------------------------------------------------------
+constexpr int MD_BLOCKS = 256;
+constexpr int MD_MAXV = 32;
+
+__global__ __launch_bounds__(256) void multidot_partial_kernel(const cd* V, int nv, const cd* w, long long n,
+                                                               double* partial) {
+  __shared__ double sh[16];
+  double accr[MD_MAXV], acci[MD_MAXV];
+  for (int q = 0; q < nv; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cd x = w[i];
+    for (int q = 0; q < nv; ++q) {
+      const cd v = V[(long long)q * n + i];
+      accr[q] += v.x * x.x + v.y * x.y;
+      acci[q] += v.x * x.y - v.y * x.x;
+    }
+  }
+  for (int q = 0; q < nv; ++q) {
+    const double r = block_sum(accr[q], sh);
+    const double im = block_sum(acci[q], sh);
+    if (threadIdx.x == 0) {
+      partial[((long long)blockIdx.x * MD_MAXV + q) * 2 + 0] = r;
+      partial[((long long)blockIdx.x * MD_MAXV + q) * 2 + 1] = im;
+    }
+  }
+}
+
+__global__ void multidot_final_kernel(const double* partial, int nparts, int nv, double* out) {
+  const int q = threadIdx.x;
+  if (q >= nv) return;
+  double r = 0.0, im = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    r += partial[((long long)b * MD_MAXV + q) * 2 + 0];
+    im += partial[((long long)b * MD_MAXV + q) * 2 + 1];
+  }
+  out[2 * q] = r;
+  out[2 * q + 1] = im;
+}
+
+hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
+                    hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  if (nv > MD_MAXV) return hipErrorInvalidValue;
+  const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(MD_BLOCKS, (n + 255) / 256));
+  hipLaunchKernelGGL(multidot_partial_kernel, dim3(g), dim3(256), 0, s, (const cd*)V, nv, (const cd*)w, n, partial);
+  hipLaunchKernelGGL(multidot_final_kernel, dim3(1), dim3(64), 0, s, partial, (int)g, nv, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, const double* c, double sign,
+                                                        cd* w, long long n) {
+  double cr[MD_MAXV], ci[MD_MAXV];
+  for (int q = 0; q < nv; ++q) { cr[q] = sign * c[2 * q]; ci[q] = sign * c[2 * q + 1]; }
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    cd acc = w[i];
+    for (int q = 0; q < nv; ++q) {
+      const cd v = V[(long long)q * n + i];
+      acc.x += cr[q] * v.x - ci[q] * v.y;
+      acc.y += cr[q] * v.y + ci[q] * v.x;
+    }
+    w[i] = acc;
+  }
+}
+
+hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  if (nv > MD_MAXV) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)V, nv, c, sign, (cd*)w, n);
+  return hipGetLastError();
+}
+
+// w = x * (sr + i si) (scaled copy, complex128)
+__global__ void scale_copy_kernel(const cd* x, double sr, double si, cd* w, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cd v = x[i];
+    w[i] = cd{sr * v.x - si * v.y, sr * v.y + si * v.x};
+  }
+}
+
+hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, sr, si, (cd*)w, n);
+  return hipGetLastError();
+}
+
+// Elementwise in-place scaling by a complex scalar for any dtype.
+template <typename T>
+__global__ void scale_kernel(T* x, long long n, double sr, double si) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    double r, im;
+    get2(x, i, r, im);
+    put2(x, i, sr * r - si * im, sr * im + si * r);
+  }
+}
+
+hipError_t scale_inplace(int dt, void* x, long long n, double sr, double si, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (dt) {
+    case F32: hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, (float*)x, n, sr, si); break;
+    case F64: hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, (double*)x, n, sr, si); break;
+    case C64: hipLaunchKernelGGL(scale_kernel<cf>, dim3(grid_for(n)), dim3(256), 0, s, (cf*)x, n, sr, si); break;
+    case C128: hipLaunchKernelGGL(scale_kernel<cd>, dim3(grid_for(n)), dim3(256), 0, s, (cd*)x, n, sr, si); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// W12[(w, s1', s2'), (s1, s2, w'')] = sum_{w'} W1[w,w',s1,s1'] W2[w',w'',s2,s2']
+// (one thread per output element; W1, W2 of shape (wd, wd, d, d)).
+template <typename T>
+__global__ void w12_kernel(const T* W1, const T* W2, T* W12, int wd, int d) {
+  const int K = wd * d * d;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * K) return;
+  const int row = idx / K, col = idx % K;
+  const int w = row / (d * d), s1p = (row / d) % d, s2p = row % d;
+  const int s1 = col / (d * wd), s2 = (col / wd) % d, wpp = col % wd;
+  double ar = 0, ai = 0;
+  for (int wp = 0; wp < wd; ++wp) {
+    double r1, i1, r2, i2;
+    get2(W1, (((long long)w * wd + wp) * d + s1) * d + s1p, r1, i1);
+    get2(W2, (((long long)wp * wd + wpp) * d + s2) * d + s2p, r2, i2);
+    ar += r1 * r2 - i1 * i2;
+    ai += r1 * i2 + i1 * r2;
+  }
+  put2(W12, idx, ar, ai);
+}
+
+hipError_t mpo_pair(int dt, const void* W1, const void* W2, void* W12, int wd, int d, hipStream_t s) {
+  const int K = wd * d * d, n = K * K;
+  switch (dt) {
+    case F32: hipLaunchKernelGGL(w12_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, s, (const float*)W1, (const float*)W2, (float*)W12, wd, d); break;
+    case F64: hipLaunchKernelGGL(w12_kernel<double>, dim3((n + 255) / 256), dim3(256), 0, s, (const double*)W1, (const double*)W2, (double*)W12, wd, d); break;
+    case C64: hipLaunchKernelGGL(w12_kernel<cf>, dim3((n + 255) / 256), dim3(256), 0, s, (const cf*)W1, (const cf*)W2, (cf*)W12, wd, d); break;
+    case C128: hipLaunchKernelGGL(w12_kernel<cd>, dim3((n + 255) / 256), dim3(256), 0, s, (const cd*)W1, (const cd*)W2, (cd*)W12, wd, d); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Upper triangle of a k x k matrix (strict lower part zeroed), diagonal
+// multiplied by mask (0 for dropped columns): R factor of Cholesky-QR.
+template <typename T>
+__global__ void triu_mask_kernel(T* R, long long ld, long long sR, int k, const double* mask, long long smask) {
+  const int b = blockIdx.y;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < (long long)k * k; idx += (long long)gridDim.x * 256) {
+    const int r = (int)(idx / k), c = (int)(idx % k);
+    T* p = R + b * sR + (long long)r * ld + c;
+    if (r > c) put2(p, 0, 0.0, 0.0);
+    else if (r == c) {
+      double vr, vi;
+      get2(p, 0, vr, vi);
+      const double m = mask[b * smask + r];
+      put2(p, 0, vr * m, vi * m);
+    }
+  }
+}
+
+hipError_t triu_mask(int dt, void* R, long long ld, long long sR, int k, const double* mask, long long smask,
+                     int batch, hipStream_t s) {
+  dim3 g(grid_for((long long)k * k), batch);
+  switch (dt) {
+    case F64: hipLaunchKernelGGL(triu_mask_kernel<double>, g, dim3(256), 0, s, (double*)R, ld, sR, k, mask, smask); break;
+    case C128: hipLaunchKernelGGL(triu_mask_kernel<cd>, g, dim3(256), 0, s, (cd*)R, ld, sR, k, mask, smask); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Reverse the order of the first k columns of U (n x ld) and of lam (for
+// ascending eigenvalue order).
+template <typename T>
+__global__ void reverse_cols_kernel(T* U, long long ld, int rows, int k) {
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= (long long)rows * (k / 2)) return;
+  const int r = (int)(idx / (k / 2)), c = (int)(idx % (k / 2));
+  T* row = U + (long long)r * ld;
+  const T t = row[c];
+  row[c] = row[k - 1 - c];
+  row[k - 1 - c] = t;
+}
+
+hipError_t reverse_columns(int dt, void* U, long long ld, int rows, int k, hipStream_t s) {
+  if (k < 2) return hipSuccess;
+  const long long n = (long long)rows * (k / 2);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (dt == C128) hipLaunchKernelGGL(reverse_cols_kernel<cd>, dim3(g), dim3(256), 0, s, (cd*)U, ld, rows, k);
+  else if (dt == F64) hipLaunchKernelGGL(reverse_cols_kernel<double>, dim3(g), dim3(256), 0, s, (double*)U, ld, rows, k);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace tci

@@ -1,0 +1,31 @@
+// Elementwise / vector kernels (see vecops.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tci {
+
+constexpr int LINCOMB_MAX = 16;
+struct LinCombArgs {
+  int nin;
+  const void* in[LINCOMB_MAX];
+  double cre[LINCOMB_MAX], cim[LINCOMB_MAX];
+};
+
+hipError_t convert(int src, const void* in, int dst, void* out, long long n, hipStream_t s);
+hipError_t conjugate(int dt, const void* in, void* out, long long n, hipStream_t s);
+hipError_t linear_combine(int dt, const LinCombArgs& a, void* out, long long n, hipStream_t s);
+// partial: nparts doubles; the result is max over partial[0 .. min(nparts, blocks)-1]
+hipError_t max_abs_diff(int dt, const void* a, const void* b, long long n, double* partial, int nparts,
+                        hipStream_t s);
+constexpr int MULTIDOT_PARTIAL_DOUBLES = 256 * 32 * 2;
+hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
+                    hipStream_t s);
+hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s);
+hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s);
+hipError_t scale_inplace(int dt, void* x, long long n, double sr, double si, hipStream_t s);
+hipError_t mpo_pair(int dt, const void* W1, const void* W2, void* W12, int wd, int d, hipStream_t s);
+hipError_t triu_mask(int dt, void* R, long long ld, long long sR, int k, const double* mask, long long smask,
+                     int batch, hipStream_t s);
+hipError_t reverse_columns(int dt, void* U, long long ld, int rows, int k, hipStream_t s);
+
+}  // namespace tci

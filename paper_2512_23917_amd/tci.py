@@ -1,0 +1,378 @@
+"""Thin Python binding of libtci_mi355x.so (the C ABI in include/tci_c.h).
+
+Only argument marshalling lives here: every numeric step runs in the HIP
+library.  PyTorch provides device memory and the stream: tensors are wrapped
+(borrowed) views of contiguous torch tensors, outputs are allocated as torch
+tensors of sufficient capacity and reshaped to the size the library reports.
+The library must be built (``python -m paper_2512_23917_amd.build``); there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtci_mi355x.so")
+
+F32, F64, C64, C128 = 0, 1, 2, 3
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+SVD_PLAIN, SVD_RANDOMIZED, SVD_LEARNED = 0, 1, 2
+DIR_LEFT, DIR_RIGHT = 0, 1
+
+STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "SHAPE", 3: "LABEL", 4: "DTYPE", 5: "OUT_OF_MEMORY",
+          6: "DEVICE", 7: "NOT_CONVERGED", 8: "NUMERIC", 9: "UNSUPPORTED"}
+
+TORCH_OF = {F32: torch.float32, F64: torch.float64, C64: torch.complex64, C128: torch.complex128}
+DTYPE_OF = {v: k for k, v in TORCH_OF.items()}
+ELEM_BYTES = {F32: 4, F64: 8, C64: 8, C128: 16}
+
+
+class TciError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class UpdateParams(ctypes.Structure):
+    _fields_ = [("chi_min", ctypes.c_int64), ("chi_max", ctypes.c_int64),
+                ("target_trunc_err", ctypes.c_double), ("s_min", ctypes.c_double),
+                ("direction", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("svd_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("cert_tol", ctypes.c_double),
+                ("sketch_model", ctypes.c_void_p)]
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [("chi", ctypes.c_int64), ("trunc_err", ctypes.c_double),
+                ("discarded_abs", ctypes.c_double), ("norm2", ctypes.c_double),
+                ("used_fallback", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
+                ("max_residual", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2512_23917_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "tci_version": (ctypes.c_char_p, []),
+        "tci_last_error": (ctypes.c_char_p, []),
+        "tci_create_context": (i32, [P(p), ctypes.c_int, p]),
+        "tci_destroy_context": (i32, [p]),
+        "tci_set_stream": (i32, [p, p]),
+        "tci_set_precision": (i32, [p, ctypes.c_int]),
+        "tci_allocate": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), P(p)]),
+        "tci_zeros": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), P(p)]),
+        "tci_wrap": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), p, P(p)]),
+        "tci_copy": (i32, [p, p, P(p)]),
+        "tci_move": (i32, [p, P(p), P(p)]),
+        "tci_destroy": (i32, [p, p]),
+        "tci_order": (i32, [p, p, P(ctypes.c_int)]),
+        "tci_shape": (i32, [p, p, P(i64), ctypes.c_int]),
+        "tci_size": (i32, [p, p, P(i64)]),
+        "tci_size_bytes": (i32, [p, p, P(i64)]),
+        "tci_dtype_of": (i32, [p, p, P(ctypes.c_int)]),
+        "tci_data_ptr": (i32, [p, p, P(p)]),
+        "tci_get_elem": (i32, [p, p, P(i64), p]),
+        "tci_set_elem": (i32, [p, p, P(i64), p]),
+        "tci_set_labels": (i32, [p, p, P(i32), ctypes.c_int]),
+        "tci_get_labels": (i32, [p, p, P(i32), ctypes.c_int]),
+        "tci_from_host": (i32, [p, p, p, ctypes.c_size_t]),
+        "tci_to_host": (i32, [p, p, p, ctypes.c_size_t]),
+        "tci_convert": (i32, [p, p, ctypes.c_int, P(p)]),
+        "tci_reshape": (i32, [p, p, ctypes.c_int, P(i64), p]),
+        "tci_transpose": (i32, [p, p, P(i32), p]),
+        "tci_cplx_conj": (i32, [p, p, p]),
+        "tci_scale": (i32, [p, p, p]),
+        "tci_linear_combine": (i32, [p, ctypes.c_int, P(p), p, p]),
+        "tci_norm": (i32, [p, p, P(f64)]),
+        "tci_normalize": (i32, [p, p, P(f64)]),
+        "tci_contract": (i32, [p, p, P(i32), ctypes.c_int, p, P(i32), ctypes.c_int, p, P(i32), ctypes.c_int]),
+        "tci_contract_str": (i32, [p, p, ctypes.c_char_p, p, ctypes.c_char_p, p, ctypes.c_char_p]),
+        "tci_svd": (i32, [p, p, ctypes.c_int, p, p, p]),
+        "tci_trunc_svd": (i32, [p, p, ctypes.c_int, p, p, p, P(f64), i64, i64, f64, f64]),
+        "tci_qr": (i32, [p, p, ctypes.c_int, p, p]),
+        "tci_eigh": (i32, [p, p, p, p]),
+        "tci_close": (i32, [p, p, p, f64, P(ctypes.c_int)]),
+        "tci_update_params_default": (None, [P(UpdateParams)]),
+        "tci_two_site_update_batched": (i32, [p, ctypes.c_int, P(p), P(p), P(p), P(UpdateParams),
+                                              P(p), P(p), P(p), P(UpdateInfo)]),
+        "tci_heff_matvec": (i32, [p, p, p, p, p, p, p]),
+        "tci_lanczos_ground": (i32, [p, p, p, p, p, p, ctypes.c_int, P(f64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int, func: str):
+    if st != 0:
+        raise TciError(st, func, lib().tci_last_error().decode())
+
+
+def _i64(seq):
+    seq = [int(x) for x in seq]
+    return (ctypes.c_int64 * max(1, len(seq)))(*seq)
+
+
+def _i32(seq):
+    seq = [int(x) for x in seq]
+    return (ctypes.c_int32 * max(1, len(seq)))(*seq)
+
+
+class Context:
+    """tci_create_context on a torch device, ordered on its current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP library needs an MI355X")
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
+        self.stream = st
+        h = ctypes.c_void_p()
+        _check(lib().tci_create_context(ctypes.byref(h), device, ctypes.c_void_p(st.cuda_stream)),
+               "tci_create_context")
+        self.h = h
+
+    def set_precision(self, prec: int):
+        _check(lib().tci_set_precision(self.h, prec), "tci_set_precision")
+
+    def close(self):
+        if self.h:
+            _check(lib().tci_destroy_context(self.h), "tci_destroy_context")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tensor:
+    """A tci_tensor borrowing the memory of a contiguous torch tensor."""
+
+    def __init__(self, ctx: Context, buf: torch.Tensor, shape=None):
+        if not buf.is_contiguous():
+            buf = buf.contiguous()
+        self.ctx = ctx
+        self.buf = buf
+        self.dtype = DTYPE_OF[buf.dtype]
+        shape = list(buf.shape) if shape is None else list(shape)
+        h = ctypes.c_void_p()
+        _check(lib().tci_wrap(ctx.h, self.dtype, len(shape), _i64(shape), ctypes.c_void_p(buf.data_ptr()),
+                              ctypes.byref(h)), "tci_wrap")
+        self.h = h
+
+    @classmethod
+    def from_torch(cls, ctx, t: torch.Tensor):
+        return cls(ctx, t.to(ctx.torch_device).contiguous())
+
+    @classmethod
+    def from_numpy(cls, ctx, a: np.ndarray, dtype: int | None = None):
+        t = torch.from_numpy(np.ascontiguousarray(a))
+        if dtype is not None:
+            t = t.to(TORCH_OF[dtype])
+        return cls(ctx, t.to(ctx.torch_device))
+
+    @classmethod
+    def empty(cls, ctx, dtype: int, capacity: int):
+        """Output handle with room for `capacity` elements (shape set by the library)."""
+        buf = torch.empty(max(1, int(capacity)), dtype=TORCH_OF[dtype], device=ctx.torch_device)
+        return cls(ctx, buf, shape=[buf.numel()])
+
+    def shape(self):
+        n = ctypes.c_int()
+        _check(lib().tci_order(self.ctx.h, self.h, ctypes.byref(n)), "tci_order")
+        out = (ctypes.c_int64 * max(1, n.value))()
+        _check(lib().tci_shape(self.ctx.h, self.h, out, n.value), "tci_shape")
+        return tuple(out[i] for i in range(n.value))
+
+    def current_dtype(self):
+        d = ctypes.c_int()
+        _check(lib().tci_dtype_of(self.ctx.h, self.h, ctypes.byref(d)), "tci_dtype_of")
+        return d.value
+
+    def torch(self) -> torch.Tensor:
+        """View of the data with the current shape (shares memory)."""
+        shp = self.shape()
+        n = int(np.prod(shp)) if shp else 1
+        dt = TORCH_OF[self.current_dtype()]
+        ptr = ctypes.c_void_p()
+        _check(lib().tci_data_ptr(self.ctx.h, self.h, ctypes.byref(ptr)), "tci_data_ptr")
+        if ptr.value == self.buf.data_ptr() and dt == self.buf.dtype and n <= self.buf.numel():
+            return self.buf.view(-1)[:n].view(shp)
+        raise RuntimeError("tensor storage is not the wrapped torch buffer")
+
+    def numpy(self) -> np.ndarray:
+        torch.cuda.synchronize(self.ctx.torch_device)
+        return self.torch().cpu().numpy()
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().tci_destroy(self.ctx.h, self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- operations
+def version() -> str:
+    return lib().tci_version().decode()
+
+
+def norm(ctx: Context, t: Tensor) -> float:
+    out = ctypes.c_double()
+    _check(lib().tci_norm(ctx.h, t.h, ctypes.byref(out)), "tci_norm")
+    return out.value
+
+
+def normalize(ctx: Context, t: Tensor) -> float:
+    out = ctypes.c_double()
+    _check(lib().tci_normalize(ctx.h, t.h, ctypes.byref(out)), "tci_normalize")
+    return out.value
+
+
+def transpose(ctx: Context, t: Tensor, perm, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, t.dtype, int(np.prod(t.shape())))
+    _check(lib().tci_transpose(ctx.h, t.h, _i32(perm), out.h), "tci_transpose")
+    return out
+
+
+def reshape(ctx: Context, t: Tensor, shape, out: Tensor | None = None) -> Tensor:
+    out = t if out is None else out
+    _check(lib().tci_reshape(ctx.h, t.h, len(shape), _i64(shape), out.h), "tci_reshape")
+    return out
+
+
+def _labels(lab):
+    if isinstance(lab, str):
+        return [ord(c) for c in lab]
+    return [int(x) for x in lab]
+
+
+def contract(ctx: Context, a: Tensor, la, b: Tensor, lb, lc, out: Tensor | None = None) -> Tensor:
+    la, lb, lc = _labels(la), _labels(lb), _labels(lc)
+    if out is None:
+        dims = dict(zip(la, a.shape()))
+        dims.update(zip(lb, b.shape()))
+        cap = int(np.prod([dims.get(x, 1) for x in lc])) if lc else 1
+        out = Tensor.empty(ctx, a.dtype, cap)
+    _check(lib().tci_contract(ctx.h, a.h, _i32(la), len(la), b.h, _i32(lb), len(lb), out.h, _i32(lc), len(lc)),
+           "tci_contract")
+    return out
+
+
+def trunc_svd(ctx: Context, a: Tensor, k_rows: int, chi_min: int, chi_max: int, target: float = 0.0,
+              s_min: float = 0.0):
+    shp = a.shape()
+    rows = int(np.prod(shp[:k_rows]))
+    cols = int(np.prod(shp[k_rows:]))
+    kap = min(rows, cols, chi_max)
+    u = Tensor.empty(ctx, a.dtype, rows * kap)
+    vh = Tensor.empty(ctx, a.dtype, kap * cols)
+    s = Tensor.empty(ctx, F64 if a.dtype in (F64, C128) else F32, kap)
+    err = ctypes.c_double()
+    _check(lib().tci_trunc_svd(ctx.h, a.h, k_rows, u.h, s.h, vh.h, ctypes.byref(err), chi_min, chi_max, target,
+                               s_min), "tci_trunc_svd")
+    return u, s, vh, err.value
+
+
+def svd(ctx: Context, a: Tensor, k_rows: int):
+    shp = a.shape()
+    rows = int(np.prod(shp[:k_rows]))
+    cols = int(np.prod(shp[k_rows:]))
+    kap = min(rows, cols)
+    u = Tensor.empty(ctx, a.dtype, rows * kap)
+    vh = Tensor.empty(ctx, a.dtype, kap * cols)
+    s = Tensor.empty(ctx, F64 if a.dtype in (F64, C128) else F32, kap)
+    _check(lib().tci_svd(ctx.h, a.h, k_rows, u.h, s.h, vh.h), "tci_svd")
+    return u, s, vh
+
+
+def qr(ctx: Context, a: Tensor, k_rows: int):
+    shp = a.shape()
+    rows = int(np.prod(shp[:k_rows]))
+    cols = int(np.prod(shp[k_rows:]))
+    rho = min(rows, cols)
+    q = Tensor.empty(ctx, a.dtype, rows * rho)
+    r = Tensor.empty(ctx, a.dtype, rho * cols)
+    _check(lib().tci_qr(ctx.h, a.h, k_rows, q.h, r.h), "tci_qr")
+    return q, r
+
+
+def eigh(ctx: Context, a: Tensor):
+    n = a.shape()[0]
+    w = Tensor.empty(ctx, F64, n)
+    v = Tensor.empty(ctx, a.dtype, n * n)
+    _check(lib().tci_eigh(ctx.h, a.h, w.h, v.h), "tci_eigh")
+    return w, v
+
+
+def close(ctx: Context, a: Tensor, b: Tensor, eps: float) -> bool:
+    r = ctypes.c_int()
+    _check(lib().tci_close(ctx.h, a.h, b.h, eps, ctypes.byref(r)), "tci_close")
+    return bool(r.value)
+
+
+def update_params(**kw) -> UpdateParams:
+    p = UpdateParams()
+    lib().tci_update_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, params: UpdateParams):
+    """Returns (A_out, s_out, B_out, infos) lists; outputs are library-sized views."""
+    n = len(A)
+    P = ctypes.c_void_p * n
+    chil, d, chim = A[0].shape()
+    chir = B[0].shape()[2]
+    kap = min(chil * d, d * chir, params.chi_max)
+    dt = A[0].dtype
+    A_out = [Tensor.empty(ctx, dt, chil * d * kap) for _ in range(n)]
+    B_out = [Tensor.empty(ctx, dt, kap * d * chir) for _ in range(n)]
+    s_out = [Tensor.empty(ctx, F64, kap) for _ in range(n)]
+    infos = (UpdateInfo * n)()
+    g = P(*[x.h.value if x is not None else None for x in gates]) if gates is not None else None
+    _check(lib().tci_two_site_update_batched(ctx.h, n, P(*[x.h.value for x in A]), P(*[x.h.value for x in B]),
+                                             g, ctypes.byref(params), P(*[x.h.value for x in A_out]),
+                                             P(*[x.h.value for x in s_out]), P(*[x.h.value for x in B_out]),
+                                             infos), "tci_two_site_update_batched")
+    return A_out, s_out, B_out, list(infos)
+
+
+def heff_matvec(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, x: Tensor,
+                y: Tensor | None = None) -> Tensor:
+    if y is None:
+        y = Tensor.empty(ctx, x.dtype, int(np.prod(x.shape())))
+    _check(lib().tci_heff_matvec(ctx.h, L.h, W1.h, W2.h, R.h, x.h, y.h), "tci_heff_matvec")
+    return y
+
+
+def lanczos_ground(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, theta: Tensor,
+                   n_matvec: int = 20) -> float:
+    e = ctypes.c_double()
+    _check(lib().tci_lanczos_ground(ctx.h, L.h, W1.h, W2.h, R.h, theta.h, n_matvec, ctypes.byref(e)),
+           "tci_lanczos_ground")
+    return e.value
