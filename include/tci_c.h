@@ -73,6 +73,7 @@ typedef enum {
 
 typedef struct tci_context_s* tci_context;
 typedef struct tci_tensor_s* tci_tensor;
+typedef struct tci_sketch_model_s* tci_sketch_model;
 
 /* ------------------------------------------------------------------ */
 /* Version and errors (Spec, miscellaneous routines: version)          */
@@ -290,6 +291,8 @@ typedef struct {
   uint64_t seed;            /* Philox key of the sketch */
   double cert_tol;          /* randomized acceptance: max residual <= cert_tol * s_1 (0: 1e-7) */
   void* sketch_model;       /* tci_sketch_model for TCI_SVD_LEARNED */
+  const tci_tensor* prev_spectra; /* TCI_SVD_LEARNED: per update, the bond's spectrum before the
+                                     update (F64 vector, descending); indexed like A / theta */
 } tci_update_params;
 
 typedef struct {
@@ -322,6 +325,15 @@ tci_status tci_two_site_update_batched(tci_context ctx, int n, const tci_tensor*
                                        tci_tensor* s_out, tci_tensor* B_out,
                                        tci_update_info* infos);
 
+/* The second half of the update for given two-site tensors: theta[i] of
+ * shape (chi_l, d, d, chi_r) (all i the same shape and dtype) is split by
+ * trunc_svd with k_rows = 2 under params (plain SVD), s renormalised and
+ * written back as in tci_two_site_update_batched.  Used after the Lanczos
+ * step of a DMRG update.  Synchronous. */
+tci_status tci_split_batched(tci_context ctx, int n, const tci_tensor* theta,
+                             const tci_update_params* params, tci_tensor* A_out,
+                             tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos);
+
 /* Effective-Hamiltonian matvec of the two-site DMRG update:
  * y[a,s1,s2,b] = sum L[a,w,a'] W1[w,w',s1,s1'] W2[w',w'',s2,s2'] R[b,w'',b']
  *                    x[a',s1',s2',b'].
@@ -338,6 +350,69 @@ tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_ten
  * kept in FP64.  Synchronous. */
 tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
                               tci_tensor R, tci_tensor theta_inout, int n_matvec, double* energy);
+
+/* ------------------------------------------------------------------ */
+/* Sketch-rank model for TCI_SVD_LEARNED                                */
+/* ------------------------------------------------------------------ */
+/* A perceptron 35 -> 128 -> 128 -> 1 with exact GELU that predicts
+ * y = log2 chi*(eps) of a bond from its features
+ *   [log2(chi_max)/11, d/4, -log10(eps)/16, 32 clamped log10 quantiles
+ *    q_t = clamp(log10(s_j/s_0)/16, -1, 0), j = floor((t+1/2)/32 (len-1))]
+ * of the bond's previous spectrum s.  The update uses the sketch rank
+ * k = min(n, 32 ceil((2^y 1.1 + 16)/32)) and the plain truncated SVD when
+ * y > log2(chi_max).  Parameters are FP32, flat: W1 (128x35), b1, W2
+ * (128x128), b2, W3 (1x128), b3.  All data pointers below are device
+ * pointers unless marked host. */
+
+/* New model with He-uniform weights from Philox4x32-10 (key seed, stream 7),
+ * zero biases and zero Adam state. */
+tci_status tci_sketch_model_create(tci_context ctx, uint64_t seed, tci_sketch_model* out);
+tci_status tci_sketch_model_destroy(tci_context ctx, tci_sketch_model m);
+/* Number of parameters (21249). */
+int64_t tci_sketch_model_nparams(void);
+/* Copy the flat parameters to / from host memory (n must equal nparams). */
+tci_status tci_sketch_model_get_params(tci_context ctx, tci_sketch_model m, float* host, int64_t n);
+tci_status tci_sketch_model_set_params(tci_context ctx, tci_sketch_model m, const float* host, int64_t n);
+/* Raw binary file: "TCISKM1\0", int32 count, count float32 parameters. */
+tci_status tci_sketch_model_save(tci_context ctx, tci_sketch_model m, const char* path);
+tci_status tci_sketch_model_load(tci_context ctx, const char* path, tci_sketch_model* out);
+/* y[i] = model(X[i, 0:35]) for i < n (X row-major n x 35).  Asynchronous. */
+tci_status tci_sketch_predict(tci_context ctx, tci_sketch_model m, const float* X, int n, float* y);
+/* Gradient of the mean pinball loss (tau = 0.9, targets T) w.r.t. the flat
+ * parameters into grad (device, nparams); *loss (host, may be NULL). */
+tci_status tci_sketch_grads(tci_context ctx, tci_sketch_model m, const float* X, const float* T, int n,
+                            float* grad, float* loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on a batch. */
+tci_status tci_sketch_train_step(tci_context ctx, tci_sketch_model m, const float* X, const float* T,
+                                 int n, float lr, float* loss);
+/* Features of n bonds: spectra s (row i at s + i*ss, length len[i]). */
+tci_status tci_sketch_features(tci_context ctx, const double* s, int64_t ss, const int32_t* len, int n,
+                               int chi_max, int d, double eps, float* X);
+
+/* Raw Philox4x32-10 blocks (key seed, counter (first + i, stream, 0)) into
+ * out[4i .. 4i+3] (device), for checking the generator against published
+ * vectors. */
+tci_status tci_philox_blocks(tci_context ctx, uint64_t seed, uint32_t stream, uint64_t first, int64_t n,
+                             uint32_t* out);
+
+/* ------------------------------------------------------------------ */
+/* Kernel timing (instrumentation; not part of the paper's API)         */
+/* ------------------------------------------------------------------ */
+
+/* Start (enable != 0) or stop recording a HIP event pair around every
+ * matrix-core GEMM and tridiagonal matrix-vector launch, on the stream the
+ * kernel runs on.  Either call clears the records.  Process-wide. */
+tci_status tci_profile_enable(tci_context ctx, int enable);
+
+/* Sum over the recorded launches with tag `tag` ("<call site>:<class>",
+ * e.g. "heff_L:c64_bf16x3", "gemm:c128_fp64", "gemm:hemv"): number of
+ * launches, total event time in ms and total algorithmic work (flops for
+ * GEMMs, bytes for the matrix-vector product).  Synchronises the stream. */
+tci_status tci_profile_query(tci_context ctx, const char* tag, int64_t* count, double* total_ms,
+                             double* work);
+
+/* Distinct recorded tags separated by newlines, NUL-terminated in buf. */
+tci_status tci_profile_tags(tci_context ctx, char* buf, int cap);
 
 #ifdef __cplusplus
 }

@@ -24,13 +24,13 @@ import numpy as np
 from . import eigh, philox_normal, svd_matrix, trunc_rule
 
 
-def gaussian_sketch(n: int, k: int, seed: int, complex_: bool) -> np.ndarray:
+def gaussian_sketch(n: int, k: int, seed: int, complex_: bool, stream: int = 0) -> np.ndarray:
     """Omega[i, j]: real case z[i*k+j]; complex case (z[2t] + i z[2t+1]) / sqrt 2
-    with t = i*k + j, z the Philox normal stream (stream id 0)."""
+    with t = i*k + j, z the Philox normal stream `stream` under key `seed`."""
     if complex_:
-        z = philox_normal(seed, 0, 2 * n * k).reshape(n * k, 2)
+        z = philox_normal(seed, stream, 2 * n * k).reshape(n * k, 2)
         return ((z[:, 0] + 1j * z[:, 1]) / np.sqrt(2.0)).reshape(n, k)
-    return philox_normal(seed, 0, n * k).reshape(n, k).astype(np.complex128)
+    return philox_normal(seed, stream, n * k).reshape(n, k).astype(np.complex128)
 
 
 def cholesky_drop(g, tau=1e-12):
@@ -95,14 +95,15 @@ def rule_with_total(sig, total, chi_min, chi_max, target, s_min):
 
 
 def randomized_tsvd(theta, k, q=2, seed=0, chi_min=1, chi_max=None, target=0.0,
-                    s_min=0.0, cert=1e-7):
+                    s_min=0.0, cert=1e-7, stream=0, complex_=None):
     """Returns dict(u, s, vh, chi, err, accepted, residual, sig_all)."""
     theta = np.asarray(theta, dtype=np.complex128)
     m, n = theta.shape
     if chi_max is None:
         chi_max = min(m, n)
-    complex_ = bool(np.any(theta.imag != 0))
-    omega = gaussian_sketch(n, k, seed, complex_)
+    if complex_ is None:
+        complex_ = bool(np.any(theta.imag != 0))
+    omega = gaussian_sketch(n, k, seed, complex_, stream)
     y = theta @ omega
     for _ in range(q):
         z = theta.conj().T @ chol_qr2(y)
@@ -125,9 +126,9 @@ def randomized_tsvd(theta, k, q=2, seed=0, chi_min=1, chi_max=None, target=0.0,
 
 
 def tsvd_with_fallback(theta, k, q=2, seed=0, chi_min=1, chi_max=None, target=0.0,
-                       s_min=0.0, cert=1e-7):
+                       s_min=0.0, cert=1e-7, stream=0, complex_=None):
     """Randomized first; the plain truncated SVD when it is not accepted."""
-    r = randomized_tsvd(theta, k, q, seed, chi_min, chi_max, target, s_min, cert)
+    r = randomized_tsvd(theta, k, q, seed, chi_min, chi_max, target, s_min, cert, stream, complex_)
     if r["accepted"]:
         r["fallback"] = False
         return r

@@ -19,6 +19,7 @@
 #include "linalg.hpp"
 #include "runtime.hpp"
 #include "vecops.hpp"
+#include "prof.hpp"
 
 namespace tci {
 
@@ -73,14 +74,17 @@ static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, 
   const int kw = p.w * p.d * p.d;
   hipStream_t s = ctx->stream;
   // X1 = L' x'
+  ProfTag t1("heff_L");
   GemmArgs g1 = gemm_args(p.chil * p.w, p.d * p.d * p.chir, p.chil, OP_N, OP_N, p.L, p.chil, x, p.d * p.d * p.chir,
                           p.X1, p.d * p.d * p.chir);
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g1, s));
   // X2[a] = W12^T X1[a]
+  ProfTag t2("heff_W12");
   GemmArgs g2 = gemm_args(kw, p.chir, kw, OP_T, OP_N, p.W12, kw, p.X1, p.chir, p.X2, p.chir);
   g2.sA = 0; g2.sB = (long long)kw * p.chir; g2.sC = (long long)kw * p.chir; g2.batch = p.chil;
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g2, s));
   // y = X2' R'^T
+  ProfTag t3("heff_R");
   GemmArgs g3 = gemm_args(p.chil * p.d * p.d, p.chir, p.w * p.chir, OP_N, OP_T, p.X2, (long long)p.w * p.chir, p.R,
                           (long long)p.w * p.chir, y, p.chir);
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g3, s));

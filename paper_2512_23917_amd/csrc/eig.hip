@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "gemm.hpp"
 #include "eig.hpp"
+#include "prof.hpp"
 
 namespace tci {
 
@@ -222,6 +223,8 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
                          p > 0 ? i - 1 : -1, i, j0);
       if (i + 1 < n) {
         dim3 grid((n - i - 1 + 15) / 16, batch);
+        // algorithmic bytes: the trailing matrix read once per problem
+        ProfScope ps(s, (double)(n - i - 1) * (n - i - 1) * sizeof(T) * batch, "hemv");
         hipLaunchKernelGGL(tri_hemv_kernel<T>, grid, dim3(256), 0, s, a, i);
       }
     }

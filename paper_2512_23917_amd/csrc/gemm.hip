@@ -16,6 +16,7 @@
 // problem in device memory so ragged batches run in one launch.
 #include "common.hpp"
 #include "gemm.hpp"
+#include "prof.hpp"
 
 namespace tci {
 
@@ -533,6 +534,15 @@ static hipError_t launch(K kern, const GemmArgs& a, int BM, int BN, hipStream_t 
 
 hipError_t gemm(int dtype, int prec, const GemmArgs& a, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return hipSuccess;
+  // algorithmic flops: 8 per complex multiply-add (four real products), 2 per
+  // real one; split-BF16x3 executes three bf16 products per multiply-add
+  const bool cplx = dtype == C64 || dtype == C128;
+  double flops = (cplx ? 8.0 : 2.0) * a.m * (double)a.n * a.k * a.batch;
+  if ((dtype == C64 || dtype == F32) && prec == PREC_BF16X3) flops *= 3.0;
+  const char* cls = dtype == C128 ? "c128_fp64" : dtype == F64 ? "f64_fp64"
+                  : prec == PREC_BF16X3 ? (dtype == C64 ? "c64_bf16x3" : "f32_bf16x3")
+                  : (dtype == C64 ? "c64_fp32" : "f32_fp32");
+  ProfScope ps(s, flops, cls);
   if (a.k <= 0) {
     // empty sum: C = beta * C
     return gemm_scale_c(dtype, a, s);

@@ -211,6 +211,150 @@ static tci_status store_as(tci_context ctx, int wdt, const void* src, tci_tensor
   return TCI_OK;
 }
 
+// Write the factors of the local problems listed in `idx` (local index ->
+// output slot) from a TsvdOut: A' = U (s), B' = (s) V^H with s renormalised.
+static tci_status store_outputs(tci_context ctx, int dt, int wdt, int chil, int d, int chir, const TsvdOut& o,
+                                const std::vector<int>& idx, const tci_update_params& p, tci_tensor* A_out,
+                                tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos,
+                                const std::vector<double>* resid, bool fallback, const std::vector<int>* krank) {
+  hipStream_t s = ctx->stream;
+  const int m = chil * d, n = d * chir, nb = (int)idx.size();
+  const size_t wes = elem_bytes(wdt);
+  const int kz = o.kz;
+  ARENA(Ucmp, char, wes * (size_t)m * kz * nb);
+  ARENA(Vcmp, char, wes * (size_t)kz * n * nb);
+  const bool right = p.direction == TCI_DIR_RIGHT;
+  TCI_CHECK_HIP(compact_columns(wdt, o.U, kz, (long long)m * kz, Ucmp, (long long)m * kz, m, kz, o.chi,
+                                right ? o.sn : nullptr, o.kmax, nb, s));
+  TCI_CHECK_HIP(scale_rows(wdt, o.Vh, (long long)kz * n, Vcmp, (long long)kz * n, n, kz, o.chi,
+                           right ? nullptr : o.sn, o.kmax, nb, s));
+  for (int i = 0; i < nb; ++i) {
+    const int g = idx[i];
+    const int64_t chi = o.chi_h[i];
+    const int64_t ash[3] = {chil, d, chi}, bsh[3] = {chi, d, chir}, ssh[1] = {chi};
+    TCI_TRY(ensure_shape(ctx, A_out[g], dt, 3, ash));
+    TCI_TRY(ensure_shape(ctx, B_out[g], dt, 3, bsh));
+    TCI_TRY(ensure_shape(ctx, s_out[g], F64, 1, ssh));
+    TCI_TRY(store_as(ctx, wdt, Ucmp + wes * (size_t)m * kz * i, A_out[g]));
+    TCI_TRY(store_as(ctx, wdt, Vcmp + wes * (size_t)kz * n * i, B_out[g]));
+    TCI_CHECK_HIP(hipMemcpyAsync(s_out[g]->data, o.sn + (size_t)o.kmax * i, sizeof(double) * chi,
+                                 hipMemcpyDeviceToDevice, s));
+    if (infos) {
+      tci_update_info& inf = infos[g];
+      std::memset(&inf, 0, sizeof(inf));
+      inf.chi = chi;
+      inf.trunc_err = o.err_h[i];
+      inf.discarded_abs = o.disc_h[i];
+      inf.norm2 = o.total_h[i];
+      inf.used_fallback = fallback ? 1 : 0;
+      inf.sketch_rank = krank ? (*krank)[g] : 0;
+      inf.max_residual = resid ? (*resid)[i] : 0.0;
+    }
+  }
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  return TCI_OK;
+}
+
+// Gather problems `idx` of a strided batch (stride elems) into a new buffer.
+static tci_status gather(tci_context ctx, int dt, const void* src, long long stride, const std::vector<int>& idx,
+                         const void** out) {
+  const size_t es = elem_bytes(dt);
+  char* dst = static_cast<char*>(ctx->arena.get(es * (size_t)stride * idx.size()));
+  if (!dst) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  for (size_t i = 0; i < idx.size(); ++i)
+    TCI_CHECK_HIP(hipMemcpyAsync(dst + es * stride * i, static_cast<const char*>(src) + es * stride * idx[i],
+                                 es * stride, hipMemcpyDeviceToDevice, ctx->stream));
+  *out = dst;
+  return TCI_OK;
+}
+
+// trunc_svd of nb matrices theta ((chil*d) x (d*chir)): th_lo in the storage
+// dtype dt, thw its FP64 working copy (the same pointer when dt is FP64);
+// plain, randomized or learned per params; then renormalised s and the
+// write-back.  `first` is the global index of problem 0 (sketch stream id).
+static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int chil, int d, int chir,
+                                  const void* th_lo, const void* thw, const tci_update_params& p, int first,
+                                  tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos) {
+  const int m = chil * d, n = d * chir, ng = std::min(m, n);
+  TruncParams tp{(int)std::min<int64_t>(p.chi_min, ng), (int)std::min<int64_t>(p.chi_max, ng), p.target_trunc_err,
+                 p.s_min};
+  if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
+  const long long smn = (long long)m * n;
+  std::vector<int> plain_idx, sk_idx, kvec(nb, 0);
+  if (p.svd_mode == TCI_SVD_PLAIN) {
+    for (int i = 0; i < nb; ++i) plain_idx.push_back(i);
+  } else {
+    TCI_TRY(choose_sketch_ranks(ctx, p, nb, first, ng, tp.chi_max, d, kvec));
+    for (int i = 0; i < nb; ++i) {
+      if (kvec[i] > 0 && kvec[i] < ng) sk_idx.push_back(i);
+      else plain_idx.push_back(i);
+    }
+  }
+  if (!sk_idx.empty()) {
+    const void* lo = th_lo;
+    const void* hi = thw;
+    if ((int)sk_idx.size() != nb) {
+      TCI_TRY(gather(ctx, dt, th_lo, smn, sk_idx, &lo));
+      hi = lo;
+      if (thw != th_lo) TCI_TRY(gather(ctx, wdt, thw, smn, sk_idx, &hi));
+    }
+    std::vector<int> ks;
+    std::vector<uint32_t> streams;
+    for (int i : sk_idx) {
+      ks.push_back(kvec[i]);
+      streams.push_back((uint32_t)(first + i));
+    }
+    TsvdOut o;
+    std::vector<double> resid;
+    const int q = p.power_iters < 0 ? 2 : p.power_iters;
+    const int prec = is_double(dt) ? PREC_FP64 : p.precision;
+    TCI_TRY(sketch_run(ctx, dt, wdt, prec, (int)sk_idx.size(), m, n, lo, hi, tp, ks, q, p.seed, streams, o, resid));
+    const double cert = p.cert_tol > 0 ? p.cert_tol : 1e-7;
+    std::vector<int> acc_local, acc_global;
+    for (size_t i = 0; i < sk_idx.size(); ++i) {
+      if (o.err_h[i] <= p.target_trunc_err && resid[i] <= cert) {
+        acc_local.push_back((int)i);
+        acc_global.push_back(sk_idx[i]);
+      } else {
+        plain_idx.push_back(sk_idx[i]);
+      }
+    }
+    if (acc_local.size() == sk_idx.size()) {
+      TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, acc_global, p, A_out, s_out, B_out, infos, &resid, false,
+                            &kvec));
+    } else if (!acc_local.empty()) {
+      // store the accepted ones one at a time (their TsvdOut rows are strided)
+      for (size_t a = 0; a < acc_local.size(); ++a) {
+        TsvdOut one = o;
+        const int i = acc_local[a];
+        const size_t ew = elem_bytes(wdt);
+        one.U = static_cast<char*>(o.U) + ew * (size_t)m * o.kz * i;
+        one.Vh = static_cast<char*>(o.Vh) + ew * (size_t)o.kz * n * i;
+        one.chi = o.chi + i;
+        one.sn = o.sn + (size_t)o.kmax * i;
+        one.s = o.s + (size_t)o.kmax * i;
+        one.chi_h = {o.chi_h[i]};
+        one.err_h = {o.err_h[i]};
+        one.disc_h = {o.disc_h[i]};
+        one.total_h = {o.total_h[i]};
+        std::vector<double> r1 = {resid[i]};
+        TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, one, {acc_global[a]}, p, A_out, s_out, B_out, infos, &r1,
+                              false, &kvec));
+      }
+    }
+  }
+  if (!plain_idx.empty()) {
+    std::sort(plain_idx.begin(), plain_idx.end());
+    const void* hi = thw;
+    if ((int)plain_idx.size() != nb) TCI_TRY(gather(ctx, wdt, thw, smn, plain_idx, &hi));
+    TsvdOut o;
+    TCI_TRY(tsvd_run(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
+    TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, plain_idx, p, A_out, s_out, B_out, infos, nullptr,
+                          p.svd_mode != TCI_SVD_PLAIN, &kvec));
+  }
+  return TCI_OK;
+}
+
 }  // namespace tci
 
 using namespace tci;
@@ -409,7 +553,6 @@ tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tens
   const int prec = p.precision;
   if (is_double(dt) != (prec == TCI_PREC_FP64))
     TCI_RET(TCI_ERR_DTYPE, "FP64 precision needs F64/C128 tensors, mixed precisions F32/C64");
-  if (p.svd_mode != TCI_SVD_PLAIN) return tci_two_site_update_sketched(ctx, nupd, A, B, gates, &p, A_out, s_out, B_out, infos);
   Trace tr(ctx, "two_site_update_batched", std::to_string(nupd) + " x " + std::to_string(chil) + "," +
                                                std::to_string(d) + "," + std::to_string(chir));
   const int m = (int)(chil * d), n = (int)(d * chir), K = (int)chim;
@@ -464,40 +607,52 @@ tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tens
       TCI_CHECK_HIP(convert(dt, th, wdt, tw, smn * nb, s));
       thw = tw;
     }
-    TruncParams tp{(int)std::min<int64_t>(p.chi_min, std::min(m, n)), (int)std::min<int64_t>(p.chi_max, std::min(m, n)),
-                   p.target_trunc_err, p.s_min};
-    if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
-    TsvdOut o;
-    TCI_TRY(tsvd_run(ctx, wdt, nb, m, n, thw, tp, o));
-    // write-back
-    const int kz = o.kz;
-    ARENA(Ucmp, char, wes * (size_t)m * kz * nb);
-    ARENA(Vcmp, char, wes * (size_t)kz * n * nb);
-    const bool right = p.direction == TCI_DIR_RIGHT;
-    TCI_CHECK_HIP(compact_columns(wdt, o.U, kz, (long long)m * kz, Ucmp, (long long)m * kz, m, kz, o.chi,
-                                  right ? o.sn : nullptr, o.kmax, nb, s));
-    TCI_CHECK_HIP(scale_rows(wdt, o.Vh, (long long)kz * n, Vcmp, (long long)kz * n, n, kz, o.chi,
-                             right ? nullptr : o.sn, o.kmax, nb, s));
-    for (int i = 0; i < nb; ++i) {
-      const int64_t chi = o.chi_h[i];
-      const int64_t ash[3] = {chil, d, chi}, bsh[3] = {chi, d, chir}, ssh[1] = {chi};
-      TCI_TRY(ensure_shape(ctx, A_out[c0 + i], dt, 3, ash));
-      TCI_TRY(ensure_shape(ctx, B_out[c0 + i], dt, 3, bsh));
-      TCI_TRY(ensure_shape(ctx, s_out[c0 + i], F64, 1, ssh));
-      TCI_TRY(store_as(ctx, wdt, Ucmp + wes * (size_t)m * kz * i, A_out[c0 + i]));
-      TCI_TRY(store_as(ctx, wdt, Vcmp + wes * (size_t)kz * n * i, B_out[c0 + i]));
-      TCI_CHECK_HIP(hipMemcpyAsync(s_out[c0 + i]->data, o.sn + (size_t)o.kmax * i, sizeof(double) * chi,
-                                   hipMemcpyDeviceToDevice, s));
-      if (infos) {
-        tci_update_info& inf = infos[c0 + i];
-        std::memset(&inf, 0, sizeof(inf));
-        inf.chi = chi;
-        inf.trunc_err = o.err_h[i];
-        inf.discarded_abs = o.disc_h[i];
-        inf.norm2 = o.total_h[i];
-      }
-    }
+    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, th, thw, p, c0, A_out + c0,
+                            s_out + c0, B_out + c0, infos ? infos + c0 : nullptr));
     TCI_CHECK_HIP(hipStreamSynchronize(s));
+  }
+  return TCI_OK;
+}
+
+tci_status tci_split_batched(tci_context ctx, int nupd, const tci_tensor* theta, const tci_update_params* params,
+                             tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos) {
+  if (!ctx || nupd < 1 || !theta || !A_out || !s_out || !B_out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  tci_update_params p;
+  if (params) p = *params;
+  else tci_update_params_default(&p);
+  if (p.chi_min < 1 || p.chi_max < 1 || p.chi_min > p.chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
+  const tci_tensor t0 = theta[0];
+  if (!t0 || t0->order != 4) TCI_RET(TCI_ERR_SHAPE, "theta must be order 4 (chi_l, d, d, chi_r)");
+  const int dt = t0->dtype;
+  const int64_t chil = t0->shape[0], d = t0->shape[1], chir = t0->shape[3];
+  if (t0->shape[2] != d) TCI_RET(TCI_ERR_SHAPE, "theta physical dimensions differ");
+  for (int i = 0; i < nupd; ++i) {
+    if (!theta[i] || !A_out[i] || !s_out[i] || !B_out[i]) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null tensor");
+    if (theta[i]->dtype != dt || theta[i]->order != 4) TCI_RET(TCI_ERR_DTYPE, "mixed dtypes in the batch");
+    for (int k = 0; k < 4; ++k)
+      if (theta[i]->shape[k] != t0->shape[k]) TCI_RET(TCI_ERR_SHAPE, "all thetas of a batch must have one shape");
+  }
+  Trace tr(ctx, "split_batched", std::to_string(nupd) + " x " + std::to_string(chil) + "," + std::to_string(chir));
+  const int wdt = work_dtype(dt);
+  const size_t es = elem_bytes(dt), wes = elem_bytes(wdt);
+  const long long smn = (long long)chil * d * d * chir;
+  hipStream_t s = ctx->stream;
+  const int maxb = p.max_batch > 0 ? p.max_batch : 64;
+  for (int c0 = 0; c0 < nupd; c0 += maxb) {
+    const int nb = std::min(maxb, nupd - c0);
+    ctx->arena.reset();
+    ARENA(tl, char, es * (size_t)smn * nb);
+    for (int i = 0; i < nb; ++i)
+      TCI_CHECK_HIP(hipMemcpyAsync(tl + es * smn * i, theta[c0 + i]->data, es * smn, hipMemcpyDeviceToDevice, s));
+    const void* tw = tl;
+    if (wdt != dt) {
+      ARENA(t64, char, wes * (size_t)smn * nb);
+      TCI_CHECK_HIP(convert(dt, tl, wdt, t64, smn * nb, s));
+      tw = t64;
+    }
+    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, tl, tw, p, c0, A_out + c0, s_out + c0,
+                            B_out + c0, infos ? infos + c0 : nullptr));
   }
   return TCI_OK;
 }

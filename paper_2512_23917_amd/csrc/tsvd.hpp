@@ -30,8 +30,12 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
 
 }  // namespace tci
 
-extern "C" tci_status tci_two_site_update_sketched(tci_context ctx, int nupd, const tci_tensor* A,
-                                                   const tci_tensor* B, const tci_tensor* gates,
-                                                   const tci_update_params* p, tci_tensor* A_out,
-                                                   tci_tensor* s_out, tci_tensor* B_out,
-                                                   tci_update_info* infos);
+namespace tci {
+// Randomized truncated SVD of nb problems (see sketch.cpp).
+tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int m, int n, const void* th_lo,
+                      const void* th64, const TruncParams& tp, const std::vector<int>& kvec, int q, uint64_t seed,
+                      const std::vector<uint32_t>& streams, TsvdOut& out, std::vector<double>& resid_h);
+// Sketch rank per problem (0 = plain SVD) for TCI_SVD_RANDOMIZED / TCI_SVD_LEARNED.
+tci_status choose_sketch_ranks(tci_context ctx, const tci_update_params& p, int nb, int first, int ng, int chi_max,
+                               int d, std::vector<int>& kvec);
+}  // namespace tci

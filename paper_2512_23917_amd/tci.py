@@ -44,7 +44,7 @@ class UpdateParams(ctypes.Structure):
                 ("svd_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("cert_tol", ctypes.c_double),
-                ("sketch_model", ctypes.c_void_p)]
+                ("sketch_model", ctypes.c_void_p), ("prev_spectra", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -110,8 +110,24 @@ def lib():
         "tci_update_params_default": (None, [P(UpdateParams)]),
         "tci_two_site_update_batched": (i32, [p, ctypes.c_int, P(p), P(p), P(p), P(UpdateParams),
                                               P(p), P(p), P(p), P(UpdateInfo)]),
+        "tci_split_batched": (i32, [p, ctypes.c_int, P(p), P(UpdateParams), P(p), P(p), P(p), P(UpdateInfo)]),
         "tci_heff_matvec": (i32, [p, p, p, p, p, p, p]),
         "tci_lanczos_ground": (i32, [p, p, p, p, p, p, ctypes.c_int, P(f64)]),
+        "tci_sketch_model_create": (i32, [p, ctypes.c_uint64, P(p)]),
+        "tci_sketch_model_destroy": (i32, [p, p]),
+        "tci_sketch_model_nparams": (i64, []),
+        "tci_sketch_model_get_params": (i32, [p, p, p, i64]),
+        "tci_sketch_model_set_params": (i32, [p, p, p, i64]),
+        "tci_sketch_model_save": (i32, [p, p, ctypes.c_char_p]),
+        "tci_sketch_model_load": (i32, [p, ctypes.c_char_p, P(p)]),
+        "tci_sketch_predict": (i32, [p, p, p, ctypes.c_int, p]),
+        "tci_sketch_grads": (i32, [p, p, p, p, ctypes.c_int, p, P(ctypes.c_float)]),
+        "tci_sketch_train_step": (i32, [p, p, p, p, ctypes.c_int, ctypes.c_float, P(ctypes.c_float)]),
+        "tci_sketch_features": (i32, [p, p, i64, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, f64, p]),
+        "tci_philox_blocks": (i32, [p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, i64, p]),
+        "tci_profile_enable": (i32, [p, ctypes.c_int]),
+        "tci_profile_query": (i32, [p, ctypes.c_char_p, P(i64), P(f64), P(f64)]),
+        "tci_profile_tags": (i32, [p, ctypes.c_char_p, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -334,6 +350,14 @@ def close(ctx: Context, a: Tensor, b: Tensor, eps: float) -> bool:
     return bool(r.value)
 
 
+def _attach_prev(params: UpdateParams, prev):
+    if prev is None:
+        return None
+    arr = (ctypes.c_void_p * len(prev))(*[x.h.value for x in prev])
+    params.prev_spectra = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    return arr
+
+
 def update_params(**kw) -> UpdateParams:
     p = UpdateParams()
     lib().tci_update_params_default(ctypes.byref(p))
@@ -342,9 +366,12 @@ def update_params(**kw) -> UpdateParams:
     return p
 
 
-def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, params: UpdateParams):
-    """Returns (A_out, s_out, B_out, infos) lists; outputs are library-sized views."""
+def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, params: UpdateParams,
+                            prev_spectra: list | None = None):
+    """Returns (A_out, s_out, B_out, infos) lists; outputs are library-sized views.
+    prev_spectra (learned sketch): per update the bond's spectrum before the update."""
     n = len(A)
+    keep = _attach_prev(params, prev_spectra)
     P = ctypes.c_void_p * n
     chil, d, chim = A[0].shape()
     chir = B[0].shape()[2]
@@ -362,6 +389,24 @@ def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, 
     return A_out, s_out, B_out, list(infos)
 
 
+def split_batched(ctx: Context, thetas: list, params: UpdateParams, prev_spectra: list | None = None):
+    """trunc_svd + renormalisation + write-back of given (chi_l, d, d, chi_r) tensors."""
+    n = len(thetas)
+    keep = _attach_prev(params, prev_spectra)
+    P = ctypes.c_void_p * n
+    chil, d, _, chir = thetas[0].shape()
+    kap = min(chil * d, d * chir, params.chi_max)
+    dt = thetas[0].dtype
+    A_out = [Tensor.empty(ctx, dt, chil * d * kap) for _ in range(n)]
+    B_out = [Tensor.empty(ctx, dt, kap * d * chir) for _ in range(n)]
+    s_out = [Tensor.empty(ctx, F64, kap) for _ in range(n)]
+    infos = (UpdateInfo * n)()
+    _check(lib().tci_split_batched(ctx.h, n, P(*[x.h.value for x in thetas]), ctypes.byref(params),
+                                   P(*[x.h.value for x in A_out]), P(*[x.h.value for x in s_out]),
+                                   P(*[x.h.value for x in B_out]), infos), "tci_split_batched")
+    return A_out, s_out, B_out, list(infos)
+
+
 def heff_matvec(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, x: Tensor,
                 y: Tensor | None = None) -> Tensor:
     if y is None:
@@ -376,3 +421,113 @@ def lanczos_ground(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, t
     _check(lib().tci_lanczos_ground(ctx.h, L.h, W1.h, W2.h, R.h, theta.h, n_matvec, ctypes.byref(e)),
            "tci_lanczos_ground")
     return e.value
+
+
+def profile_enable(ctx: Context, on: bool = True):
+    _check(lib().tci_profile_enable(ctx.h, 1 if on else 0), "tci_profile_enable")
+
+
+def profile_tags(ctx: Context) -> list:
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().tci_profile_tags(ctx.h, buf, 8192), "tci_profile_tags")
+    return [x for x in buf.value.decode().split("\n") if x]
+
+
+def profile_query(ctx: Context, tag: str):
+    """(launch count, total ms, total algorithmic work) for one tag."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    w = ctypes.c_double()
+    _check(lib().tci_profile_query(ctx.h, tag.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)),
+           "tci_profile_query")
+    return n.value, ms.value, w.value
+
+
+# ---------------------------------------------------------------- sketch-rank model
+class SketchModel:
+    """tci_sketch_model: the learned predictor of log2 chi* (FP32, on the GPU)."""
+
+    def __init__(self, ctx: Context, seed: int = 0, path: str | None = None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        if path is None:
+            _check(lib().tci_sketch_model_create(ctx.h, seed, ctypes.byref(h)), "tci_sketch_model_create")
+        else:
+            _check(lib().tci_sketch_model_load(ctx.h, path.encode(), ctypes.byref(h)), "tci_sketch_model_load")
+        self.h = h
+
+    @staticmethod
+    def nparams() -> int:
+        return int(lib().tci_sketch_model_nparams())
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.nparams(), dtype=np.float32)
+        _check(lib().tci_sketch_model_get_params(self.ctx.h, self.h, out.ctypes.data_as(ctypes.c_void_p), out.size),
+               "tci_sketch_model_get_params")
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().tci_sketch_model_set_params(self.ctx.h, self.h, p.ctypes.data_as(ctypes.c_void_p), p.size),
+               "tci_sketch_model_set_params")
+
+    def save(self, path: str):
+        _check(lib().tci_sketch_model_save(self.ctx.h, self.h, path.encode()), "tci_sketch_model_save")
+
+    def predict(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(self.ctx.torch_device, torch.float32).contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=self.ctx.torch_device)
+        _check(lib().tci_sketch_predict(self.ctx.h, self.h, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                        ctypes.c_void_p(y.data_ptr())), "tci_sketch_predict")
+        torch.cuda.synchronize(self.ctx.torch_device)
+        return y
+
+    def grads(self, X: torch.Tensor, T: torch.Tensor):
+        X = X.to(self.ctx.torch_device, torch.float32).contiguous()
+        T = T.to(self.ctx.torch_device, torch.float32).contiguous()
+        g = torch.empty(self.nparams(), dtype=torch.float32, device=self.ctx.torch_device)
+        loss = ctypes.c_float()
+        _check(lib().tci_sketch_grads(self.ctx.h, self.h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                      X.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss)), "tci_sketch_grads")
+        return loss.value, g
+
+    def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float = 1e-3) -> float:
+        loss = ctypes.c_float()
+        _check(lib().tci_sketch_train_step(self.ctx.h, self.h, ctypes.c_void_p(X.data_ptr()),
+                                           ctypes.c_void_p(T.data_ptr()), X.shape[0], lr, ctypes.byref(loss)),
+               "tci_sketch_train_step")
+        return loss.value
+
+    def close(self):
+        if self.h:
+            lib().tci_sketch_model_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sketch_features(ctx: Context, spectra: list, chi_max: int, d: int, eps: float) -> torch.Tensor:
+    """Feature rows (n x 35, FP32, device) of a list of descending spectra (numpy)."""
+    n = len(spectra)
+    L = max(1, max(len(s) for s in spectra))
+    S = np.zeros((n, L))
+    for i, s in enumerate(spectra):
+        S[i, :len(s)] = s
+    Sd = torch.from_numpy(S).to(ctx.torch_device)
+    ln = torch.tensor([len(s) for s in spectra], dtype=torch.int32, device=ctx.torch_device)
+    X = torch.empty((n, 35), dtype=torch.float32, device=ctx.torch_device)
+    _check(lib().tci_sketch_features(ctx.h, ctypes.c_void_p(Sd.data_ptr()), L, ctypes.c_void_p(ln.data_ptr()), n,
+                                     chi_max, d, eps, ctypes.c_void_p(X.data_ptr())), "tci_sketch_features")
+    torch.cuda.synchronize(ctx.torch_device)
+    return X
+
+
+def philox_blocks(ctx: Context, seed: int, stream: int, first: int, n: int) -> np.ndarray:
+    out = torch.empty(4 * n, dtype=torch.int32, device=ctx.torch_device)
+    _check(lib().tci_philox_blocks(ctx.h, seed, stream, first, n, ctypes.c_void_p(out.data_ptr())), "tci_philox_blocks")
+    torch.cuda.synchronize(ctx.torch_device)
+    return out.cpu().numpy().view(np.uint32)

@@ -1,0 +1,157 @@
+"""GPU parity of the DMRG pieces (effective-Hamiltonian matvec, Lanczos,
+split of a given two-site tensor) against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dmrg as odmrg
+from oracle import mps as omps
+from paper_2512_23917_amd import synth
+
+from gpu_util import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2512_23917_amd import tci
+    return tci
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def up(T, ctx, a, dt):
+    return T.Tensor.from_numpy(ctx, np.asarray(a), dt)
+
+
+def env(chi, seed, complex_=True):
+    g = synth.rng(2, seed)
+    left = synth.hermitian_environment(g, chi, complex_)
+    right = synth.hermitian_environment(g, chi, complex_)
+    w = synth.heisenberg_mpo()
+    x = synth.complex_gaussian(g, (chi, 2, 2, chi)) if complex_ else synth.real_gaussian(g, (chi, 2, 2, chi))
+    if not complex_:
+        w = w.real
+    return left, w, right, x
+
+
+@pytest.mark.parametrize("chi", [1, 3, 16, 40])
+def test_heff_matvec_fp64(T, ctx, chi):
+    left, w, right, x = env(chi, chi)
+    ref = odmrg.heff_apply(left, w, w, right, x)
+    y = T.heff_matvec(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                      up(T, ctx, right, T.C128), up(T, ctx, x, T.C128)).numpy()
+    assert rel_fro(y, ref) < 1e-13
+
+
+def test_heff_matvec_real(T, ctx):
+    left, w, right, x = env(12, 5, complex_=False)
+    ref = odmrg.heff_apply(left, w, w, right, x)
+    y = T.heff_matvec(ctx, up(T, ctx, left, T.F64), up(T, ctx, w, T.F64), up(T, ctx, w, T.F64),
+                      up(T, ctx, right, T.F64), up(T, ctx, x, T.F64)).numpy()
+    assert rel_fro(y, ref) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("PREC_FP32", 3e-6), ("PREC_BF16X3", 3e-5)])
+def test_heff_matvec_mixed(T, ctx, prec, tol):
+    left, w, right, x = env(24, 9)
+    c64 = lambda a: np.asarray(a).astype(np.complex64)
+    ref = odmrg.heff_apply(c64(left).astype(np.complex128), c64(w).astype(np.complex128),
+                           c64(w).astype(np.complex128), c64(right).astype(np.complex128),
+                           c64(x).astype(np.complex128))
+    ctx.set_precision(getattr(T, prec))
+    try:
+        y = T.heff_matvec(ctx, up(T, ctx, c64(left), T.C64), up(T, ctx, c64(w), T.C64), up(T, ctx, c64(w), T.C64),
+                          up(T, ctx, c64(right), T.C64), up(T, ctx, c64(x), T.C64)).numpy()
+    finally:
+        ctx.set_precision(T.PREC_FP32)
+    assert rel_fro(y, ref) < tol
+
+
+def test_heff_trivial_environment_spectrum(T, ctx):
+    left, right = synth.trivial_environments()
+    w = synth.heisenberg_mpo()
+    cols = []
+    for k in range(4):
+        e = np.zeros(4, dtype=np.complex128)
+        e[k] = 1.0
+        y = T.heff_matvec(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                          up(T, ctx, right, T.C128), up(T, ctx, e.reshape(1, 2, 2, 1), T.C128)).numpy()
+        cols.append(y.reshape(-1))
+    h = np.stack(cols, axis=1)
+    np.testing.assert_allclose(np.linalg.eigvalsh(h), [-0.75, 0.25, 0.25, 0.25], atol=1e-15)
+
+
+@pytest.mark.parametrize("chi,nmv", [(2, 16), (6, 20), (16, 20)])
+def test_lanczos_matches_oracle(T, ctx, chi, nmv):
+    left, w, right, x = env(chi, 100 + chi)
+    mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
+    e_ref, psi_ref, _, _ = odmrg.lanczos_ground(mv, x, n_matvec=nmv)
+    th = up(T, ctx, x, T.C128)
+    e = T.lanczos_ground(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                         up(T, ctx, right, T.C128), th, nmv)
+    assert e == pytest.approx(e_ref, rel=1e-10)
+    assert rel_fro(th.numpy(), psi_ref) < 1e-8
+    if chi == 2:
+        h = odmrg.heff_dense(left, w, w, right)
+        assert e == pytest.approx(np.linalg.eigvalsh(h)[0], rel=1e-11)
+
+
+def test_lanczos_mixed_energy(T, ctx):
+    chi = 16
+    left, w, right, x = env(chi, 77)
+    mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
+    e_ref, psi_ref, _, _ = odmrg.lanczos_ground(mv, x, n_matvec=20)
+    c64 = lambda a: np.asarray(a).astype(np.complex64)
+    th = up(T, ctx, c64(x), T.C64)
+    ctx.set_precision(T.PREC_FP32)
+    e = T.lanczos_ground(ctx, up(T, ctx, c64(left), T.C64), up(T, ctx, c64(w), T.C64), up(T, ctx, c64(w), T.C64),
+                         up(T, ctx, c64(right), T.C64), th, 20)
+    assert e == pytest.approx(e_ref, rel=1e-5)
+
+
+def test_split_batched_matches_oracle(T, ctx):
+    g = synth.rng(2, 5)
+    thetas = [synth.complex_gaussian(g, (20, 2, 2, 24)) for _ in range(3)]
+    p = T.update_params(chi_min=1, chi_max=30, target_trunc_err=1e-4, direction=1)
+    Ao, so, Bo, infos = T.split_batched(ctx, [up(T, ctx, t, T.C128) for t in thetas], p)
+    for i, th in enumerate(thetas):
+        u, s, vh, err = oracle.trunc_svd(th, 2, 1, 30, 1e-4, 0.0)
+        assert infos[i].chi == len(s)
+        assert infos[i].trunc_err == pytest.approx(err, rel=1e-8)
+        sn = s / np.linalg.norm(s)
+        np.testing.assert_allclose(so[i].numpy(), sn, atol=1e-12)
+        rec = np.einsum("asm,mtb->astb", Ao[i].numpy(), Bo[i].numpy())
+        rec_o = np.einsum("asm,mtb->astb", u * sn[None, None, :], vh)
+        assert rel_fro(rec, rec_o) < 1e-10
+
+
+def test_dmrg_update_pipeline_matches_oracle(T, ctx):
+    """theta0 = A.B, 20 Lanczos matvecs, trunc_svd (eps 1e-8, chi <= 24), renormalise."""
+    chi = 12
+    g = synth.rng(2, 9)
+    a, b = synth.complex_gaussian(g, (chi, 2, chi)), synth.complex_gaussian(g, (chi, 2, chi))
+    left = synth.hermitian_environment(g, chi)
+    right = synth.hermitian_environment(g, chi)
+    w = synth.heisenberg_mpo()
+    theta0 = omps.theta_of(a, b)
+    mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
+    e_ref, psi, _, _ = odmrg.lanczos_ground(mv, theta0, 20)
+    u, s, vh, err = oracle.trunc_svd(psi, 2, 1, 24, 1e-8, 0.0)
+    th = T.contract(ctx, up(T, ctx, a, T.C128), "asm", up(T, ctx, b, T.C128), "mtb", "astb")
+    e = T.lanczos_ground(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                         up(T, ctx, right, T.C128), th, 20)
+    assert e == pytest.approx(e_ref, rel=1e-10)
+    p = T.update_params(chi_min=1, chi_max=24, target_trunc_err=1e-8, direction=1)
+    Ao, so, Bo, infos = T.split_batched(ctx, [th], p)
+    assert infos[0].chi == len(s)
+    rec = np.einsum("asm,mtb->astb", Ao[0].numpy(), Bo[0].numpy())
+    sn = s / np.linalg.norm(s)
+    assert rel_fro(rec, np.einsum("asm,mtb->astb", u * sn[None, None, :], vh)) < 1e-8

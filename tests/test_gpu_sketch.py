@@ -1,0 +1,184 @@
+"""GPU parity of the randomized / learned truncated SVD and of the sketch-rank
+model's kernels against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from oracle import mps as omps
+from oracle import rsvd as orsvd
+from paper_2512_23917_amd import synth
+
+from gpu_util import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2512_23917_amd import tci
+    return tci
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def up(T, ctx, a, dt):
+    return T.Tensor.from_numpy(ctx, np.asarray(a), dt)
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_known_answers_and_oracle(T, ctx):
+    kat0 = T.philox_blocks(ctx, 0, 0, 0, 1)
+    assert [int(x) for x in kat0] == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    got = T.philox_blocks(ctx, 0xDEADBEEF12345, 3, 1000, 4096)
+    want = oracle.philox_blocks(0xDEADBEEF12345, 3, 1000, 4096)
+    np.testing.assert_array_equal(got, want)
+
+
+# ------------------------------------------------------------------ randomized tSVD
+def _spectrum_theta(chi, alpha, seed):
+    g = synth.rng(5, seed)
+    s_true = synth.power_spectrum(chi, alpha)
+    a, b = synth.two_site_blocks_from_spectrum(g, chi // 2, 2, s_true)   # theta chi x chi, rank chi
+    return a, b, s_true
+
+
+@pytest.mark.parametrize("alpha,k", [(3.0, 64), (2.5, 96)])
+def test_randomized_update_matches_oracle_randomized(T, ctx, alpha, k):
+    """Same Philox sketch on both sides: the GPU randomized SVD reproduces the
+    oracle's randomized SVD (FP64), and its kept values match the exact SVD."""
+    a, b, s_true = _spectrum_theta(256, alpha, int(alpha * 10))
+    theta = np.einsum("asm,mtb->astb", a, b)
+    th = theta.reshape(256, 256)
+    want_chi, _ = oracle.trunc_rule(s_true, 1, 256, 1e-8, 0.0)
+    ref = orsvd.tsvd_with_fallback(th, k, q=2, seed=11, chi_max=200, target=1e-8, stream=0, complex_=True)
+    assert not ref["fallback"]
+    p = T.update_params(chi_min=1, chi_max=200, target_trunc_err=1e-8, direction=1, svd_mode=T.SVD_RANDOMIZED,
+                        sketch_rank=k, power_iters=2, seed=11)
+    Ao, so, Bo, inf = T.split_batched(ctx, [up(T, ctx, theta, T.C128)], p)
+    assert inf[0].used_fallback == 0 and inf[0].sketch_rank == k
+    assert inf[0].chi == ref["chi"] == want_chi
+    assert inf[0].trunc_err == pytest.approx(ref["err"], rel=1e-6)
+    s = so[0].numpy()
+    s_ref = ref["s"] / np.linalg.norm(ref["s"])
+    assert np.abs(s - s_ref).max() < 1e-12
+    assert np.abs(s - s_true[:want_chi] / np.linalg.norm(s_true[:want_chi])).max() < 1e-9
+    rec = np.einsum("asm,mtb->astb", Ao[0].numpy(), Bo[0].numpy()).reshape(256, 256)
+    rec_ref = ref["u"] @ np.diag(s_ref) @ ref["vh"]
+    assert rel_fro(rec, rec_ref) < 1e-9
+    assert inf[0].max_residual == pytest.approx(np.max(ref["residual"]) / ref["sig_all"][0], rel=1e-3, abs=1e-12)
+
+
+def test_randomized_falls_back_to_plain(T, ctx):
+    a, b, s_true = _spectrum_theta(128, 1.0, 3)
+    theta = np.einsum("asm,mtb->astb", a, b)
+    p = T.update_params(chi_min=1, chi_max=128, target_trunc_err=1e-8, direction=1, svd_mode=T.SVD_RANDOMIZED,
+                        sketch_rank=16, power_iters=1, seed=2)
+    Ao, so, Bo, inf = T.split_batched(ctx, [up(T, ctx, theta, T.C128)], p)
+    assert inf[0].used_fallback == 1
+    want_chi, want_err = oracle.trunc_rule(s_true, 1, 128, 1e-8, 0.0)
+    assert inf[0].chi == want_chi
+    assert np.abs(so[0].numpy() - s_true[:want_chi] / np.linalg.norm(s_true[:want_chi])).max() < 1e-10
+
+
+def test_randomized_mixed_bf16x3_update(T, ctx):
+    """complex64 storage, split-BF16x3 products, FP64 core: kept singular
+    values within 1e-6 normwise, reconstruction within 1e-5."""
+    chi = 128
+    g = synth.rng(5, 77)
+    s_true = synth.power_spectrum(chi, 3.0)
+    a, b = synth.two_site_blocks_from_spectrum(g, chi, 2, s_true)      # theta 256 x 256, rank 128
+    gate = synth.haar_gate(g)
+    ref = omps.two_site_update(a, b, gate, 1, 200, 1e-8, 0.0, omps.RIGHT)
+    c64 = lambda x: np.asarray(x).astype(np.complex64)
+    p = T.update_params(chi_min=1, chi_max=200, target_trunc_err=1e-8, direction=1, svd_mode=T.SVD_RANDOMIZED,
+                        sketch_rank=ref["chi"] + 32, power_iters=2, seed=5, precision=T.PREC_BF16X3)
+    Ao, so, Bo, inf = T.two_site_update_batched(ctx, [up(T, ctx, c64(a), T.C64)], [up(T, ctx, c64(b), T.C64)],
+                                                [up(T, ctx, c64(gate), T.C64)], p)
+    chi_ref = ref["chi"]
+    assert abs(inf[0].chi - chi_ref) <= 2
+    c = min(inf[0].chi, chi_ref)
+    s = so[0].numpy()
+    assert np.abs(s[:c] - ref["s"][:c]).max() <= 1e-6 * ref["s"][0]
+    rec = np.einsum("asm,mtb->astb", Ao[0].numpy().astype(np.complex128), Bo[0].numpy().astype(np.complex128))
+    rec_ref = np.einsum("asm,mtb->astb", ref["a_out"], ref["b_out"])
+    assert rel_fro(rec, rec_ref) < 1e-5
+
+
+# ------------------------------------------------------------------ sketch-rank model
+def test_model_init_matches_oracle_init(T, ctx):
+    m = T.SketchModel(ctx, seed=0)
+    got = m.params().astype(np.float64)
+    want = omlp.init_params(0).astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(got, want)
+    m.close()
+
+
+def test_model_forward_grads_adam_match_oracle(T, ctx):
+    g = np.random.default_rng(3)
+    theta = omlp.init_params(1) + 0.02 * g.standard_normal(omlp.N_PARAMS)
+    theta32 = theta.astype(np.float32)
+    x = g.standard_normal((256, 35)).astype(np.float32)
+    t = (g.standard_normal(256) * 2 + 5).astype(np.float32)
+    m = T.SketchModel(ctx, seed=1)
+    m.set_params(theta32)
+    y = m.predict(torch.from_numpy(x)).cpu().numpy()
+    y_ref, _ = omlp.forward(theta32.astype(np.float64), x.astype(np.float64))
+    assert rel_fro(y, y_ref) < 1e-5
+    loss, grad = m.grads(torch.from_numpy(x), torch.from_numpy(t))
+    loss_ref, grad_ref = omlp.loss_and_grad(theta32.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(loss_ref, rel=1e-5)
+    gr = grad.cpu().numpy()
+    for part, part_ref in zip(omlp.unpack(gr), omlp.unpack(grad_ref)):
+        assert rel_fro(part, part_ref) < 1e-4
+    # one Adam step from zero state
+    X = torch.from_numpy(x).to(ctx.torch_device)
+    Tt = torch.from_numpy(t).to(ctx.torch_device)
+    m.train_step(X, Tt, 1e-3)
+    th_ref, _, _ = omlp.adam_step(theta32.astype(np.float64), grad_ref, np.zeros(omlp.N_PARAMS),
+                                  np.zeros(omlp.N_PARAMS), 1, lr=1e-3)
+    assert rel_fro(m.params(), th_ref) < 1e-6
+    m.close()
+
+
+def test_features_match_oracle(T, ctx):
+    specs = [synth.power_spectrum(300, 2.0), synth.exp_spectrum(1024, 200.0), np.array([1.0, 0.5]),
+             synth.power_spectrum(33, 1.0)]
+    X = T.sketch_features(ctx, specs, 1024, 2, 1e-8).cpu().numpy()
+    for i, s in enumerate(specs):
+        np.testing.assert_allclose(X[i], omlp.features(s, 1024, 2, 1e-8), atol=1e-6)
+
+
+def test_learned_update_uses_model_rank(T, ctx):
+    """With a model whose output is a constant y, the update uses the sketch
+    rank of the rule k = 32 ceil((2^y 1.1 + 16) / 32) and accepts when the
+    sketch covers chi*."""
+    a, b, s_true = _spectrum_theta(256, 3.0, 21)
+    theta = np.einsum("asm,mtb->astb", a, b)
+    want_chi, _ = oracle.trunc_rule(s_true, 1, 256, 1e-8, 0.0)
+    m = T.SketchModel(ctx, seed=0)
+    p0 = np.zeros(omlp.N_PARAMS, dtype=np.float32)
+    y_const = math.log2(want_chi) + 0.5
+    p0[-1] = y_const                       # b3: constant prediction
+    m.set_params(p0)
+    k_rule = omlp.sketch_rank(y_const, 256, 200)
+    prev = up(T, ctx, s_true, T.F64)
+    p = T.update_params(chi_min=1, chi_max=200, target_trunc_err=1e-8, direction=1, svd_mode=T.SVD_LEARNED,
+                        power_iters=2, seed=4)
+    p.sketch_model = m.h.value
+    Ao, so, Bo, inf = T.split_batched(ctx, [up(T, ctx, theta, T.C128)], p, prev_spectra=[prev])
+    assert inf[0].sketch_rank == k_rule and inf[0].used_fallback == 0 and inf[0].chi == want_chi
+    # a prediction above log2 chi_max selects the plain SVD directly
+    p0[-1] = math.log2(200) + 1.0
+    m.set_params(p0)
+    Ao, so, Bo, inf = T.split_batched(ctx, [up(T, ctx, theta, T.C128)], p, prev_spectra=[prev])
+    assert inf[0].sketch_rank == 0 and inf[0].used_fallback == 1 and inf[0].chi == want_chi
+    m.close()
