@@ -14,8 +14,11 @@ where s is the previous (descending) spectrum of the bond.
 Target: log2 chi*(eps) of the bond after the update.
 Loss: pinball (quantile) loss with tau = 0.9, averaged over the batch:
     rho(u) = max(tau u, (tau - 1) u),  u = target - prediction.
-Sketch rank from a prediction y: k = min(n, 32 * ceil((2^y * 1.1 + 16) / 32));
-y > log2(chi_max) means "use the plain truncated SVD".
+Sketch rank from a prediction y: k = 32 * ceil((1.5 * 2^y + 32) / 32); the
+plain truncated SVD is used instead when y > log2(chi_max) or k > 0.6 n.  (The
+oversampling follows the randomized-SVD error bound of Halko, Martinsson and
+Tropp: with q power iterations the residual of the kept triplet j scales like
+(s_{k+1}/s_j)^(2q+1), so a slowly decaying spectrum needs k well above chi*.)
 Parameters are stored flat in the order W1 (128x35, row-major), b1, W2
 (128x128), b2, W3 (1x128), b3.
 """
@@ -53,8 +56,10 @@ def sketch_rank(y: float, n: int, chi_max: int):
     """Returns the sketch rank, or None for 'plain truncated SVD'."""
     if y > math.log2(chi_max):
         return None
-    k = 32 * math.ceil((2.0 ** y * 1.1 + 16.0) / 32.0)
-    return min(n, k)
+    k = 32 * math.ceil((2.0 ** y * 1.5 + 32.0) / 32.0)
+    if k > 0.6 * n:
+        return None
+    return k
 
 
 def unpack(theta):

@@ -107,6 +107,9 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   }
   TCI_CHECK_HIP(w_from(Ylo, Y64, sY * nb));
   TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
+  // Power iterations in the contraction precision; the last product with
+  // theta, and B = Q^H theta, in FP64 so that the Rayleigh-Ritz step sees the
+  // sketched subspace without the rounding of the mixed products.
   for (int it = 0; it < q; ++it) {
     TCI_CHECK_HIP(lo_from(Y64, Ylo, sY * nb));
     GemmArgs g1 = gemm_args(n, kmax, m, OP_C, OP_N, th_lo, n, Ylo, kmax, Zlo, kmax);
@@ -114,24 +117,27 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     TCI_CHECK_HIP(gemm(dt_lo, prec, g1, s));
     TCI_CHECK_HIP(w_from(Zlo, Z64, sZ * nb));
     TCI_TRY(ortho2(ctx, wdt, Z64, kmax, sZ, n, kmax, nb));
-    TCI_CHECK_HIP(lo_from(Z64, Zlo, sZ * nb));
-    GemmArgs g2 = gemm_args(m, kmax, n, OP_N, OP_N, th_lo, n, Zlo, kmax, Ylo, kmax);
-    g2.sA = smn; g2.sB = sZ; g2.sC = sY; g2.batch = nb;
-    TCI_CHECK_HIP(gemm(dt_lo, prec, g2, s));
-    TCI_CHECK_HIP(w_from(Ylo, Y64, sY * nb));
+    if (it + 1 < q) {
+      TCI_CHECK_HIP(lo_from(Z64, Zlo, sZ * nb));
+      GemmArgs g2 = gemm_args(m, kmax, n, OP_N, OP_N, th_lo, n, Zlo, kmax, Ylo, kmax);
+      g2.sA = smn; g2.sB = sZ; g2.sC = sY; g2.batch = nb;
+      TCI_CHECK_HIP(gemm(dt_lo, prec, g2, s));
+      TCI_CHECK_HIP(w_from(Ylo, Y64, sY * nb));
+    } else {
+      GemmArgs g2 = gemm_args(m, kmax, n, OP_N, OP_N, th64, n, Z64, kmax, Y64, kmax);
+      g2.sA = smn; g2.sB = sZ; g2.sC = sY; g2.batch = nb;
+      TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g2, s));
+    }
     TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
   }
-  // B = Q^H theta (contraction precision), Gram B B^H (FP64)
+  // B = Q^H theta (FP64), Gram B B^H (FP64)
   const long long sB = (long long)kmax * n;
-  TCI_CHECK_HIP(lo_from(Y64, Ylo, sY * nb));
-  SK_ARENA(Blo, char, el * (size_t)sB * nb);
   SK_ARENA(B64, char, ew * (size_t)sB * nb);
   {
-    GemmArgs g = gemm_args(kmax, n, m, OP_C, OP_N, Ylo, kmax, th_lo, n, Blo, n);
+    GemmArgs g = gemm_args(kmax, n, m, OP_C, OP_N, Y64, kmax, th64, n, B64, n);
     g.sA = sY; g.sB = smn; g.sC = sB; g.batch = nb;
-    TCI_CHECK_HIP(gemm(dt_lo, prec, g, s));
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
-  TCI_CHECK_HIP(w_from(Blo, B64, sB * nb));
   const long long sG = (long long)kmax * kmax;
   SK_ARENA(Gk, char, ew * (size_t)sG * nb);
   {
@@ -253,13 +259,15 @@ tci_status sketch_predict_dev(tci_context ctx, tci_sketch_model m, const float* 
 tci_status sketch_features_dev(tci_context ctx, const double* s, long long ss, const int* len, int chi_max, int d,
                                double eps, float* X, int n);
 
-// Sketch rank of the model's prediction y = log2 chi*: k = min(ng, 32 ceil((2^y 1.1 + 16) / 32));
-// 0 (plain SVD) when y > log2 chi_max.
+// Sketch rank of the model's prediction y = log2 chi*:
+// k = 32 ceil((1.5 * 2^y + 32) / 32); 0 (plain SVD) when y > log2 chi_max or
+// when k > 0.6 n (the sketch would then cost about as much as the plain SVD).
 static int rank_from_prediction(double y, int ng, int chi_max) {
   if (!(y <= std::log2((double)chi_max))) return 0;
-  const double want = std::pow(2.0, y) * 1.1 + 16.0;
+  const double want = std::pow(2.0, y) * 1.5 + 32.0;
   const int k = 32 * (int)std::ceil(want / 32.0);
-  return std::min(ng, std::max(32, k));
+  if (k > 0.6 * ng) return 0;
+  return k;
 }
 
 tci_status choose_sketch_ranks(tci_context ctx, const tci_update_params& p, int nb, int first, int ng, int chi_max,

@@ -61,9 +61,10 @@ def test_features_closed_form():
 
 
 def test_sketch_rank_rule():
-    assert mlp.sketch_rank(math.log2(100.0), 2048, 1024) == 128   # 110 + 16 = 126 -> 128
+    assert mlp.sketch_rank(math.log2(100.0), 2048, 1024) == 192   # 150 + 32 = 182 -> 192
     assert mlp.sketch_rank(math.log2(1024.0) + 0.01, 2048, 1024) is None
-    assert mlp.sketch_rank(9.9, 600, 1024) == 600
+    assert mlp.sketch_rank(9.9, 600, 1024) is None                # k = 1472 > 0.6 * 600
+    assert mlp.sketch_rank(5.0, 2048, 1024) == 96                 # 48 + 32 = 80 -> 96
 
 
 def test_init_is_he_uniform_and_deterministic():
