@@ -1,0 +1,274 @@
+// Split-BF16x3 GEMM on pre-split operand planes.
+//
+// A float operand x is split once into x = hi + lo with hi = rne_bf16(x) and
+// lo = rne_bf16(x - hi) (both round-to-nearest-even, lo from the exact FP32
+// difference).  For complex operands the planes are (re_hi, re_lo, im_hi,
+// im_lo).  The planes of op(A) are stored [plane][Mp][Kp] and those of op(B)
+// as [plane][Np][Kp] (k contiguous, zero padded to the tile sizes), which is
+// the order in which one lane of v_mfma_f32_16x16x32_bf16 consumes 8
+// consecutive k values of one row (A) or one column (B).  The product keeps
+// three terms, hi*hi + hi*lo + lo*hi, accumulated in FP32; the complex
+// product uses four real products.
+//
+// Tiles: 128 x 128 outputs per workgroup (4 waves, 64 x 64 each), k tile 32;
+// the next k tile is fetched into registers while the current one feeds the
+// matrix cores.
+#include "common.hpp"
+#include "gemm.hpp"
+#include "bf16x3.hpp"
+#include "prof.hpp"
+
+namespace tci {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+constexpr int XBM = 128, XBN = 128, XBK = 32, XKP = XBK + 8;
+
+// ---------------------------------------------------------------------------
+// Splitting: X(r, k) = src[r*ld + k] (mode 0) or src[k*ld + r] (mode 1), with
+// optional conjugation; writes planes[p][r][k] for r < Rp, k < Kp (zero pad).
+// Mode 1 goes through a 64 x 64 LDS tile so that reads and writes coalesce.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void getf(const T* p, float& r, float& i);
+template <> __device__ inline void getf(const float* p, float& r, float& i) { r = *p; i = 0.f; }
+template <> __device__ inline void getf(const cf* p, float& r, float& i) { const cf v = *p; r = v.x; i = v.y; }
+
+__device__ inline void split1(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void split_planes_kernel(const T* src, long long ld, long long ssrc, int mode,
+                                                           int conj, int R, int K, __bf16* dst, int Rp, int Kp,
+                                                           long long sdst) {
+  constexpr bool CPLX = sizeof(T) == 8;
+  __shared__ float tre[64][65], tim[64][65];
+  const int b = blockIdx.z;
+  const T* s = src + b * ssrc;
+  __bf16* d = dst + b * sdst;
+  const long long plane = (long long)Rp * Kp;
+  const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  const float sg = conj ? -1.f : 1.f;
+  if (mode == 0) {
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int rr = e / 64, kk = e % 64;
+      const int r = r0 + rr, k = k0 + kk;
+      float vr = 0.f, vi = 0.f;
+      if (r < R && k < K) getf(s + (long long)r * ld + k, vr, vi);
+      tre[rr][kk] = vr;
+      tim[rr][kk] = sg * vi;
+    }
+  } else {
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int kk = e / 64, rr = e % 64;
+      const int r = r0 + rr, k = k0 + kk;
+      float vr = 0.f, vi = 0.f;
+      if (r < R && k < K) getf(s + (long long)k * ld + r, vr, vi);
+      tre[rr][kk] = vr;
+      tim[rr][kk] = sg * vi;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int rr = e / 64, kk = e % 64;
+    const int r = r0 + rr, k = k0 + kk;
+    if (r >= Rp || k >= Kp) continue;
+    const long long o = (long long)r * Kp + k;
+    __bf16 h, l;
+    split1(tre[rr][kk], h, l);
+    d[o] = h;
+    d[plane + o] = l;
+    if constexpr (CPLX) {
+      split1(tim[rr][kk], h, l);
+      d[2 * plane + o] = h;
+      d[3 * plane + o] = l;
+    }
+  }
+}
+
+hipError_t split_planes(int dtype, const void* src, long long ld, long long ssrc, int mode, int conj, int R, int K,
+                        void* dst, int Rp, int Kp, long long sdst, int batch, hipStream_t s) {
+  dim3 grid((Kp + 63) / 64, (Rp + 63) / 64, batch);
+  if (dtype == C64)
+    hipLaunchKernelGGL(split_planes_kernel<cf>, grid, dim3(256), 0, s, (const cf*)src, ld, ssrc, mode, conj, R, K,
+                       (__bf16*)dst, Rp, Kp, sdst);
+  else if (dtype == F32)
+    hipLaunchKernelGGL(split_planes_kernel<float>, grid, dim3(256), 0, s, (const float*)src, ld, ssrc, mode, conj, R,
+                       K, (__bf16*)dst, Rp, Kp, sdst);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// GEMM on planes.  Workgroup tile 128 x 128, waves 2 x 2 (64 x 64 each =
+// 4 x 4 MFMA blocks).  Staging: each plane tile is 128 rows x 32 k = 8 KB =
+// 512 chunks of 16 bytes; thread t moves chunks t and t + 256 of each plane.
+// ---------------------------------------------------------------------------
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
+  constexpr int NP = CPLX ? 4 : 2;
+  __shared__ __attribute__((aligned(16))) __bf16 As[NP][XBM][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][XBN][XKP];
+  // tile coordinates, XCD-aware as in the plain GEMM
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const long total = (long)gx * gy * gz;
+  long lin = blockIdx.x + (long)gx * (blockIdx.y + (long)gy * blockIdx.z);
+  if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+  const int tn = (int)(lin % gx);
+  lin /= gx;
+  const int tm = (int)(lin % gy);
+  const int b = (int)(lin / gy);
+  const int m0 = tm * XBM, n0 = tn * XBN;
+  const __bf16* A = a.Ap + b * a.sAp;
+  const __bf16* B = a.Bp + b * a.sBp;
+  const long long pa = (long long)a.Mp * a.Kp, pb = (long long)a.Np * a.Kp;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  f4v acc_re[4][4], acc_im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc_re[i][j] = f4v{0, 0, 0, 0};
+      acc_im[i][j] = f4v{0, 0, 0, 0};
+    }
+
+  // chunk c in [0, 512): row c >> 2, k offset (c & 3) * 8
+  u4v ra[NP][2], rb[NP][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = t + 256 * h;
+        const int row = c >> 2, ko = (c & 3) * 8;
+        ra[p][h] = *reinterpret_cast<const u4v*>(A + p * pa + (long long)(m0 + row) * a.Kp + k0 + ko);
+        rb[p][h] = *reinterpret_cast<const u4v*>(B + p * pb + (long long)(n0 + row) * a.Kp + k0 + ko);
+      }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = t + 256 * h;
+        const int row = c >> 2, ko = (c & 3) * 8;
+        *reinterpret_cast<u4v*>(&As[p][row][ko]) = ra[p][h];
+        *reinterpret_cast<u4v*>(&Bs[p][row][ko]) = rb[p][h];
+      }
+  };
+
+  fetch(0);
+  for (int k0 = 0; k0 < a.Kp; k0 += XBK) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + XBK < a.Kp) fetch(k0 + XBK);
+    bf8v fa[NP][4], fb[NP][4];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[p][i] = *reinterpret_cast<const bf8v*>(&As[p][wm * 64 + i * 16 + lr][8 * lk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[p][wn * 64 + j * 16 + lr][8 * lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], acc_re[i][j], 0, 0, 0);
+        if constexpr (CPLX) {
+          const bf8v nh = -fa[2][i], nl = -fa[3][i];
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[2][j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[3][j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nl, fb[2][j], acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[2][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[3][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[2][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[0][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[1][j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[3][i], fb[0][j], acc_im[i][j], 0, 0, 0);
+        }
+      }
+  }
+
+  // epilogue: C = alpha * acc + beta * C (rows 4*(l/16)+r, column l%16 of each block)
+  const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+  const float ar = (float)a.alpha_re, ai = (float)a.alpha_im, br = (float)a.beta_re, bi = (float)a.beta_im;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+        const int col = n0 + wn * 64 + j * 16 + lr;
+        if (row < a.m && col < a.n) {
+          const float vr = acc_re[i][j][r], vi = CPLX ? acc_im[i][j][r] : 0.f;
+          float orr = ar * vr - ai * vi, oi = ar * vi + ai * vr;
+          if constexpr (CPLX) {
+            cf* p = reinterpret_cast<cf*>(a.C) + b * a.sC + (long long)row * a.ldc + col;
+            if (!beta0) {
+              const cf c = *p;
+              orr += br * c.x - bi * c.y;
+              oi += br * c.y + bi * c.x;
+            }
+            *p = cf{orr, oi};
+          } else {
+            float* p = reinterpret_cast<float*>(a.C) + b * a.sC + (long long)row * a.ldc + col;
+            if (!beta0) orr += br * *p;
+            *p = orr;
+          }
+        }
+      }
+}
+
+hipError_t gemm_planes(int dtype, const PlaneGemmArgs& a, hipStream_t s) {
+  if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return hipSuccess;
+  if (a.Mp % XBM || a.Np % XBN || a.Kp % XBK || a.Mp < a.m || a.Np < a.n) return hipErrorInvalidValue;
+  dim3 grid(a.Np / XBN, a.Mp / XBM, a.batch);
+  const bool cplx = dtype == C64;
+  const double flops = (cplx ? 8.0 : 2.0) * 3.0 * a.m * (double)a.n * a.k * a.batch;
+  ProfScope ps(s, flops, cplx ? "c64_bf16x3" : "f32_bf16x3");
+  if (cplx) hipLaunchKernelGGL(gemm_planes_kernel<true>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(gemm_planes_kernel<false>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int planes_of(int dtype) { return dtype == C64 ? 4 : 2; }
+int pad_rows(int r) { return (r + XBM - 1) / XBM * XBM; }
+int pad_k(int k) { return (k + XBK - 1) / XBK * XBK; }
+
+// op(A) (M x K) -> planes [P][Mp][Kp]
+hipError_t split_a(int dtype, int opA, const void* A, long long lda, long long sA, int M, int K, void* dst, int batch,
+                   hipStream_t s) {
+  const int mode = (opA == OP_N || opA == OP_R) ? 0 : 1;
+  const int conj = (opA == OP_C || opA == OP_R) ? 1 : 0;
+  const int Mp = pad_rows(M), Kp = pad_k(K);
+  return split_planes(dtype, A, lda, sA, mode, conj, M, K, dst, Mp, Kp, (long long)planes_of(dtype) * Mp * Kp, batch, s);
+}
+
+// op(B) (K x N) -> planes [P][Np][Kp] of op(B)^T
+hipError_t split_b(int dtype, int opB, const void* B, long long ldb, long long sB, int K, int N, void* dst, int batch,
+                   hipStream_t s) {
+  const int mode = (opB == OP_N || opB == OP_R) ? 1 : 0;
+  const int conj = (opB == OP_C || opB == OP_R) ? 1 : 0;
+  const int Np = pad_rows(N), Kp = pad_k(K);
+  return split_planes(dtype, B, ldb, sB, mode, conj, N, K, dst, Np, Kp, (long long)planes_of(dtype) * Np * Kp, batch, s);
+}
+
+size_t planes_bytes(int dtype, int rows, int k) {
+  return sizeof(__bf16) * (size_t)planes_of(dtype) * pad_rows(rows) * pad_k(k);
+}
+
+}  // namespace tci

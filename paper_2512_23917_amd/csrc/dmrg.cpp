@@ -4,6 +4,9 @@
 //   X2[a][(s1,s2,w''),b']   = sum_{w,s1',s2'} W12[(w,s1',s2'),(s1,s2,w'')] X1[a][(w,s1',s2'),b']
 //   y[(a,s1,s2),b]          = sum_{w'',b'} X2[(a,s1,s2),(w'',b')] R[b,(w'',b')]
 // with W12 = sum_w' W1[w,w',s1,s1'] W2[w',w'',s2,s2'] formed once per call.
+// In the split-BF16x3 precision the environments are split into bf16 planes
+// once per call; x and X2 are split once per matvec, and the two large
+// products run on the pre-split planes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +18,7 @@
 #include "../../include/tci_c.h"
 #include "common.hpp"
 #include "eig.hpp"
+#include "bf16x3.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
 #include "runtime.hpp"
@@ -30,6 +34,8 @@ struct HeffPlan {
   void* W12;  // (w d d) x (d d w)
   void* X1;   // chil * w * d * d * chir
   void* X2;   // chil * d * d * w * chir
+  bool planes;               // split-BF16x3 on pre-split planes
+  void *Lp, *Rp, *Xp, *X2p;  // planes of L', R', x', X2'
 };
 
 static tci_status heff_check(tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, tci_tensor x, int& chil,
@@ -67,7 +73,30 @@ static tci_status heff_prepare(tci_context ctx, tci_tensor L, tci_tensor W1, tci
   p.X2 = ctx->arena.get(es * (size_t)chil * kw * chir);
   if (!p.W12 || !p.X1 || !p.X2) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "heff workspace");
   TCI_CHECK_HIP(mpo_pair(p.dt, W1->data, W2->data, p.W12, wd, d, ctx->stream));
+  p.planes = (p.dt == C64 || p.dt == F32) && p.prec == PREC_BF16X3;
+  if (p.planes) {
+    const int dd = d * d;
+    p.Lp = ctx->arena.get(planes_bytes(p.dt, chil * wd, chil));
+    p.Rp = ctx->arena.get(planes_bytes(p.dt, chir, wd * chir));
+    p.Xp = ctx->arena.get(planes_bytes(p.dt, dd * chir, chil));
+    p.X2p = ctx->arena.get(planes_bytes(p.dt, chil * dd, wd * chir));
+    if (!p.Lp || !p.Rp || !p.Xp || !p.X2p) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "heff plane workspace");
+    // L' = L[(a,w),a'] as op(A) of the first product; R'^T as op(B) of the last
+    TCI_CHECK_HIP(split_a(p.dt, OP_N, L->data, chil, 0, chil * wd, chil, p.Lp, 1, ctx->stream));
+    TCI_CHECK_HIP(split_b(p.dt, OP_T, R->data, (long long)wd * chir, 0, wd * chir, chir, p.Rp, 1, ctx->stream));
+  }
   return TCI_OK;
+}
+
+static PlaneGemmArgs plane_args(int m, int n, int k, const void* Ap, const void* Bp, void* C, long long ldc) {
+  PlaneGemmArgs a{};
+  a.m = m; a.n = n; a.k = k;
+  a.Mp = pad_rows(m); a.Np = pad_rows(n); a.Kp = pad_k(k);
+  a.Ap = static_cast<const __bf16*>(Ap); a.Bp = static_cast<const __bf16*>(Bp);
+  a.C = C; a.ldc = ldc;
+  a.alpha_re = 1.0;
+  a.batch = 1;
+  return a;
 }
 
 static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, void* y) {
@@ -75,9 +104,15 @@ static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, 
   hipStream_t s = ctx->stream;
   // X1 = L' x'
   ProfTag t1("heff_L");
-  GemmArgs g1 = gemm_args(p.chil * p.w, p.d * p.d * p.chir, p.chil, OP_N, OP_N, p.L, p.chil, x, p.d * p.d * p.chir,
-                          p.X1, p.d * p.d * p.chir);
-  TCI_CHECK_HIP(gemm(p.dt, p.prec, g1, s));
+  const int dd = p.d * p.d;
+  if (p.planes) {
+    TCI_CHECK_HIP(split_b(p.dt, OP_N, x, (long long)dd * p.chir, 0, p.chil, dd * p.chir, p.Xp, 1, s));
+    TCI_CHECK_HIP(gemm_planes(p.dt, plane_args(p.chil * p.w, dd * p.chir, p.chil, p.Lp, p.Xp, p.X1, dd * p.chir), s));
+  } else {
+    GemmArgs g1 = gemm_args(p.chil * p.w, dd * p.chir, p.chil, OP_N, OP_N, p.L, p.chil, x, dd * p.chir, p.X1,
+                            dd * p.chir);
+    TCI_CHECK_HIP(gemm(p.dt, p.prec, g1, s));
+  }
   // X2[a] = W12^T X1[a]
   ProfTag t2("heff_W12");
   GemmArgs g2 = gemm_args(kw, p.chir, kw, OP_T, OP_N, p.W12, kw, p.X1, p.chir, p.X2, p.chir);
@@ -85,6 +120,11 @@ static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, 
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g2, s));
   // y = X2' R'^T
   ProfTag t3("heff_R");
+  if (p.planes) {
+    TCI_CHECK_HIP(split_a(p.dt, OP_N, p.X2, (long long)p.w * p.chir, 0, p.chil * dd, p.w * p.chir, p.X2p, 1, s));
+    TCI_CHECK_HIP(gemm_planes(p.dt, plane_args(p.chil * dd, p.chir, p.w * p.chir, p.X2p, p.Rp, y, p.chir), s));
+    return TCI_OK;
+  }
   GemmArgs g3 = gemm_args(p.chil * p.d * p.d, p.chir, p.w * p.chir, OP_N, OP_T, p.X2, (long long)p.w * p.chir, p.R,
                           (long long)p.w * p.chir, y, p.chir);
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g3, s));

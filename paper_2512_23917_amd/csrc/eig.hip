@@ -61,178 +61,381 @@ __device__ inline cd bsum(cd v, double* sh) {
   return cd{a, b};
 }
 
-// w_ip = tau (y - V t2' ...) for panel column pp = ip - j0 (see LAPACK's
-// latrd):  t1 = W(ip+1:n, 0:pp)^H v,  t2 = V(ip+1:n, 0:pp)^H v,
-//          w = tau (y - V t1 - W t2),  w += (-tau/2 w^H v) v.
+// ---------------------------------------------------------------------------
+// Per-column kernels of the blocked reduction (LAPACK latrd organisation,
+// lower storage, panel of NB columns starting at j0; p = i - j0):
+//
+//  colA (row blocks of TT rows over [row0, n)):
+//    finish w_ip (ip = i-1): with t1 = W^H v, t2 = V^H v and yv = v^H A22 v
+//      (reduced by the previous colC),  alpha = -|tau|^2/2 (yv - t1^H t2 - t2^H t1),
+//      w(r) = tau (y(r) - V(r,:) t1 - W(r,:) t2) + alpha v(r),  y(r) = sum_t P[t][r];
+//    update column i: a(r,i) -= V(r,:) conj(W(i,:)) + W(r,:) conj(V(i,:));
+//    d_i = Re a(i,i); partial ||a(i+2:n,i)||^2 reduced by the last workgroup.
+//  colC (lower-triangle tiles TT x TT of the trailing matrix):
+//    reflector of a(i+1:n,i): beta = -sign(Re a) ||.||, tau = (beta - a)/beta,
+//    v = [1, x / (a - beta)];  tile (R,C), C <= R, adds A_RC v_C to P[C][R rows]
+//    and, for C < R, A_RC^H v_R to P[R][C rows]; partial quadratic form
+//    v^H A v and, on diagonal tiles, t1 = W^H v and t2 = V^H v over its rows;
+//    the last workgroup reduces the partials.
+// Every tile of the lower triangle is read once per column.
+// ---------------------------------------------------------------------------
+constexpr int TT = 64;
+
 template <typename T, int NB>
-__device__ void finish_w(const TriArgs& a, int b, int ip, int j0, double* sh, T* s_t1, T* s_t2) {
-  const int n = a.n;
-  const T* V = reinterpret_cast<const T*>(a.Vt) + b * a.sVt;
-  T* W = reinterpret_cast<T*>(a.Wp) + b * a.sWp;
-  const T* Y = reinterpret_cast<const T*>(a.y) + b * a.sy;
-  const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ip];
-  const int pp = ip - j0, tid = threadIdx.x;
-  const T* v = V + (long)ip * n;
-  for (int q = 0; q < pp; ++q) {
-    T p1 = EigT<T>::zero(), p2 = EigT<T>::zero();
-    const T* vq = V + (long)(j0 + q) * n;
-    for (int r = ip + 1 + tid; r < n; r += 256) {
-      p1 = add(p1, mulr(cj(W[(long)r * NB + q]), v[r]));
-      p2 = add(p2, mulr(cj(vq[r]), v[r]));
-    }
-    p1 = bsum(p1, sh);
-    p2 = bsum(p2, sh);
-    if (tid == 0) { s_t1[q] = p1; s_t2[q] = p2; }
+struct TriWs {
+  // byte offsets inside one problem's workspace
+  __host__ __device__ static size_t xv(int) { return 0; }
+  __host__ __device__ static size_t P(int n) { return align(sizeof(T) * (size_t)n); }
+  __host__ __device__ static size_t pa(int n) { return P(n) + align(sizeof(T) * (size_t)nbt(n) * n); }
+  __host__ __device__ static size_t pc(int n) { return pa(n) + align(sizeof(double) * (size_t)nbt(n)); }
+  __host__ __device__ static size_t fa(int n) { return pc(n) + align(sizeof(T) * (size_t)ntile(n) * (1 + 2 * NB)); }
+  __host__ __device__ static size_t fc(int n) { return fa(n) + 256; }
+  __host__ __device__ static size_t cnt(int n) { return fc(n) + align(sizeof(T) * (1 + 2 * NB)); }
+  __host__ __device__ static size_t bytes(int n) { return cnt(n) + 256; }
+  __host__ __device__ static int nbt(int n) { return (n + TT - 1) / TT; }
+  __host__ __device__ static int ntile(int n) { return nbt(n) * (nbt(n) + 1) / 2; }
+  __host__ __device__ static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
+};
+
+template <typename T>
+__device__ inline T vload(const T* p) {
+  if constexpr (sizeof(T) == 16) {
+    const volatile double* q = reinterpret_cast<const volatile double*>(p);
+    return T{q[0], q[1]};
+  } else {
+    return *reinterpret_cast<const volatile double*>(p);
   }
-  __syncthreads();
-  T dotp = EigT<T>::zero();
-  for (int r = ip + 1 + tid; r < n; r += 256) {
-    T acc = Y[r];
-    for (int q = 0; q < pp; ++q) {
-      acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], s_t1[q]));
-      acc = sub(acc, mulr(W[(long)r * NB + q], s_t2[q]));
-    }
-    acc = mulr(taup, acc);
-    W[(long)r * NB + pp] = acc;
-    dotp = add(dotp, mulr(cj(acc), v[r]));
-  }
-  dotp = bsum(dotp, sh);
-  const T alpha = mulr(scl(-0.5, taup), dotp);
-  for (int r = ip + 1 + tid; r < n; r += 256)
-    W[(long)r * NB + pp] = add(W[(long)r * NB + pp], mulr(alpha, v[r]));
-  for (int r = tid; r <= ip && r < n; r += 256) W[(long)r * NB + pp] = EigT<T>::zero();
-  __syncthreads();
 }
 
-// Column i: a(i:n, i) -= V(i:n, j0:i) conj(W(i, 0:p)) + W(i:n, 0:p) conj(V(i, j0:i)),
-// d_i = Re a(i,i), then the reflector that maps a(i+1:n, i) to beta e_1 (beta
-// real, LAPACK larfg convention: H = I - tau v v^H, v(i+1) = 1).
+// Reflector scalars from ||x(i+2:n)||^2 and alpha = x(i+1).
+template <typename T>
+__device__ inline void reflector(T alpha, double xn2, double& beta, T& tau, T& scal) {
+  const double ar = re(alpha), ai = im(alpha);
+  if (xn2 == 0.0 && ai == 0.0) {
+    beta = ar;
+    tau = EigT<T>::zero();
+    scal = EigT<T>::zero();
+    return;
+  }
+  const double nrm = sqrt(ar * ar + ai * ai + xn2);
+  beta = ar >= 0.0 ? -nrm : nrm;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    tau = (beta - ar) / beta;
+    scal = 1.0 / (ar - beta);
+  } else {
+    tau = cd{(beta - ar) / beta, -ai / beta};
+    const double xr = ar - beta, xi = ai, den = xr * xr + xi * xi;
+    scal = cd{xr / den, -xi / den};
+  }
+}
+
 template <typename T, int NB>
-__device__ void column_reflect(const TriArgs& a, int b, int i, int j0, double* sh, T* s_vrow,
-                               T* s_wrow, T* s_scal) {
-  const int n = a.n, tid = threadIdx.x;
+__global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int icol, int ifin, int j0) {
+  __shared__ T s_t1[NB], s_t2[NB], s_vrow[NB], s_wrow[NB];
+  __shared__ T s_alpha, s_wi;
+  __shared__ double red[256];
+  __shared__ int s_last;
+  const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
+  char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
+  T* xv = reinterpret_cast<T*>(ws + TriWs<T, NB>::xv(n));
+  const T* P = reinterpret_cast<const T*>(ws + TriWs<T, NB>::P(n));
+  double* pa = reinterpret_cast<double*>(ws + TriWs<T, NB>::pa(n));
+  double* fa = reinterpret_cast<double*>(ws + TriWs<T, NB>::fa(n));
+  const T* fc = reinterpret_cast<const T*>(ws + TriWs<T, NB>::fc(n));
+  int* cnt = reinterpret_cast<int*>(ws + TriWs<T, NB>::cnt(n));
   T* G = reinterpret_cast<T*>(a.G) + b * a.sG;
   T* V = reinterpret_cast<T*>(a.Vt) + b * a.sVt;
-  const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
-  T* tau = reinterpret_cast<T*>(a.tau) + b * a.stau;
-  double* d = a.d + b * a.sde;
-  double* e = a.e + b * a.sde;
+  T* W = reinterpret_cast<T*>(a.Wp) + b * a.sWp;
+  const T* Y = reinterpret_cast<const T*>(a.y) + b * a.sy;
   const long ldg = a.ldg;
-  const int p = i - j0;
+  const int rlo = row0 + blockIdx.x * TT;          // first row of this block
+  const int r = rlo + (tid & (TT - 1));            // row of this thread (4 threads per row)
+  const int part = tid >> 6;                       // 0..3
+  const bool rv = r < n;
+
+  // ---- finish w_ifin (panel column pp = ifin - j0) on rows >= ifin + 1 = row0
+  if (ifin >= 0) {
+    const int pp = ifin - j0;
+    if (tid < pp) { s_t1[tid] = fc[1 + tid]; s_t2[tid] = fc[1 + NB + tid]; }
+    __syncthreads();
+    if (tid == 0) {
+      const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ifin];
+      T yv = fc[0];
+      for (int q = 0; q < pp; ++q) {
+        yv = sub(yv, mulr(cj(s_t1[q]), s_t2[q]));
+        yv = sub(yv, mulr(cj(s_t2[q]), s_t1[q]));
+      }
+      s_alpha = scl(-0.5 * nrm2(taup), yv);
+    }
+    __syncthreads();
+    const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ifin];
+    const T alpha = s_alpha;
+    const int tb0 = (ifin + 1) / TT, nbt = TriWs<T, NB>::nbt(n);
+    const T* vfin = V + (long)ifin * n;
+    // w for this thread's row (4 threads share a row: each sums a quarter)
+    T acc = EigT<T>::zero();
+    if (rv) {
+      for (int t = tb0 + part; t < nbt; t += 4) acc = add(acc, P[(long)t * n + r]);
+      for (int q = part; q < pp; q += 4) {
+        acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], s_t1[q]));
+        acc = sub(acc, mulr(W[(long)r * NB + q], s_t2[q]));
+      }
+    }
+    // combine the 4 parts through LDS (complex as two doubles)
+    double* rr = red;
+    __syncthreads();
+    rr[tid] = re(acc);
+    __syncthreads();
+    double sre = 0.0, sim = 0.0;
+    if (part == 0) sre = rr[tid] + rr[tid + 64] + rr[tid + 128] + rr[tid + 192];
+    __syncthreads();
+    rr[tid] = im(acc);
+    __syncthreads();
+    if (part == 0) sim = rr[tid] + rr[tid + 64] + rr[tid + 128] + rr[tid + 192];
+    if (part == 0 && rv) {
+      T yy;
+      if constexpr (sizeof(T) == 16) yy = cd{sre, sim}; else yy = sre;
+      const T w = add(mulr(taup, yy), mulr(alpha, vfin[r]));
+      W[(long)r * NB + pp] = w;
+    }
+    // rows above ifin + 1 carry a zero w
+    if (blockIdx.x == 0)
+      for (int q = tid; q < row0; q += 256) W[(long)q * NB + pp] = EigT<T>::zero();
+    __syncthreads();
+  }
+  if (icol < 0) return;
+
+  // ---- column update of icol (row0 == icol) with p panel columns
+  const int i = icol, p = i - j0;
+  // row i of V and W (W(i, p-1) was just finished by the workgroup owning row i:
+  // recompute it here so that every workgroup has it without a grid-wide wait)
   if (tid < p) {
     s_vrow[tid] = V[(long)(j0 + tid) * n + i];
-    s_wrow[tid] = W[(long)i * NB + tid];
+    if (tid < p - 1 || ifin < 0) s_wrow[tid] = W[(long)i * NB + tid];
+  }
+  if (ifin >= 0 && p >= 1) {
+    // W(i, p-1): same formula as above for row i
+    const int pp = p - 1;
+    T acc = EigT<T>::zero();
+    const int tb0 = (ifin + 1) / TT, nbt = TriWs<T, NB>::nbt(n);
+    for (int t = tb0 + tid; t < nbt; t += 256) acc = add(acc, P[(long)t * n + i]);
+    if (tid < pp) {
+      acc = sub(acc, mulr(V[(long)(j0 + tid) * n + i], s_t1[tid]));
+      acc = sub(acc, mulr(W[(long)i * NB + tid], s_t2[tid]));
+    }
+    __syncthreads();
+    red[tid] = re(acc);
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    const double sr = red[0];
+    __syncthreads();
+    red[tid] = im(acc);
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ifin];
+      T yy;
+      if constexpr (sizeof(T) == 16) yy = cd{sr, red[0]}; else yy = sr;
+      s_wi = add(mulr(taup, yy), mulr(s_alpha, V[(long)ifin * n + i]));
+      s_wrow[pp] = s_wi;
+    }
   }
   __syncthreads();
   double xn2 = 0.0;
-  for (int r = i + tid; r < n; r += 256) {
+  if (part == 0 && rv) {
     T acc = G[(long)r * ldg + i];
     for (int q = 0; q < p; ++q) {
       acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], cj(s_wrow[q])));
       acc = sub(acc, mulr(W[(long)r * NB + q], cj(s_vrow[q])));
     }
     G[(long)r * ldg + i] = acc;
-    if (r >= i + 2) xn2 += nrm2(acc);
+    if (r >= i + 1) xv[r] = acc;
+    if (r >= i + 2) xn2 = nrm2(acc);
+    if (r == i) a.d[b * a.sde + i] = re(acc);
   }
-  xn2 = block_sum(xn2, sh);
+  // ||x||^2 partial of this block, then the last block reduces all partials
+  red[tid] = xn2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (i + 1 >= n) return;
   if (tid == 0) {
-    d[i] = re(G[(long)i * ldg + i]);
-    if (i + 1 < n) {
-      const T alpha = G[(long)(i + 1) * ldg + i];
-      const double ar = re(alpha), ai = im(alpha);
-      T tv = EigT<T>::zero(), scal = EigT<T>::zero();
-      double beta;
-      if (xn2 == 0.0 && ai == 0.0) {
-        beta = ar;  // nothing to annihilate: H = I
-      } else {
-        const double nrm = sqrt(ar * ar + ai * ai + xn2);
-        beta = ar >= 0.0 ? -nrm : nrm;
-        // tau = (beta - alpha) / beta,  scal = 1 / (alpha - beta)
-        if constexpr (sizeof(T) == sizeof(double)) {
-          tv = (beta - ar) / beta;
-          scal = 1.0 / (ar - beta);
-        } else {
-          tv = cd{(beta - ar) / beta, -ai / beta};
-          const double xr = ar - beta, xi = ai, den = xr * xr + xi * xi;
-          scal = cd{xr / den, -xi / den};
-        }
-      }
-      e[i] = beta;
-      tau[i] = tv;
-      *s_scal = scal;
-    } else {
-      tau[i] = EigT<T>::zero();
+    pa[blockIdx.x] = red[0];
+    __threadfence();
+    const int ticket = atomicAdd(&cnt[0], 1);
+    s_last = (ticket == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();
+    const volatile double* vp = pa;
+    double tot = 0.0;
+    for (int k = 0; k < (int)gridDim.x; ++k) tot += vp[k];
+    fa[0] = tot;
+    cnt[0] = 0;
+  }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0) {
+  __shared__ T s_vR[TT], s_vC[TT];
+  __shared__ T s_q[4];
+  __shared__ T s_colsum[4][TT];
+  __shared__ T s_tt[2 * NB];
+  __shared__ int s_last;
+  __shared__ T s_scal;
+  const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
+  const int p = i - j0;
+  char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
+  const T* xv = reinterpret_cast<const T*>(ws + TriWs<T, NB>::xv(n));
+  T* P = reinterpret_cast<T*>(ws + TriWs<T, NB>::P(n));
+  T* pc = reinterpret_cast<T*>(ws + TriWs<T, NB>::pc(n));
+  const double* fa = reinterpret_cast<const double*>(ws + TriWs<T, NB>::fa(n));
+  T* fc = reinterpret_cast<T*>(ws + TriWs<T, NB>::fc(n));
+  int* cnt = reinterpret_cast<int*>(ws + TriWs<T, NB>::cnt(n));
+  const T* G = reinterpret_cast<const T*>(a.G) + b * a.sG;
+  T* V = reinterpret_cast<T*>(a.Vt) + b * a.sVt;
+  const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
+  // tile (R, C), C <= R, among the active blocks [b0, nbt)
+  const int b0 = (i + 1) / TT;
+  int k = blockIdx.x, Rp = 0;
+  while ((Rp + 1) * (Rp + 2) / 2 <= k) ++Rp;
+  const int Cp = k - Rp * (Rp + 1) / 2;
+  const int R = b0 + Rp, C = b0 + Cp;
+  const bool diag = (R == C);
+  // reflector scalars (every workgroup computes them from the reduced norm)
+  if (tid == 0) {
+    double beta;
+    T tv, sc;
+    reflector(xv[i + 1], fa[0], beta, tv, sc);
+    s_scal = sc;
+    if (k == 0) {
+      a.e[b * a.sde + i] = beta;
+      reinterpret_cast<T*>(a.tau)[b * a.stau + i] = tv;
     }
   }
   __syncthreads();
-  if (i + 1 < n) {
-    const T scal = *s_scal;
-    T* v = V + (long)i * n;
-    for (int r = tid; r < n; r += 256) {
-      T val;
-      if (r <= i) val = EigT<T>::zero();
-      else if (r == i + 1) val = EigT<T>::one();
-      else val = mulr(G[(long)r * ldg + i], scal);
-      v[r] = val;
+  const T scal = s_scal;
+  auto vval = [&](int c) -> T {
+    if (c <= i || c >= n) return EigT<T>::zero();
+    if (c == i + 1) return EigT<T>::one();
+    return mulr(xv[c], scal);
+  };
+  if (tid < TT) {
+    s_vR[tid] = vval(R * TT + tid);
+    s_vC[tid] = vval(C * TT + tid);
+  }
+  __syncthreads();
+  // reflector i into Vt (diagonal tiles own their rows; tile 0 zeroes the rows above)
+  if (diag && tid < TT) {
+    const int rr = R * TT + tid;
+    if (rr < n) V[(long)i * n + rr] = s_vR[tid];
+  }
+  if (k == 0)
+    for (int rr = tid; rr < b0 * TT; rr += 256) V[(long)i * n + rr] = EigT<T>::zero();
+  // load the tile: thread (cl, rg) holds rows rg + 4k, column cl
+  const int cl = tid & 63, rg = tid >> 6;
+  const int c = C * TT + cl;
+  const bool cok = (c > i) && (c < n);
+  T colacc = EigT<T>::zero();
+  T qacc = EigT<T>::zero();
+#pragma unroll 4
+  for (int kk = 0; kk < TT / 4; ++kk) {
+    const int rl = rg + 4 * kk;
+    const int r = R * TT + rl;
+    T g = EigT<T>::zero();
+    if (cok && r > i && r < n) g = G[(long)r * a.ldg + c];
+    // row sum: y_R(r) += g v_C(c)
+    T rs = wsum(mulr(g, s_vC[cl]));
+    if (cl == 0 && r < n) {
+      P[(long)C * n + r] = rs;   // the whole wave holds the row sum; lane 0 writes
+      qacc = add(qacc, mulr(cj(s_vR[rl]), rs));
     }
+    // column sum: y_C(c) += conj(g) v_R(r)
+    colacc = add(colacc, mulr(cj(g), s_vR[rl]));
   }
-}
-
-// One workgroup per problem: finish w of column i_fin (if >= 0), then update
-// and reflect column i_col (if >= 0).
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void tri_small_kernel(TriArgs a, int i_fin, int i_col, int j0) {
-  __shared__ double sh[16];
-  __shared__ T s_t1[NB], s_t2[NB], s_vrow[NB], s_wrow[NB], s_scal;
-  const int b = blockIdx.x;
-  if (i_fin >= 0) finish_w<T, NB>(a, b, i_fin, j0, sh, s_t1, s_t2);
-  if (i_col >= 0) column_reflect<T, NB>(a, b, i_col, j0, sh, s_vrow, s_wrow, &s_scal);
-}
-
-// y(r) = sum_{c > i} G(r, c) v_i(c) for r > i: full Hermitian storage of the
-// trailing matrix as it stood at the start of the panel.  One wave per row,
-// lanes stride over the (contiguous) columns.
-template <typename T>
-__global__ __launch_bounds__(256) void tri_hemv_kernel(TriArgs a, int i) {
-  const int b = blockIdx.y, n = a.n;
-  const T* G = reinterpret_cast<const T*>(a.G) + b * a.sG;
-  const T* v = reinterpret_cast<const T*>(a.Vt) + b * a.sVt + (long)i * n;
-  T* Y = reinterpret_cast<T*>(a.y) + b * a.sy;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int r = i + 1 + blockIdx.x * 16 + wid * 4 + rr;
-    if (r >= n) break;
+  // wave 0..3 lane 0 hold quadratic-form pieces for their rows
+  if (cl == 0) s_q[rg] = qacc;
+  s_colsum[rg][cl] = colacc;
+  __syncthreads();
+  if (!diag && tid < TT) {
+    T cs = add(add(s_colsum[0][tid], s_colsum[1][tid]), add(s_colsum[2][tid], s_colsum[3][tid]));
+    const int cc = C * TT + tid;
+    if (cc < n) P[(long)R * n + cc] = cs;
+  }
+  // partials of this tile: quadratic form, and t1 = W^H v, t2 = V^H v on diagonal tiles
+  T* mypc = pc + (long)k * (1 + 2 * NB);
+  if (tid == 0) {
+    T q = add(add(s_q[0], s_q[1]), add(s_q[2], s_q[3]));
+    if (!diag) q = add(q, cj(q));
+    mypc[0] = q;
+  }
+  if (tid < 2 * NB) {
+    const int q = tid % NB;
+    const bool isw = tid < NB;
     T acc = EigT<T>::zero();
-    const T* grow = G + (long)r * a.ldg;
-    for (int c = i + 1 + lane; c < n; c += 64) acc = add(acc, mulr(grow[c], v[c]));
-    acc = wsum(acc);
-    if (lane == 0) Y[r] = acc;
+    if (diag && q < p) {
+      for (int rl = 0; rl < TT; ++rl) {
+        const int r = R * TT + rl;
+        if (r <= i || r >= n) continue;
+        const T other = isw ? W[(long)r * NB + q] : V[(long)(j0 + q) * n + r];
+        acc = add(acc, mulr(cj(other), s_vR[rl]));
+      }
+    }
+    mypc[1 + tid] = acc;
   }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const int ticket = atomicAdd(&cnt[1], 1);
+    s_last = (ticket == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    if (tid < 1 + 2 * NB) {
+      T acc = EigT<T>::zero();
+      for (int kk = 0; kk < (int)gridDim.x; ++kk) acc = add(acc, vload(pc + (long)kk * (1 + 2 * NB) + tid));
+      fc[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) cnt[1] = 0;
+  }
+  (void)s_tt;
 }
 
 template <typename T, int NB>
 static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
   const int n = a.n;
   const size_t es = sizeof(T);
+  const int nbt = TriWs<T, NB>::nbt(n);
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int pe = min(NB, n - j0);
     for (int p = 0; p < pe; ++p) {
       const int i = j0 + p;
-      hipLaunchKernelGGL((tri_small_kernel<T, NB>), dim3(batch), dim3(256), 0, s, a,
-                         p > 0 ? i - 1 : -1, i, j0);
+      const int rowsA = n - i;
+      hipLaunchKernelGGL((tri_colA_kernel<T, NB>), dim3((rowsA + TT - 1) / TT, batch), dim3(256), 0, s, a, i, i,
+                         p > 0 ? i - 1 : -1, j0);
       if (i + 1 < n) {
-        dim3 grid((n - i - 1 + 15) / 16, batch);
-        // algorithmic bytes: the trailing matrix read once per problem
-        ProfScope ps(s, (double)(n - i - 1) * (n - i - 1) * sizeof(T) * batch, "hemv");
-        hipLaunchKernelGGL(tri_hemv_kernel<T>, grid, dim3(256), 0, s, a, i);
+        const int nact = nbt - (i + 1) / TT;
+        // algorithmic bytes: the lower triangle of the trailing matrix read once
+        ProfScope ps(s, 0.5 * (double)(n - i - 1) * (n - i) * sizeof(T) * batch, "hemv");
+        hipLaunchKernelGGL((tri_colC_kernel<T, NB>), dim3(nact * (nact + 1) / 2, batch), dim3(256), 0, s, a, i, j0);
       }
     }
     const int t = j0 + pe;
     if (t < n) {
-      // finish w of the panel's last column (no column update: i = t is the next panel's)
-      hipLaunchKernelGGL((tri_small_kernel<T, NB>), dim3(batch), dim3(256), 0, s, a, t - 1, -1, j0);
-      // G(t:n, t:n) -= V W^H + W V^H over the panel columns
+      // finish w of the panel's last column, then the trailing update
+      hipLaunchKernelGGL((tri_colA_kernel<T, NB>), dim3((n - t + TT - 1) / TT, batch), dim3(256), 0, s, a, t, -1,
+                         t - 1, j0);
       const int m = n - t;
       char* G = reinterpret_cast<char*>(a.G);
       char* V = reinterpret_cast<char*>(a.Vt);
@@ -254,10 +457,17 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
+size_t tridiag_ws_bytes(int dtype, int n) {
+  return dtype == C128 ? TriWs<cd, TRIDIAG_NB>::bytes(n) : TriWs<double, TRIDIAG_NB>::bytes(n);
+}
+
 hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s) {
+  if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
+  if (a.sws < (long long)tridiag_ws_bytes(dtype, a.n)) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(a.ws, 0, (size_t)a.sws * batch, s);
+  if (e != hipSuccess) return e;
   if (dtype == C128) return tridiag_impl<cd, TRIDIAG_NB>(a, batch, s);
-  if (dtype == F64) return tridiag_impl<double, TRIDIAG_NB>(a, batch, s);
-  return hipErrorInvalidValue;
+  return tridiag_impl<double, TRIDIAG_NB>(a, batch, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,7 +20,11 @@ struct TriArgs {
   void* Vt; long long sVt;
   void* Wp; long long sWp;
   void* y; long long sy;
+  void* ws; long long sws;   // per-problem workspace of tridiag_ws_bytes(n) bytes, counters zeroed
 };
+
+// Bytes of the per-problem workspace of the reduction (zero-fill before use).
+size_t tridiag_ws_bytes(int dtype, int n);
 
 // G = Q T Q^H (dtype C128 or F64).
 hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s);

@@ -157,6 +157,9 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   TriArgs ta{};
   ta.n = ng; ta.G = Gk; ta.ldg = ng; ta.sG = sG; ta.d = d; ta.e = e; ta.sde = ng; ta.tau = tau; ta.stau = ng;
   ta.Vt = Vt; ta.sVt = sG; ta.Wp = Wp; ta.sWp = (long long)ng * TRIDIAG_NB; ta.y = yv; ta.sy = ng;
+  ta.sws = (long long)tridiag_ws_bytes(wdt, ng);
+  ta.ws = ctx->arena.get((size_t)ta.sws * nb);
+  if (!ta.ws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * (size_t)ng * nb, s));
   TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
   SK_ARENA(lam, double, (size_t)kk * nb);

@@ -95,6 +95,9 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   ta.Vt = Vt; ta.sVt = sG;
   ta.Wp = Wp; ta.sWp = (long long)ng * TRIDIAG_NB;
   ta.y = y; ta.sy = ng;
+  ta.sws = (long long)tridiag_ws_bytes(wdt, ng);
+  ta.ws = ctx->arena.get((size_t)ta.sws * nb);
+  if (!ta.ws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * (size_t)ng * nb, s));
   TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
   // top eigenvalues and the truncation rule
@@ -486,6 +489,9 @@ tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v) {
   ARENA(y, char, es * n);
   TriArgs ta{};
   ta.n = n; ta.G = G; ta.ldg = n; ta.d = d; ta.e = e; ta.tau = tau; ta.Vt = Vt; ta.Wp = Wp; ta.y = y;
+  ta.sws = (long long)tridiag_ws_bytes(dt, n);
+  ta.ws = ctx->arena.get((size_t)ta.sws);
+  if (!ta.ws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * n, s));
   TCI_CHECK_HIP(tridiagonalize(dt, ta, 1, s));
   ARENA(lam, double, n);

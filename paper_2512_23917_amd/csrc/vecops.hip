@@ -176,16 +176,18 @@ __global__ __launch_bounds__(256) void multidot_partial_kernel(const cd* V, int 
   }
 }
 
-__global__ void multidot_final_kernel(const double* partial, int nparts, int nv, double* out) {
-  const int q = threadIdx.x;
-  if (q >= nv) return;
-  double r = 0.0, im = 0.0;
-  for (int b = 0; b < nparts; ++b) {
-    r += partial[((long long)b * MD_MAXV + q) * 2 + 0];
-    im += partial[((long long)b * MD_MAXV + q) * 2 + 1];
+// One workgroup per coefficient q: thread b loads partial b, fixed-order tree sum.
+__global__ __launch_bounds__(256) void multidot_final_kernel(const double* partial, int nparts, int nv, double* out) {
+  __shared__ double sr[256], si[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  sr[t] = t < nparts ? partial[((long long)t * MD_MAXV + q) * 2 + 0] : 0.0;
+  si[t] = t < nparts ? partial[((long long)t * MD_MAXV + q) * 2 + 1] : 0.0;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) { sr[t] += sr[t + off]; si[t] += si[t + off]; }
+    __syncthreads();
   }
-  out[2 * q] = r;
-  out[2 * q + 1] = im;
+  if (t == 0) { out[2 * q] = sr[0]; out[2 * q + 1] = si[0]; }
 }
 
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
@@ -194,7 +196,7 @@ hipError_t multidot(const void* V, int nv, const void* w, long long n, double* p
   if (nv > MD_MAXV) return hipErrorInvalidValue;
   const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(MD_BLOCKS, (n + 255) / 256));
   hipLaunchKernelGGL(multidot_partial_kernel, dim3(g), dim3(256), 0, s, (const cd*)V, nv, (const cd*)w, n, partial);
-  hipLaunchKernelGGL(multidot_final_kernel, dim3(1), dim3(64), 0, s, partial, (int)g, nv, out);
+  hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
 

@@ -59,17 +59,24 @@ def test_heff_matvec_real(T, ctx):
     assert rel_fro(y, ref) < 1e-13
 
 
-@pytest.mark.parametrize("prec,tol", [("PREC_FP32", 3e-6), ("PREC_BF16X3", 3e-5)])
-def test_heff_matvec_mixed(T, ctx, prec, tol):
-    left, w, right, x = env(24, 9)
-    c64 = lambda a: np.asarray(a).astype(np.complex64)
+@pytest.mark.parametrize("prec,tol,chi,complex_", [("PREC_FP32", 3e-6, 24, True), ("PREC_BF16X3", 3e-5, 24, True),
+                                                   ("PREC_BF16X3", 3e-5, 200, True),
+                                                   ("PREC_BF16X3", 3e-5, 72, False),
+                                                   ("PREC_FP32", 3e-6, 72, False)])
+def test_heff_matvec_mixed(T, ctx, prec, tol, chi, complex_):
+    """chi = 200: the environment planes are 1000 x 200 and the vector planes
+    800 x 200, i.e. ragged in every padded dimension of the plane GEMM."""
+    left, w, right, x = env(chi, 9, complex_)
+    lo = np.complex64 if complex_ else np.float32
+    dt = T.C64 if complex_ else T.F32
+    c64 = lambda a: np.asarray(a).astype(lo)
     ref = odmrg.heff_apply(c64(left).astype(np.complex128), c64(w).astype(np.complex128),
                            c64(w).astype(np.complex128), c64(right).astype(np.complex128),
                            c64(x).astype(np.complex128))
     ctx.set_precision(getattr(T, prec))
     try:
-        y = T.heff_matvec(ctx, up(T, ctx, c64(left), T.C64), up(T, ctx, c64(w), T.C64), up(T, ctx, c64(w), T.C64),
-                          up(T, ctx, c64(right), T.C64), up(T, ctx, c64(x), T.C64)).numpy()
+        y = T.heff_matvec(ctx, up(T, ctx, c64(left), dt), up(T, ctx, c64(w), dt), up(T, ctx, c64(w), dt),
+                          up(T, ctx, c64(right), dt), up(T, ctx, c64(x), dt)).numpy()
     finally:
         ctx.set_precision(T.PREC_FP32)
     assert rel_fro(y, ref) < tol
@@ -104,16 +111,20 @@ def test_lanczos_matches_oracle(T, ctx, chi, nmv):
         assert e == pytest.approx(np.linalg.eigvalsh(h)[0], rel=1e-11)
 
 
-def test_lanczos_mixed_energy(T, ctx):
+@pytest.mark.parametrize("prec", ["PREC_FP32", "PREC_BF16X3"])
+def test_lanczos_mixed_energy(T, ctx, prec):
     chi = 16
     left, w, right, x = env(chi, 77)
     mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
     e_ref, psi_ref, _, _ = odmrg.lanczos_ground(mv, x, n_matvec=20)
     c64 = lambda a: np.asarray(a).astype(np.complex64)
     th = up(T, ctx, c64(x), T.C64)
-    ctx.set_precision(T.PREC_FP32)
-    e = T.lanczos_ground(ctx, up(T, ctx, c64(left), T.C64), up(T, ctx, c64(w), T.C64), up(T, ctx, c64(w), T.C64),
-                         up(T, ctx, c64(right), T.C64), th, 20)
+    ctx.set_precision(getattr(T, prec))
+    try:
+        e = T.lanczos_ground(ctx, up(T, ctx, c64(left), T.C64), up(T, ctx, c64(w), T.C64),
+                             up(T, ctx, c64(w), T.C64), up(T, ctx, c64(right), T.C64), th, 20)
+    finally:
+        ctx.set_precision(T.PREC_FP32)
     assert e == pytest.approx(e_ref, rel=1e-5)
 
 
