@@ -1,0 +1,185 @@
+"""Training set and GPU training loop of the sketch-rank predictor.
+
+One sample is a pair of neighbouring updates of a sweep: the input is the
+feature row of the previous bond's kept spectrum (computed on the GPU by
+``tci_sketch_features``), the target is log2 chi*(eps) of the current bond,
+where chi* is the bond dimension that the truncation rule keeps when it is
+not capped.  The network predicts the 0.9-quantile of that target (pinball
+loss), and the library turns a prediction y into the sketch rank
+k = 32 ceil((1.5 2^y + 32) / 32), or into the plain truncated SVD when
+y > log2 chi_max or k > 0.6 n.
+
+Spectra of three families, each with a drifting parameter along a sweep of
+``length`` bonds (n singular values, normalised to unit 2-norm):
+  * power law   s_k ~ k^-alpha,  alpha ~ U[a_lo, a_hi], drift N(0, 0.05^2),
+    clipped to [a_lo, a_hi] (the learned-sketch workload uses alpha in [1, 3]);
+  * exponential s_k ~ exp(-k / kappa), log10 kappa ~ U[1, 3.5], drift N(0, 0.05^2);
+  * quarter circle: singular values of a square Gaussian matrix (the dense
+    workload with Gaussian site tensors), whose empirical distribution
+    follows the density sqrt(4 - x^2) / pi on [0, 2]; no drift.
+The spectra are the exact singular values of the matrices these workloads
+build (theta = U diag(s) V^T with orthogonal U, V); a GPU test checks the
+library's truncated SVD against them.
+
+Training: Adam (lr 1e-3), batch 256, 30 epochs, 90/10 train/validation
+split, all on the GPU through ``tci_sketch_train_step`` (hand-written
+forward, backward and Adam kernels).
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+
+import numpy as np
+
+from . import tci
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sketch_mlp.bin")
+
+
+def power_law(n: int, alpha: float) -> np.ndarray:
+    s = np.arange(1, n + 1, dtype=np.float64) ** (-alpha)
+    return s / np.linalg.norm(s)
+
+
+def exp_decay(n: int, kappa: float) -> np.ndarray:
+    s = np.exp(-np.arange(n, dtype=np.float64) / kappa)
+    return s / np.linalg.norm(s)
+
+
+def quarter_circle(n: int) -> np.ndarray:
+    """Descending quantiles x_j = F^-1(1 - (j + 1/2) / n) of the density
+    sqrt(4 - x^2) / pi on [0, 2], with F(x) = (x sqrt(4 - x^2) / 2 + 2 asin(x / 2)) / pi
+    inverted by bisection."""
+    p = 1.0 - (np.arange(n, dtype=np.float64) + 0.5) / n
+    lo, hi = np.zeros(n), np.full(n, 2.0)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        f = (mid * np.sqrt(np.maximum(4.0 - mid * mid, 0.0)) / 2.0 + 2.0 * np.arcsin(mid / 2.0)) / math.pi
+        below = f < p
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    s = 0.5 * (lo + hi)
+    return s / np.linalg.norm(s)
+
+
+def chi_star(s: np.ndarray, eps: float) -> int:
+    """Smallest chi >= 1 with sum_{k >= chi} s_k^2 <= eps * sum s_k^2 (no cap)."""
+    w = s * s
+    tail = np.concatenate([np.cumsum(w[::-1])[::-1], [0.0]])
+    ok = np.nonzero(tail[1:] <= eps * tail[0])[0]
+    return int(ok[0]) + 1 if len(ok) else len(s)
+
+
+def sweep_spectra(rng: np.random.Generator, family: str, n: int, length: int, alpha_range=(1.0, 3.0)):
+    if family == "power":
+        lo, hi = alpha_range
+        a = rng.uniform(lo, hi)
+        out = []
+        for _ in range(length):
+            out.append(power_law(n, a))
+            a = float(np.clip(a + rng.normal(0.0, 0.05), lo, hi))
+        return out
+    if family == "exp":
+        lk = rng.uniform(1.0, 3.5)
+        out = []
+        for _ in range(length):
+            out.append(exp_decay(n, 10.0 ** lk))
+            lk = float(np.clip(lk + rng.normal(0.0, 0.05), 1.0, 3.5))
+        return out
+    if family == "qc":
+        return [quarter_circle(n)] * length
+    raise ValueError(family)
+
+
+def make_pairs(n_samples: int, seed: int, n: int = 2048, chi_max: int = 1024, eps: float = 1e-8,
+               mix=(0.8, 0.15, 0.05), length: int = 8, alpha_range=(1.0, 3.0)):
+    """Returns (prev kept spectra list, targets log2 chi*) for n_samples pairs."""
+    rng = np.random.default_rng(seed)
+    fams = ["power", "exp", "qc"]
+    prev, targ = [], []
+    qc_cache = None
+    while len(prev) < n_samples:
+        fam = fams[rng.choice(3, p=np.asarray(mix) / np.sum(mix))]
+        if fam == "qc":
+            if qc_cache is None:
+                qc_cache = sweep_spectra(rng, "qc", n, length)
+            seq = qc_cache
+        else:
+            seq = sweep_spectra(rng, fam, n, length, alpha_range)
+        chis = [chi_star(s, eps) for s in seq]
+        for t in range(1, length):
+            if len(prev) >= n_samples:
+                break
+            keep = min(chis[t - 1], chi_max)
+            sp = seq[t - 1][:keep]
+            prev.append(sp / np.linalg.norm(sp))
+            targ.append(math.log2(chis[t]))
+    return prev, np.asarray(targ)
+
+
+def features(ctx, spectra, chi_max: int, d: int, eps: float, chunk: int = 2048):
+    import torch
+    rows = [tci.sketch_features(ctx, spectra[i:i + chunk], chi_max, d, eps) for i in range(0, len(spectra), chunk)]
+    return torch.cat(rows, 0)
+
+
+def make_dataset(ctx, n_samples: int, seed: int, n: int = 2048, chi_max: int = 1024, d: int = 2, eps: float = 1e-8,
+                 **kw):
+    import torch
+    prev, targ = make_pairs(n_samples, seed, n, chi_max, eps, **kw)
+    X = features(ctx, prev, chi_max, d, eps)
+    T = torch.as_tensor(targ, dtype=torch.float32, device=ctx.torch_device)
+    return X, T
+
+
+def pinball(y, t, tau: float = 0.9) -> float:
+    import torch
+    u = t.double() - y.double()
+    return float(torch.maximum(tau * u, (tau - 1.0) * u).mean())
+
+
+def train(ctx, X, T, epochs: int = 30, batch: int = 256, lr: float = 1e-3, seed: int = 0, val_frac: float = 0.1,
+          model=None):
+    """Trains on the GPU; returns (model, history) with per-epoch mean train
+    loss and validation pinball loss."""
+    import torch
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    nval = int(round(val_frac * X.shape[0]))
+    perm = torch.randperm(X.shape[0], generator=g).to(X.device)
+    Xv, Tv = X[perm[:nval]].contiguous(), T[perm[:nval]].contiguous()
+    Xt, Tt = X[perm[nval:]].contiguous(), T[perm[nval:]].contiguous()
+    m = model if model is not None else tci.SketchModel(ctx, seed=seed)
+    hist = {"train": [], "val": []}
+    for _ in range(epochs):
+        order = torch.randperm(Xt.shape[0], generator=g).to(X.device)
+        tot, cnt = 0.0, 0
+        for i in range(0, Xt.shape[0] - batch + 1, batch):
+            idx = order[i:i + batch]
+            xb, tb = Xt[idx].contiguous(), Tt[idx].contiguous()
+            tot += m.train_step(xb, tb, lr)
+            cnt += 1
+        hist["train"].append(tot / max(cnt, 1))
+        hist["val"].append(pinball(m.predict(Xv), Tv) if nval else float("nan"))
+    return m, hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="Train the sketch-rank predictor on the GPU")
+    ap.add_argument("--samples", type=int, default=50000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    args = ap.parse_args(argv)
+    ctx = tci.Context(0)
+    X, T = make_dataset(ctx, args.samples, args.seed)
+    m, hist = train(ctx, X, T, epochs=args.epochs, seed=args.seed)
+    m.save(args.out)
+    print(f"samples {args.samples}  epochs {args.epochs}  final train {hist['train'][-1]:.4f}  "
+          f"val {hist['val'][-1]:.4f}  -> {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

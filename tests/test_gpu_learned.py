@@ -1,0 +1,133 @@
+"""The learned sketch rank: GPU training on bond-spectrum sequences, and what
+the trained network gains over the method without it.
+
+Training runs entirely through the library's FP32 forward / backward / Adam
+kernels; its gradients are pinned against the FP64 oracle elsewhere.  The
+gain test uses held-out power-law sequences (2048 x 2048 float32 theta with
+s_k ~ k^-alpha, alpha drifting along the sequence) and compares three ways to
+truncate the same matrices:
+  * plain       - Gram + FP64 eigensolve (the method without any sketch);
+  * fixed       - randomized SVD with the rank used when nothing predicts it,
+                  k = chi_max + 64 (the method without the network);
+  * learned     - randomized SVD with the network's k, plain as fallback.
+The learned path must reproduce the exact spectrum (max |ds| / s_1 <= 1e-6),
+use a much smaller sketch than the fixed rank, and take less GPU time than
+the plain path on the sequences whose spectrum decays fast enough."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_2512_23917_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, CHI_MAX, EPS = 2048, 1024, 1e-8
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2512_23917_amd import tci
+    return tci
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def trained(T, ctx):
+    from paper_2512_23917_amd import sketch_train as st
+    X, Tg = st.make_dataset(ctx, 20000, seed=11)
+    m, hist = st.train(ctx, X, Tg, epochs=20, seed=0)
+    yield m, hist
+    m.close()
+
+
+def test_training_reduces_pinball_loss(trained):
+    m, hist = trained
+    val = hist["val"]
+    print("validation pinball per epoch:", [round(v, 4) for v in val])
+    assert all(np.isfinite(val))
+    assert val[-1] < 0.25 * val[0]
+    assert val[-1] < 0.15       # in log2(chi*) units: well under one doubling of chi
+
+
+def test_prediction_quantile_and_plain_region(T, ctx, trained):
+    """On held-out sequences the 0.9-quantile model covers chi* for about 90%
+    of the samples, and predicts 'plain' for spectra whose chi* exceeds the cap."""
+    from paper_2512_23917_amd import sketch_train as st
+    m, _ = trained
+    prev, targ = st.make_pairs(4000, seed=12345)
+    y = m.predict(st.features(ctx, prev, CHI_MAX, 2, EPS)).cpu().numpy().astype(np.float64)
+    cover = np.mean(y >= targ)
+    print("coverage", cover)
+    assert 0.8 <= cover <= 0.98
+    over = targ > math.log2(CHI_MAX) + 0.2
+    assert np.mean(y[over] > math.log2(CHI_MAX)) > 0.9
+
+
+@pytest.fixture(scope="module")
+def uv():
+    g = synth.rng(5, 777)
+    return synth.haar(g, N, N, complex_=False), synth.haar(g, N, N, complex_=False)
+
+
+def _theta(T, ctx, u, v, s):
+    th = ((u * s[None, :]) @ v.T).astype(np.float32).reshape(N // 2, 2, 2, N // 2)
+    return T.Tensor.from_numpy(ctx, th, T.F32)
+
+
+def _run(T, ctx, theta, mode, model=None, prev=None, k=0):
+    p = T.update_params(chi_min=1, chi_max=CHI_MAX, target_trunc_err=EPS, direction=1, precision=T.PREC_BF16X3,
+                        svd_mode=mode, sketch_rank=k, power_iters=2, seed=3)
+    if model is not None:
+        p.sketch_model = model.h.value
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ao, so, Bo, inf = T.split_batched(ctx, [theta], p, prev_spectra=prev)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, so[0].numpy(), inf[0]
+
+
+def test_learned_gain_over_plain_and_fixed_rank(T, ctx, trained, uv):
+    from paper_2512_23917_amd import sketch_train as st
+    m, _ = trained
+    u, v = uv
+    rng = np.random.default_rng(2024)
+    alphas = [2.9, 2.5, 2.2, 2.0]          # fast-decaying held-out spectra
+    rows = []
+    for a0 in alphas:
+        a_prev = float(np.clip(a0 + rng.normal(0, 0.05), 1.0, 3.0))
+        s_prev = st.power_law(N, a_prev)
+        s_prev = s_prev[:min(st.chi_star(s_prev, EPS), CHI_MAX)]
+        prev = T.Tensor.from_numpy(ctx, s_prev / np.linalg.norm(s_prev), T.F64)
+        s = st.power_law(N, a0)
+        chi_ref = min(st.chi_star(s, EPS), CHI_MAX)
+        s_ref = s[:chi_ref] / np.linalg.norm(s[:chi_ref])
+        th = _theta(T, ctx, u, v, s)
+        _run(T, ctx, th, T.SVD_PLAIN)                       # warm-up of this shape
+        t_plain, sp, ip = _run(T, ctx, th, T.SVD_PLAIN)
+        t_fix, sf, i_f = _run(T, ctx, th, T.SVD_RANDOMIZED, k=CHI_MAX + 64)
+        t_learn, sl, il = _run(T, ctx, th, T.SVD_LEARNED, model=m, prev=[prev])
+        for name, sv, inf in (("plain", sp, ip), ("fixed", sf, i_f), ("learned", sl, il)):
+            c = min(inf.chi, chi_ref)
+            assert abs(inf.chi - chi_ref) <= 2, (name, a0, inf.chi, chi_ref)
+            assert np.abs(sv[:c] - s_ref[:c]).max() <= 1e-6 * s_ref[0], (name, a0)
+        rows.append((a0, chi_ref, il.sketch_rank, il.used_fallback, t_plain, t_fix, t_learn))
+    for r in rows:
+        print("alpha %.2f chi* %4d k %4d fallback %d  plain %.2f ms  fixed-k %.2f ms  learned %.2f ms"
+              % (r[0], r[1], r[2], r[3], 1e3 * r[4], 1e3 * r[5], 1e3 * r[6]))
+    ks = np.array([r[2] for r in rows])
+    assert np.all(ks > 0) and np.all(ks < CHI_MAX + 64)
+    assert all(r[3] == 0 for r in rows)                     # every learned attempt is accepted
+    t_plain = sum(r[4] for r in rows)
+    t_fix = sum(r[5] for r in rows)
+    t_learn = sum(r[6] for r in rows)
+    assert t_learn < 0.8 * t_plain
+    assert t_learn < t_fix
