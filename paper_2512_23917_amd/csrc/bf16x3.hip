@@ -10,9 +10,12 @@
 // three terms, hi*hi + hi*lo + lo*hi, accumulated in FP32; the complex
 // product uses four real products.
 //
-// Tiles: 128 x 128 outputs per workgroup (4 waves, 64 x 64 each), k tile 32;
-// the next k tile is fetched into registers while the current one feeds the
-// matrix cores.
+// Tiles: 128 x 128 outputs per workgroup (4 waves, 64 x 64 each), k tile 32,
+// two LDS stages: the next k tile is fetched into registers while the
+// current stage feeds the matrix cores, then stored to the other stage, so
+// that one barrier per k tile suffices.  Each 64-byte LDS row holds four
+// 16-byte k chunks, chunk c of row r at position c ^ ((r >> 2) & 3): the 16
+// rows that one MFMA operand load touches then fall into distinct banks.
 #include "common.hpp"
 #include "gemm.hpp"
 #include "bf16x3.hpp"
@@ -24,7 +27,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
-constexpr int XBM = 128, XBN = 128, XBK = 32, XKP = XBK + 8;
+constexpr int XBM = 128, XBN = 128, XBK = 32;
 
 // ---------------------------------------------------------------------------
 // Splitting: X(r, k) = src[r*ld + k] (mode 0) or src[k*ld + r] (mode 1), with
@@ -113,8 +116,8 @@ hipError_t split_planes(int dtype, const void* src, long long ld, long long ssrc
 template <bool CPLX>
 __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
   constexpr int NP = CPLX ? 4 : 2;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NP][XBM][XKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][XBN][XKP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][XBM][XBK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][XBN][XBK];
   // tile coordinates, XCD-aware as in the plain GEMM
   const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
   const long total = (long)gx * gy * gz;
@@ -131,6 +134,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const int lr = lane & 15, lk = lane >> 4;
+  const int rd = 8 * (lk ^ ((lr >> 2) & 3));   // swizzled k offset of this lane's operand chunk
 
   f4v acc_re[4][4], acc_im[4][4];
 #pragma unroll
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
       acc_im[i][j] = f4v{0, 0, 0, 0};
     }
 
-  // chunk c in [0, 512): row c >> 2, k offset (c & 3) * 8
+  // chunk c in [0, 512): row c >> 2, k chunk c & 3
   u4v ra[NP][2], rb[NP][2];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -154,31 +158,33 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
         rb[p][h] = *reinterpret_cast<const u4v*>(B + p * pb + (long long)(n0 + row) * a.Kp + k0 + ko);
       }
   };
-  auto stash = [&]() {
+  auto stash = [&](int st) {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int c = t + 256 * h;
-        const int row = c >> 2, ko = (c & 3) * 8;
-        *reinterpret_cast<u4v*>(&As[p][row][ko]) = ra[p][h];
-        *reinterpret_cast<u4v*>(&Bs[p][row][ko]) = rb[p][h];
+        const int row = c >> 2, ko = 8 * ((c & 3) ^ ((row >> 2) & 3));
+        *reinterpret_cast<u4v*>(&As[st][p][row][ko]) = ra[p][h];
+        *reinterpret_cast<u4v*>(&Bs[st][p][row][ko]) = rb[p][h];
       }
   };
 
+  const int nk = a.Kp / XBK;
   fetch(0);
-  for (int k0 = 0; k0 < a.Kp; k0 += XBK) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + XBK < a.Kp) fetch(k0 + XBK);
+  stash(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) fetch((kt + 1) * XBK);
     bf8v fa[NP][4], fb[NP][4];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[p][i] = *reinterpret_cast<const bf8v*>(&As[p][wm * 64 + i * 16 + lr][8 * lk]);
+      for (int i = 0; i < 4; ++i) fa[p][i] = *reinterpret_cast<const bf8v*>(&As[cur][p][wm * 64 + i * 16 + lr][rd]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[p][wn * 64 + j * 16 + lr][8 * lk]);
+      for (int j = 0; j < 4; ++j) fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[cur][p][wn * 64 + j * 16 + lr][rd]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -200,6 +206,8 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[3][i], fb[0][j], acc_im[i][j], 0, 0, 0);
         }
       }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
   }
 
   // epilogue: C = alpha * acc + beta * C (rows 4*(l/16)+r, column l%16 of each block)
@@ -239,7 +247,7 @@ hipError_t gemm_planes(int dtype, const PlaneGemmArgs& a, hipStream_t s) {
   dim3 grid(a.Np / XBN, a.Mp / XBM, a.batch);
   const bool cplx = dtype == C64;
   const double flops = (cplx ? 8.0 : 2.0) * 3.0 * a.m * (double)a.n * a.k * a.batch;
-  ProfScope ps(s, flops, cplx ? "c64_bf16x3" : "f32_bf16x3");
+  ProfScope ps(s, flops, cplx ? "c64_bf16x3_planes" : "f32_bf16x3_planes");
   if (cplx) hipLaunchKernelGGL(gemm_planes_kernel<true>, grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(gemm_planes_kernel<false>, grid, dim3(256), 0, s, a);
   return hipGetLastError();

@@ -221,12 +221,14 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
       TCI_CHECK_HIP(multiaxpy(vj, 1, coef, -1.0, w, N, s));
     }
     // two passes of classical Gram-Schmidt against v_0..v_j
-    for (int pass = 0; pass < 2; ++pass) {
-      TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
-      TCI_CHECK_HIP(multiaxpy(basis, j + 1, coef, -1.0, w, N, s));
-    }
+    // (the second pass also returns ||w||^2)
+    TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
+    TCI_CHECK_HIP(multiaxpy(basis, j + 1, coef, -1.0, w, N, s));
+    TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
+    TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
     double b2 = 0.0;
-    TCI_TRY(norm2(w, b2));
+    TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
+    TCI_CHECK_HIP(hipStreamSynchronize(s));
     const double b = std::sqrt(b2);
     tmax = std::max({tmax, std::fabs(a), b});
     if (j == n_matvec - 1) break;

@@ -52,6 +52,8 @@ __device__ inline double add(double a, double b) { return a + b; }
 __device__ inline cd add(cd a, cd b) { return a + b; }
 __device__ inline double sub(double a, double b) { return a - b; }
 __device__ inline cd sub(cd a, cd b) { return a - b; }
+__device__ inline double shfl_xor_t(double v, int m) { return __shfl_xor(v, m); }
+__device__ inline cd shfl_xor_t(cd v, int m) { return cd{__shfl_xor(v.x, m), __shfl_xor(v.y, m)}; }
 __device__ inline double wsum(double v) { return wave_sum(v); }
 __device__ inline cd wsum(cd v) { return cd{wave_sum(v.x), wave_sum(v.y)}; }
 __device__ inline double bsum(double v, double* sh) { return block_sum(v, sh); }
@@ -97,13 +99,20 @@ struct TriWs {
   __host__ __device__ static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
 };
 
+// Sum of a per-thread complex / real value over groups of 4 consecutive lanes.
 template <typename T>
-__device__ inline T vload(const T* p) {
+__device__ inline T quad_sum(T v) {
   if constexpr (sizeof(T) == 16) {
-    const volatile double* q = reinterpret_cast<const volatile double*>(p);
-    return T{q[0], q[1]};
+    double r = v.x, i = v.y;
+    r += __shfl_xor(r, 1);
+    i += __shfl_xor(i, 1);
+    r += __shfl_xor(r, 2);
+    i += __shfl_xor(i, 2);
+    return cd{r, i};
   } else {
-    return *reinterpret_cast<const volatile double*>(p);
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
   }
 }
 
@@ -274,13 +283,21 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     s_last = (ticket == (int)gridDim.x - 1);
   }
   __syncthreads();
-  if (s_last && tid == 0) {
+  if (s_last) {
+    // acquire: the partials of the other workgroups are visible after the fence
     __threadfence();
-    const volatile double* vp = pa;
     double tot = 0.0;
-    for (int k = 0; k < (int)gridDim.x; ++k) tot += vp[k];
-    fa[0] = tot;
-    cnt[0] = 0;
+    for (int k = tid; k < (int)gridDim.x; k += 256) tot += pa[k];
+    red[tid] = tot;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      fa[0] = red[0];
+      cnt[0] = 0;
+    }
   }
 }
 
@@ -289,7 +306,8 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   __shared__ T s_vR[TT], s_vC[TT];
   __shared__ T s_q[4];
   __shared__ T s_colsum[4][TT];
-  __shared__ T s_tt[2 * NB];
+  __shared__ T s_tt[4][2 * NB];
+  static_assert(2 * NB == TT, "t1/t2 thread mapping assumes 2 NB == TT");
   __shared__ int s_last;
   __shared__ T s_scal;
   const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
@@ -341,57 +359,79 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   }
   if (k == 0)
     for (int rr = tid; rr < b0 * TT; rr += 256) V[(long)i * n + rr] = EigT<T>::zero();
-  // load the tile: thread (cl, rg) holds rows rg + 4k, column cl
+  // load the tile: thread (cl, rg) holds rows rg + 4 kk (kk < 16) of column cl
   const int cl = tid & 63, rg = tid >> 6;
   const int c = C * TT + cl;
   const bool cok = (c > i) && (c < n);
   T colacc = EigT<T>::zero();
-  T qacc = EigT<T>::zero();
-#pragma unroll 4
+  T ps[TT / 4];
+#pragma unroll
   for (int kk = 0; kk < TT / 4; ++kk) {
     const int rl = rg + 4 * kk;
     const int r = R * TT + rl;
     T g = EigT<T>::zero();
     if (cok && r > i && r < n) g = G[(long)r * a.ldg + c];
-    // row sum: y_R(r) += g v_C(c)
-    T rs = wsum(mulr(g, s_vC[cl]));
-    if (cl == 0 && r < n) {
-      P[(long)C * n + r] = rs;   // the whole wave holds the row sum; lane 0 writes
-      qacc = add(qacc, mulr(cj(s_vR[rl]), rs));
-    }
-    // column sum: y_C(c) += conj(g) v_R(r)
-    colacc = add(colacc, mulr(cj(g), s_vR[rl]));
+    ps[kk] = mulr(g, s_vC[cl]);                       // row-sum term
+    colacc = add(colacc, mulr(cj(g), s_vR[rl]));      // column-sum term
   }
-  // wave 0..3 lane 0 hold quadratic-form pieces for their rows
+  // Row sums: butterfly reduce-scatter over lane bits 5..2 leaves lane l with
+  // the partial of kk = (l >> 2) & 15 over 16 lanes, then bits 1..0 finish it.
+#pragma unroll
+  for (int half = 8, bit = 32; half >= 1; half >>= 1, bit >>= 1) {
+    const bool hi = (cl & bit) != 0;
+#pragma unroll
+    for (int t = 0; t < half; ++t) {
+      const T mine = hi ? ps[t + half] : ps[t];
+      const T other = hi ? ps[t] : ps[t + half];
+      ps[t] = add(mine, shfl_xor_t(other, bit));
+    }
+  }
+  T rs = add(ps[0], shfl_xor_t(ps[0], 1));
+  rs = add(rs, shfl_xor_t(rs, 2));
+  T qacc = EigT<T>::zero();
+  {
+    const int kk = (cl >> 2) & 15, rl = rg + 4 * kk, r = R * TT + rl;
+    if ((cl & 3) == 0 && r < n) {
+      P[(long)C * n + r] = rs;
+      qacc = mulr(cj(s_vR[rl]), rs);
+    }
+  }
+  qacc = wsum(qacc);
   if (cl == 0) s_q[rg] = qacc;
   s_colsum[rg][cl] = colacc;
+  // t1 = W^H v and t2 = V^H v over this diagonal tile's rows: thread (q, part)
+  // with q < NB for W's column q, q >= NB for V's row q - NB, rows part*16 ...
+  if (diag) {
+    const int q = tid & 63, part = tid >> 6, qq = q & (NB - 1);
+    T acc = EigT<T>::zero();
+    if (qq < p) {
+#pragma unroll
+      for (int kk = 0; kk < TT / 4; ++kk) {
+        const int rl = part * (TT / 4) + kk, r = R * TT + rl;
+        if (r > i && r < n) {
+          const T other = q < NB ? W[(long)r * NB + qq] : V[(long)(j0 + qq) * n + r];
+          acc = add(acc, mulr(cj(other), s_vR[rl]));
+        }
+      }
+    }
+    s_tt[part][q] = acc;
+  }
   __syncthreads();
   if (!diag && tid < TT) {
     T cs = add(add(s_colsum[0][tid], s_colsum[1][tid]), add(s_colsum[2][tid], s_colsum[3][tid]));
     const int cc = C * TT + tid;
     if (cc < n) P[(long)R * n + cc] = cs;
   }
-  // partials of this tile: quadratic form, and t1 = W^H v, t2 = V^H v on diagonal tiles
+  // partials of this tile: quadratic form, and t1, t2 on diagonal tiles
   T* mypc = pc + (long)k * (1 + 2 * NB);
   if (tid == 0) {
     T q = add(add(s_q[0], s_q[1]), add(s_q[2], s_q[3]));
     if (!diag) q = add(q, cj(q));
     mypc[0] = q;
   }
-  if (tid < 2 * NB) {
-    const int q = tid % NB;
-    const bool isw = tid < NB;
-    T acc = EigT<T>::zero();
-    if (diag && q < p) {
-      for (int rl = 0; rl < TT; ++rl) {
-        const int r = R * TT + rl;
-        if (r <= i || r >= n) continue;
-        const T other = isw ? W[(long)r * NB + q] : V[(long)(j0 + q) * n + r];
-        acc = add(acc, mulr(cj(other), s_vR[rl]));
-      }
-    }
-    mypc[1 + tid] = acc;
-  }
+  if (tid < 2 * NB)
+    mypc[1 + tid] = diag ? add(add(s_tt[0][tid], s_tt[1][tid]), add(s_tt[2][tid], s_tt[3][tid]))
+                         : EigT<T>::zero();
   __syncthreads();
   if (tid == 0) {
     __threadfence();
@@ -400,16 +440,17 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   }
   __syncthreads();
   if (s_last) {
+    // acquire, then 4 lanes per output value sum interleaved tile partials
     __threadfence();
-    if (tid < 1 + 2 * NB) {
+    const int g = tid >> 2, j = tid & 3;
+    for (int o = g; o < 1 + 2 * NB; o += 64) {
       T acc = EigT<T>::zero();
-      for (int kk = 0; kk < (int)gridDim.x; ++kk) acc = add(acc, vload(pc + (long)kk * (1 + 2 * NB) + tid));
-      fc[tid] = acc;
+      for (int kk = j; kk < (int)gridDim.x; kk += 4) acc = add(acc, pc[(long)kk * (1 + 2 * NB) + o]);
+      acc = quad_sum(acc);
+      if (j == 0) fc[o] = acc;
     }
-    __syncthreads();
     if (tid == 0) cnt[1] = 0;
   }
-  (void)s_tt;
 }
 
 template <typename T, int NB>
@@ -495,35 +536,50 @@ __global__ void e2_kernel(const double* e, double* e2, long long sde, int n, int
   e2[b * sde + i] = v * v;
 }
 
+// Multisection: one wave per wanted eigenvalue; each round the 64 lanes
+// evaluate the Sturm count at 64 interior points of the current interval
+// [lo, hi] (count(lo) <= t < count(hi)), which shrinks it 65-fold.
 __global__ __launch_bounds__(256) void bisect_kernel(const double* d, const double* e, const double* e2,
                                                      long long sde, int n, int kmax, double* lam,
                                                      long long slam, int batch) {
   const int b = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= kmax || b >= batch) return;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= kmax || b >= batch) return;  // whole waves leave together
   const double* db = d + b * sde;
   const double* eb = e + b * sde;
   const double* e2b = e2 + b * sde;
   double lo = db[0], hi = db[0], emax2 = 0.0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = lane; i < n; i += 64) {
     const double r = (i > 0 ? fabs(eb[i - 1]) : 0.0) + (i < n - 1 ? fabs(eb[i]) : 0.0);
     lo = fmin(lo, db[i] - r);
     hi = fmax(hi, db[i] + r);
     if (i < n - 1) emax2 = fmax(emax2, e2b[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    emax2 = fmax(emax2, __shfl_xor(emax2, off));
   }
   const double scale = fmax(fabs(lo), fabs(hi));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) * 64.0;
   lo -= 4.0 * 2.220446049250313e-16 * scale + pivmin;
   hi += 4.0 * 2.220446049250313e-16 * scale + pivmin;
   const int t = n - 1 - j;  // ascending index of the wanted eigenvalue
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    if (sturm_count(db, e2b, n, mid, pivmin) <= t) lo = mid;
-    else hi = mid;
+    const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+    const bool below = (x > lo && x < hi) ? sturm_count(db, e2b, n, x, pivmin) <= t : (x <= lo);
+    const unsigned long long m = __ballot(below);
+    // first lane whose point has more than t eigenvalues below it
+    const int k = (~m == 0ull) ? 64 : __ffsll((long long)~m) - 1;
+    const double xl = __shfl(x, k > 0 ? k - 1 : 0), xh = __shfl(x, k < 64 ? k : 63);
+    const double nlo = k > 0 ? xl : lo, nhi = k < 64 ? xh : hi;
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
   }
-  lam[b * slam + j] = 0.5 * (lo + hi);
+  if (lane == 0) lam[b * slam + j] = 0.5 * (lo + hi);
 }
 
 hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, long long sde, int n,
@@ -531,7 +587,7 @@ hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, lon
   if (kmax <= 0 || batch <= 0) return hipSuccess;
   const long tot = (long)batch * n;
   hipLaunchKernelGGL(e2_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, e, e2, sde, n, batch);
-  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 63) / 64, batch), dim3(64), 0, s, d, e, e2, sde, n,
+  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 3) / 4, batch), dim3(256), 0, s, d, e, e2, sde, n,
                      kmax, lam, slam, batch);
   return hipGetLastError();
 }

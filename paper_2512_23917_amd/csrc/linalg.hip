@@ -116,44 +116,90 @@ hipError_t gate_apply(int dtype, void* theta, long long stheta, const void* gate
 // Outputs per problem: chi, eps, discarded weight eps*W, the kept s_j,
 // 1/s_j (0 for s_j = 0) and s_j / ||s_kept||_2.
 // ---------------------------------------------------------------------------
-__global__ void trunc_select_kernel(const double* lam, long long slam, int kmax, const double* total,
-                                    TruncParams p, int* chi_out, double* err_out, double* disc_out,
-                                    double* s_out, double* sinv_out, double* sn_out, long long ss,
-                                    int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per problem.  lam holds the kmax largest Gram eigenvalues in
+// descending order, total the squared Frobenius norm W.  The kept weight of
+// chi values is the prefix sum of max(lam, 0); thread t owns the contiguous
+// chunk [j0, j1) of indices and tests the candidates chi in that chunk.
+__global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, long long slam, int kmax,
+                                                           const double* total, TruncParams p, int* chi_out,
+                                                           double* err_out, double* disc_out, double* s_out,
+                                                           double* sinv_out, double* sn_out, long long ss,
+                                                           int batch) {
+  __shared__ double s_scan[256];
+  __shared__ int s_red[256];
+  __shared__ double s_kept;
+  const int b = blockIdx.x, tid = threadIdx.x;
   if (b >= batch) return;
   const double* l = lam + b * slam;
   const double W = total[b];
-  int n_a = 0;
-  while (n_a < kmax && sqrt(fmax(l[n_a], 0.0)) >= p.s_min) ++n_a;
-  double kept = 0.0;
-  int chi;
+  auto wt = [&](int j) { return fmax(l[j], 0.0); };
   auto eps_of = [&](double kept_w) { return W > 0.0 ? fmax(W - kept_w, 0.0) / W : 0.0; };
+  auto block_min = [&](int v) {
+    __syncthreads();
+    s_red[tid] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) s_red[tid] = min(s_red[tid], s_red[tid + off]);
+      __syncthreads();
+    }
+    return s_red[0];
+  };
+  // n_a: number of leading values with s_j >= s_min
+  int bad = kmax;
+  for (int j = tid; j < kmax; j += 256)
+    if (sqrt(wt(j)) < p.s_min) bad = min(bad, j);
+  const int n_a = block_min(bad);
+  // exclusive scan of the chunk sums
+  const int chunk = (kmax + 255) / 256;
+  const int j0 = min(kmax, tid * chunk), j1 = min(kmax, j0 + chunk);
+  double loc = 0.0;
+  for (int j = j0; j < j1; ++j) loc += wt(j);
+  s_scan[tid] = loc;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const double v = tid >= off ? s_scan[tid - off] : 0.0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  const double base = s_scan[tid] - loc;
+  // kept(c) = sum_{j < c} wt(j); thread t owns c in [j0, j1), the last thread also c = kmax
+  auto kept_at = [&](int c) {
+    double k = base;
+    for (int j = j0; j < c; ++j) k += wt(j);
+    return k;
+  };
+  int chi;
   if (n_a <= p.chi_min) {
     chi = n_a;
-    for (int j = 0; j < chi; ++j) kept += fmax(l[j], 0.0);
   } else {
     const int lim = min(p.chi_max, n_a);
-    chi = p.chi_min;
-    for (int j = 0; j < chi; ++j) kept += fmax(l[j], 0.0);
-    while (chi < lim && eps_of(kept) > p.target) {
-      kept += fmax(l[chi], 0.0);
-      ++chi;
+    int cand = lim;
+    double k = base;
+    const int chi_hi = (j1 == kmax) ? kmax : j1 - 1;
+    for (int c = j0; c <= chi_hi; ++c) {
+      if (c >= p.chi_min && c <= lim && eps_of(k) <= p.target) {
+        cand = c;
+        break;
+      }
+      if (c < j1) k += wt(c);
     }
+    chi = block_min(cand);
   }
-  if (chi < 1) {
-    chi = 1;
-    kept = fmax(l[0], 0.0);
+  if (chi < 1) chi = 1;
+  __syncthreads();
+  if (j0 < j1 ? (chi >= j0 && chi < j1) || (chi == kmax && j1 == kmax) : false) s_kept = kept_at(chi);
+  __syncthreads();
+  const double kept = s_kept;
+  const double nrm = sqrt(kept);
+  if (tid == 0) {
+    const double eps = eps_of(kept);
+    chi_out[b] = chi;
+    err_out[b] = eps;
+    disc_out[b] = eps * W;
   }
-  const double eps = eps_of(kept);
-  chi_out[b] = chi;
-  err_out[b] = eps;
-  disc_out[b] = eps * W;
-  double nrm = 0.0;
-  for (int j = 0; j < chi; ++j) nrm += fmax(l[j], 0.0);
-  nrm = sqrt(nrm);
-  for (int j = 0; j < kmax; ++j) {
-    const double sj = j < chi ? sqrt(fmax(l[j], 0.0)) : 0.0;
+  for (int j = tid; j < kmax; j += 256) {
+    const double sj = j < chi ? sqrt(wt(j)) : 0.0;
     s_out[b * ss + j] = sj;
     sinv_out[b * ss + j] = sj > 0.0 ? 1.0 / sj : 0.0;
     sn_out[b * ss + j] = nrm > 0.0 ? sj / nrm : 0.0;
@@ -163,8 +209,9 @@ __global__ void trunc_select_kernel(const double* lam, long long slam, int kmax,
 hipError_t trunc_select(const double* lam, long long slam, int kmax, const double* total,
                         const TruncParams& p, int* chi, double* err, double* disc, double* s,
                         double* sinv, double* sn, long long ss, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(trunc_select_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, lam, slam, kmax,
-                     total, p, chi, err, disc, s, sinv, sn, ss, batch);
+  if (batch <= 0 || kmax <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trunc_select_kernel, dim3(batch), dim3(256), 0, st, lam, slam, kmax, total, p, chi, err, disc,
+                     s, sinv, sn, ss, batch);
   return hipGetLastError();
 }
 

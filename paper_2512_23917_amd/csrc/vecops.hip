@@ -150,38 +150,61 @@ hipError_t max_abs_diff(int dt, const void* a, const void* b, long long n, doubl
 //             length n, ld n), two-pass deterministic reduction;
 //   multiaxpy: w[i] += sum_q c_q v_q[i]  (c given as (re, im) on the device).
 // ---------------------------------------------------------------------------
-constexpr int MD_BLOCKS = 256;
+constexpr int MD_BLOCKS = 1024;
 constexpr int MD_MAXV = 32;
+static_assert(MULTIDOT_PARTIAL_DOUBLES >= MD_BLOCKS * MD_MAXV * 2, "multidot partial buffer");
 
+__device__ inline double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// NV is a compile-time bound on nv so that the accumulators stay in registers.
+template <int NV>
 __global__ __launch_bounds__(256) void multidot_partial_kernel(const cd* V, int nv, const cd* w, long long n,
                                                                double* partial) {
-  __shared__ double sh[16];
-  double accr[MD_MAXV], acci[MD_MAXV];
-  for (int q = 0; q < nv; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
+  __shared__ double sh[4][2 * NV];
+  double accr[NV], acci[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
     const cd x = w[i];
-    for (int q = 0; q < nv; ++q) {
-      const cd v = V[(long long)q * n + i];
-      accr[q] += v.x * x.x + v.y * x.y;
-      acci[q] += v.x * x.y - v.y * x.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        const cd v = V[(long long)q * n + i];
+        accr[q] += v.x * x.x + v.y * x.y;
+        acci[q] += v.x * x.y - v.y * x.x;
+      }
     }
   }
-  for (int q = 0; q < nv; ++q) {
-    const double r = block_sum(accr[q], sh);
-    const double im = block_sum(acci[q], sh);
-    if (threadIdx.x == 0) {
-      partial[((long long)blockIdx.x * MD_MAXV + q) * 2 + 0] = r;
-      partial[((long long)blockIdx.x * MD_MAXV + q) * 2 + 1] = im;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if (q < nv) {
+      const double r = wave_sum64(accr[q]), im = wave_sum64(acci[q]);
+      if (lane == 0) { sh[wv][2 * q] = r; sh[wv][2 * q + 1] = im; }
     }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * nv) {
+    const double v = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    partial[((long long)blockIdx.x * MD_MAXV + t / 2) * 2 + (t & 1)] = v;
   }
 }
 
-// One workgroup per coefficient q: thread b loads partial b, fixed-order tree sum.
+// One workgroup per coefficient q: fixed-order sums of the block partials.
 __global__ __launch_bounds__(256) void multidot_final_kernel(const double* partial, int nparts, int nv, double* out) {
   __shared__ double sr[256], si[256];
   const int q = blockIdx.x, t = threadIdx.x;
-  sr[t] = t < nparts ? partial[((long long)t * MD_MAXV + q) * 2 + 0] : 0.0;
-  si[t] = t < nparts ? partial[((long long)t * MD_MAXV + q) * 2 + 1] : 0.0;
+  double ar = 0.0, ai = 0.0;
+  for (int b = t; b < nparts; b += 256) {
+    ar += partial[((long long)b * MD_MAXV + q) * 2 + 0];
+    ai += partial[((long long)b * MD_MAXV + q) * 2 + 1];
+  }
+  sr[t] = ar;
+  si[t] = ai;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (t < off) { sr[t] += sr[t + off]; si[t] += si[t + off]; }
@@ -190,35 +213,96 @@ __global__ __launch_bounds__(256) void multidot_final_kernel(const double* parti
   if (t == 0) { out[2 * q] = sr[0]; out[2 * q + 1] = si[0]; }
 }
 
+static unsigned md_grid(long long n) {
+  return (unsigned)std::max<long long>(1, std::min<long long>(MD_BLOCKS, (n + 255) / 256));
+}
+
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
                     hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   if (nv > MD_MAXV) return hipErrorInvalidValue;
-  const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(MD_BLOCKS, (n + 255) / 256));
-  hipLaunchKernelGGL(multidot_partial_kernel, dim3(g), dim3(256), 0, s, (const cd*)V, nv, (const cd*)w, n, partial);
+  const unsigned g = md_grid(n);
+  const cd* Vc = (const cd*)V;
+  const cd* wc = (const cd*)w;
+  if (nv <= 2) hipLaunchKernelGGL(multidot_partial_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
+  else if (nv <= 8) hipLaunchKernelGGL(multidot_partial_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
+  else if (nv <= 16) hipLaunchKernelGGL(multidot_partial_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
+  else hipLaunchKernelGGL(multidot_partial_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, const double* c, double sign,
-                                                        cd* w, long long n) {
-  double cr[MD_MAXV], ci[MD_MAXV];
-  for (int q = 0; q < nv; ++q) { cr[q] = sign * c[2 * q]; ci[q] = sign * c[2 * q + 1]; }
+// w += sign * sum_q c_q v_q; with nrm_part, block b also stores its part of ||w||^2.
+template <int NV>
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, const double* c, double sign, cd* w,
+                                                        long long n, double* nrm_part) {
+  __shared__ double sh[4];
+  double cr[NV], ci[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    cr[q] = q < nv ? sign * c[2 * q] : 0.0;
+    ci[q] = q < nv ? sign * c[2 * q + 1] : 0.0;
+  }
+  double ss = 0.0;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
     cd acc = w[i];
-    for (int q = 0; q < nv; ++q) {
-      const cd v = V[(long long)q * n + i];
-      acc.x += cr[q] * v.x - ci[q] * v.y;
-      acc.y += cr[q] * v.y + ci[q] * v.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        const cd v = V[(long long)q * n + i];
+        acc.x += cr[q] * v.x - ci[q] * v.y;
+        acc.y += cr[q] * v.y + ci[q] * v.x;
+      }
     }
     w[i] = acc;
+    ss += acc.x * acc.x + acc.y * acc.y;
   }
+  if (nrm_part) {
+    ss = wave_sum64(ss);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) nrm_part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int nparts, double* out) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  double a = 0.0;
+  for (int b = t; b < nparts; b += 256) a += part[b];
+  sh[t] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) sh[t] += sh[t + off];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = sh[0];
+}
+
+static hipError_t multiaxpy_launch(const void* V, int nv, const double* c, double sign, void* w, long long n,
+                                   double* nrm_part, hipStream_t s) {
+  const unsigned g = md_grid(n);
+  const cd* Vc = (const cd*)V;
+  cd* wc = (cd*)w;
+  if (nv <= 2) hipLaunchKernelGGL(multiaxpy_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
+  else if (nv <= 8) hipLaunchKernelGGL(multiaxpy_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
+  else if (nv <= 16) hipLaunchKernelGGL(multiaxpy_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
+  else hipLaunchKernelGGL(multiaxpy_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
+  return hipGetLastError();
 }
 
 hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   if (nv > MD_MAXV) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)V, nv, c, sign, (cd*)w, n);
+  return multiaxpy_launch(V, nv, c, sign, w, n, nullptr, s);
+}
+
+hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
+                           double* partial, double* out, hipStream_t s) {
+  if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
+  hipError_t e = multiaxpy_launch(V, nv, c, sign, w, n, partial, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, partial, (int)md_grid(n), out);
   return hipGetLastError();
 }
 

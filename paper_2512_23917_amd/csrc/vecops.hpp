@@ -17,10 +17,13 @@ hipError_t linear_combine(int dt, const LinCombArgs& a, void* out, long long n, 
 // partial: nparts doubles; the result is max over partial[0 .. min(nparts, blocks)-1]
 hipError_t max_abs_diff(int dt, const void* a, const void* b, long long n, double* partial, int nparts,
                         hipStream_t s);
-constexpr int MULTIDOT_PARTIAL_DOUBLES = 256 * 32 * 2;
+constexpr int MULTIDOT_PARTIAL_DOUBLES = 1024 * 32 * 2;
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
                     hipStream_t s);
 hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s);
+// multiaxpy, then out[0] = ||w||^2 (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
+hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
+                           double* partial, double* out, hipStream_t s);
 hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s);
 hipError_t scale_inplace(int dt, void* x, long long n, double sr, double si, hipStream_t s);
 hipError_t mpo_pair(int dt, const void* W1, const void* W2, void* W12, int wd, int d, hipStream_t s);
