@@ -178,17 +178,61 @@ def trivial_environments():
 # --------------------------------------------------------------------------
 def binomial_sector_sizes(total: int, n_sectors: int) -> list[int]:
     """Split `total` over `n_sectors` sectors following binomial(n_sectors-1, 1/2)
-    weights with the largest-remainder method and at least 1 per sector."""
+    weights: quotas w_k * total, floored and raised to at least 1, then the
+    difference to `total` is given to (or, if negative, taken from sectors
+    above 1 with) the largest (smallest) fractional parts, ties to the
+    lower index."""
     n = n_sectors - 1
     w = np.array([math.comb(n, k) for k in range(n_sectors)], dtype=np.float64)
     w /= w.sum()
-    base = np.ones(n_sectors, dtype=np.int64)
-    rest = total - n_sectors
-    if rest < 0:
+    if total < n_sectors:
         raise ValueError("total smaller than the number of sectors")
-    quota = w * rest
-    fl = np.floor(quota).astype(np.int64)
-    rem = rest - int(fl.sum())
-    order = np.argsort(-(quota - fl), kind="stable")
-    fl[order[:rem]] += 1
-    return [int(x) for x in base + fl]
+    quota = w * total
+    fl = np.maximum(np.floor(quota).astype(np.int64), 1)
+    frac = quota - np.floor(quota)
+    rem = total - int(fl.sum())
+    if rem > 0:
+        order = np.argsort(-frac, kind="stable")
+        fl[order[:rem]] += 1
+    while rem < 0:
+        cand = [k for k in np.argsort(frac, kind="stable") if fl[k] > 1]
+        fl[cand[0]] -= 1
+        rem += 1
+    return [int(x) for x in fl]
+
+
+def u1_bond(chi: int, n_sectors: int) -> list[tuple[int, int]]:
+    """Bond of U(1) sectors: charges 2Sz = -(n_sectors-1), ..., n_sectors-1 in
+    steps of 2 (even charges for an odd count, odd for an even count), sizes
+    from binomial_sector_sizes."""
+    dims = binomial_sector_sizes(chi, n_sectors)
+    return [(2 * k - (n_sectors - 1), dims[k]) for k in range(n_sectors)]
+
+
+U1_SPIN_CHARGE = (1, -1)   # physical index 0 = up, 1 = down
+
+
+def u1_site_blocks(g: np.random.Generator, bl, br, complex_: bool = False) -> dict:
+    """Gaussian blocks {(a, s, b): D_l[a] x D_r[b]} of a site tensor whose
+    non-zero blocks satisfy q_r[b] = q_l[a] + charge(s)."""
+    idx = {q: k for k, (q, _) in enumerate(br)}
+    out = {}
+    for a, (ql, dl) in enumerate(bl):
+        for s, cs in enumerate(U1_SPIN_CHARGE):
+            b = idx.get(ql + cs)
+            if b is None:
+                continue
+            dr = br[b][1]
+            out[(a, s, b)] = complex_gaussian(g, (dl, dr)) if complex_ else real_gaussian(g, (dl, dr))
+    return out
+
+
+def u1_gate(g: np.random.Generator) -> np.ndarray:
+    """Charge-conserving two-site gate (4 x 4, rows = outgoing pair, real
+    orthogonal): +-1 on up-up and down-down, a Haar 2 x 2 rotation on the
+    (up-down, down-up) pair."""
+    gm = np.zeros((4, 4))
+    gm[0, 0] = 1.0 if g.standard_normal() >= 0 else -1.0
+    gm[1:3, 1:3] = haar(g, 2, 2, complex_=False)
+    gm[3, 3] = 1.0 if g.standard_normal() >= 0 else -1.0
+    return gm
