@@ -30,6 +30,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+KERNEL_OF_CLASS = {  # kernel that carries each profiling class
+    "c64_bf16x3_planes": ("gemm_planes_kernel<true>", "paper_2512_23917_amd/csrc/bf16x3.hip"),
+    "c128_fp64": ("gemm_f64_kernel<cd,128,64>", "paper_2512_23917_amd/csrc/gemm.hip"),
+    "hemv": ("tri_colC_kernel<cd,32>", "paper_2512_23917_amd/csrc/eig.hip"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_planes_c64_chi1024.txt")
+
 PEAKS = {  # MI355X published dense peaks
     "c128_fp64": (78.6e12, "TFLOP/s", "mfma"),
     "f64_fp64": (78.6e12, "TFLOP/s", "mfma"),
@@ -37,6 +44,8 @@ PEAKS = {  # MI355X published dense peaks
     "f32_fp32": (157.3e12, "TFLOP/s", "mfma"),
     "c64_bf16x3": (2.5e15, "TFLOP/s", "mfma"),
     "f32_bf16x3": (2.5e15, "TFLOP/s", "mfma"),
+    "c64_bf16x3_planes": (2.5e15, "TFLOP/s", "mfma"),
+    "f32_bf16x3_planes": (2.5e15, "TFLOP/s", "mfma"),
     "hemv": (8.0e12, "GB/s", "hbm"),
 }
 
@@ -72,31 +81,39 @@ def make_inputs(tci, ctx, n_upd, chi, complex_dtype_plain, with_plain, with_mixe
     return plain, mixed, wt
 
 
-def run_step(tci, ctx, ins, w, chi, n_matvec, params, thetas):
-    """One pass of the hot path over the batch; returns the per-update infos and energies."""
+def run_step(tci, ctx, ins, w, chi, n_matvec, params, thetas, prev=None):
+    """One pass of the hot path over the batch; returns the split outputs and energies.
+    prev: per update the bond's kept spectrum of the previous step (learned sketch)."""
     energies = []
     for u, (a, b, left, right) in enumerate(ins):
         tci.contract(ctx, a, "asm", b, "mtb", "astb", out=thetas[u])
         energies.append(tci.lanczos_ground(ctx, left, w, w, right, thetas[u], n_matvec))
-    return tci.split_batched(ctx, thetas, params), energies
+    return tci.split_batched(ctx, thetas, params, prev_spectra=prev), energies
 
 
-def time_path(tci, ctx, ins, w, chi, n_matvec, params, steps, warmup, dtype, profile=False):
+def time_path(tci, ctx, ins, w, chi, n_matvec, params, steps, warmup, dtype, profile=False, first_params=None):
+    """first_params: parameters of the first pass (the learned sketch needs the
+    spectra of a previous pass; the first one uses the plain SVD)."""
     import torch
     d = 2
     thetas = [tci.Tensor.empty(ctx, dtype, chi * d * d * chi) for _ in ins]
     for t in thetas:
         tci.reshape(ctx, t, (chi, d, d, chi))
-    out = None
+    learned = first_params is not None
+    out, prev = None, None
     for i in range(warmup):
-        out = run_step(tci, ctx, ins, w, chi, n_matvec, params, thetas)
+        out = run_step(tci, ctx, ins, w, chi, n_matvec, first_params if (learned and prev is None) else params,
+                       thetas, prev)
+        prev = out[0][1] if learned else None
         log(f"  warmup {i + 1}/{warmup}")
     torch.cuda.synchronize()
     if profile:
         tci.profile_enable(ctx, True)
     t0 = time.perf_counter()
     for i in range(steps):
-        out = run_step(tci, ctx, ins, w, chi, n_matvec, params, thetas)
+        out = run_step(tci, ctx, ins, w, chi, n_matvec, first_params if (learned and prev is None) else params,
+                       thetas, prev)
+        prev = out[0][1] if learned else None
         log(f"  step {i + 1}/{steps}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -107,6 +124,36 @@ def time_path(tci, ctx, ins, w, chi, n_matvec, params, steps, warmup, dtype, pro
             prof[tag] = tci.profile_query(ctx, tag)
         tci.profile_enable(ctx, False)
     return dt, out, prof
+
+
+def traffic_per_launch(kernel, src):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel's source changed since it was taken."""
+    import hashlib
+    if src is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel") != kernel:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def host_threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return min(n, int(omp)) if omp and omp.isdigit() else n
 
 
 def cpu_baseline(chi, n_matvec, budget_s=20.0):
@@ -144,7 +191,7 @@ def cpu_baseline(chi, n_matvec, budget_s=20.0):
     oracle.svd_matrix(m)
     t_svd = (time.perf_counter() - t0) * (2 * chi / n) ** 3
     per_update = t_theta + n_matvec * t_mv + t_svd
-    return dict(value=1.0 / per_update, unit="updates/s", cores=os.cpu_count(), kind="oracle",
+    return dict(value=1.0 / per_update, unit="updates/s", cores=host_threads(), kind="oracle",
                 sample=(f"oracle slices of one chi={chi} update: theta rows 1/{chi // (rows * 2 // 2)}, "
                         f"H_eff matvec on {rows}/{chi} left rows x{n_matvec}, Jacobi SVD {n}x{n} scaled "
                         f"(2048/{n})^3; per-update estimate {per_update:.1f}s "
@@ -161,15 +208,30 @@ def main():
     ap.add_argument("--nmatvec", type=int, default=20)
     ap.add_argument("--eps", type=float, default=1e-8)
     ap.add_argument("--mixed", choices=["bf16x3", "fp32"], default="bf16x3")
+    ap.add_argument("--svd", choices=["learned", "plain"], default="learned",
+                    help="truncated SVD of the mixed path: learned sketch rank (plain fallback) or plain")
+    ap.add_argument("--model", default=None, help="sketch-model weights (default: the shipped file)")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-warmup", type=int, default=1)
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = 1 << 30
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
+        return
     from paper_2512_23917_amd import tci
     ctx = tci.Context(0)
     chi, U = args.chi, args.updates
@@ -180,9 +242,18 @@ def main():
     ctx.set_precision(mixed_prec)
     pm = tci.update_params(chi_min=1, chi_max=chi, target_trunc_err=args.eps, direction=tci.DIR_RIGHT,
                            precision=mixed_prec)
+    first = None
+    model = None
+    if args.svd == "learned":
+        from paper_2512_23917_amd import sketch_train
+        model = tci.SketchModel(ctx, path=args.model or sketch_train.DEFAULT_WEIGHTS)
+        first = pm
+        pm = tci.update_params(chi_min=1, chi_max=chi, target_trunc_err=args.eps, direction=tci.DIR_RIGHT,
+                               precision=mixed_prec, svd_mode=tci.SVD_LEARNED, power_iters=2, seed=1)
+        pm.sketch_model = model.h.value
     log("mixed path")
     t_mixed, (res_m, en_m), prof = time_path(tci, ctx, mixed_in, wt["mixed"], chi, args.nmatvec, pm,
-                                              args.steps, args.warmup, tci.C64, profile=True)
+                                              args.steps, args.warmup, tci.C64, profile=True, first_params=first)
     ups_mixed = U * args.steps / t_mixed
     infos_m = res_m[3]
 
@@ -193,24 +264,33 @@ def main():
         pp = tci.update_params(chi_min=1, chi_max=chi, target_trunc_err=args.eps, direction=tci.DIR_RIGHT,
                                precision=tci.PREC_FP64)
         t_plain, (res_p, en_p), _ = time_path(tci, ctx, plain_in, wt["plain"], chi, args.nmatvec, pp,
-                                              args.plain_steps, 0, tci.C128)
+                                              args.plain_steps, args.plain_warmup, tci.C128)
         ups_plain = U * args.plain_steps / t_plain
 
-    # dominant kernel of the measured (mixed) path
+    # dominant kernel class of the measured (mixed) path, summed over call sites
     roof = None
     if prof:
-        tag = max(prof, key=lambda k: prof[k][1])
-        cnt, ms, work = prof[tag]
-        cls = tag.split(":")[1]
+        by_cls = {}
+        for tag, (cnt, ms, work) in prof.items():
+            cls = tag.split(":")[1]
+            c = by_cls.setdefault(cls, [0, 0.0, 0.0, []])
+            c[0] += cnt
+            c[1] += ms
+            c[2] += work
+            c[3].append(tag.split(":")[0])
+        cls = max(by_cls, key=lambda k: by_cls[k][1])
+        cnt, ms, work, sites = by_cls[cls]
         peak, unit, bound = PEAKS.get(cls, (None, None, None))
         if peak:
             scale = 1e12 if unit == "TFLOP/s" else 1e9
             achieved = work / (ms * 1e-3)
+            kname, ksrc = KERNEL_OF_CLASS.get(cls, (cls, None))
             roof = {"bound": bound, "achieved": round(achieved / scale, 2), "peak": peak / scale, "unit": unit,
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": tag,
+                    "frac": round(achieved / peak, 4), "traffic": traffic_per_launch(kname, ksrc),
+                    "kernel": kname, "call_sites": sorted(set(sites)), "class": cls,
                     "launches": cnt, "avg_launch_ms": round(ms / max(cnt, 1), 4),
                     "work_per_launch": work / max(cnt, 1)}
-        share = {k: round(v[1] / (t_mixed * 1e3), 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]}
+        share = {k: round(v[1] / (t_mixed * 1e3), 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:8]}
         if roof:
             roof["time_share_top"] = share
 
@@ -231,9 +311,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 storage, bf16x3 contractions (fp32 accumulate), fp64 Krylov/Gram/eigensolve"
-                 if args.mixed == "bf16x3" else "c64 storage, fp32 contractions, fp64 Krylov/Gram/eigensolve",
-        "data": "synthetic (seeded Gaussian A, B; Hermitian Gaussian L, R; Heisenberg MPO)",
+        "dtype": "bf16x3+f64" if args.mixed == "bf16x3" else "f32+f64",
+        "data": "synthetic (seeded Gaussian A, B; channel-paired Hermitian Gaussian L, R; Heisenberg MPO)",
         "config": {"workload": f"dense two-site DMRG update chi={chi} d=2 w=5, {args.nmatvec} Lanczos matvecs, "
                                f"trunc_svd eps={args.eps} cap {chi}, {U} updates per step",
                    "updates_per_step": U, "chi": chi, "precision": args.mixed},
@@ -241,6 +320,11 @@ def main():
         "speedup_vs_plain_fp64": None if ups_plain is None else round(ups_mixed / ups_plain, 3),
         "kept_chi": [min(chis), max(chis)],
         "trunc_err": [min(i.trunc_err for i in infos_m), max(i.trunc_err for i in infos_m)],
+        "sketch": {"mode": args.svd,
+                   "fallback_rate": float(np.mean([i.used_fallback for i in infos_m])),
+                   "mean_sketch_rank": float(np.mean([i.sketch_rank for i in infos_m]))},
+        "precision_detail": "c64 storage; split-BF16x3 MFMA contractions with FP32 accumulation; "
+                            "FP64 Krylov basis, Gram, orthogonalisation and eigensolve",
         "energy_parity_mixed_vs_plain": None if en_p is None else
             float(max(abs(a - b) / abs(b) for a, b in zip(en_m, en_p))),
         "roofline": roof,

@@ -53,29 +53,28 @@ static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long
   return TCI_OK;
 }
 
-tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, const TruncParams& tp,
-                    TsvdOut& out) {
+tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, int kmax,
+                        TsvdStage& st) {
   hipStream_t s = ctx->stream;
   const size_t es = elem_bytes(wdt);
-  const bool cplx = is_complex(wdt);
   const int ng = std::min(m, n);
-  const bool left = (m <= n);
-  const int kmax = std::max(1, std::min(tp.chi_max, ng));
+  st.wdt = wdt; st.nb = nb; st.m = m; st.n = n; st.ng = ng; st.kmax = kmax;
+  st.left = (m <= n);
+  st.theta = theta;
   const long long smn = (long long)m * n;
-  out.kmax = kmax;
 
   // total weight
   ARENA(total, double, nb);
   ARENA(partial, double, (size_t)nb * SUMSQ_PARTIALS);
   TCI_CHECK_HIP(sumsq_batched(wdt, theta, smn, smn, total, partial, nb, s));
-  out.total = total;
+  st.total = total;
 
   // Gram matrix
   ARENA(Gm, char, es * (size_t)ng * ng * nb);
   const long long sG = (long long)ng * ng;
   {
-    GemmArgs g = left ? gemm_args(ng, ng, n, OP_N, OP_C, theta, n, theta, n, Gm, ng)
-                      : gemm_args(ng, ng, m, OP_C, OP_N, theta, n, theta, n, Gm, ng);
+    GemmArgs g = st.left ? gemm_args(ng, ng, n, OP_N, OP_C, theta, n, theta, n, Gm, ng)
+                         : gemm_args(ng, ng, m, OP_C, OP_N, theta, n, theta, n, Gm, ng);
     g.sA = smn; g.sB = smn; g.sC = sG; g.batch = nb;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
@@ -87,7 +86,8 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   ARENA(Vt, char, es * (size_t)ng * ng * nb);
   ARENA(Wp, char, es * (size_t)ng * TRIDIAG_NB * nb);
   ARENA(y, char, es * (size_t)ng * nb);
-  TriArgs ta{};
+  TriArgs& ta = st.ta;
+  ta = TriArgs{};
   ta.n = ng;
   ta.G = Gm; ta.ldg = ng; ta.sG = sG;
   ta.d = d; ta.e = e; ta.sde = ng;
@@ -98,38 +98,32 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   ta.sws = (long long)tridiag_ws_bytes(wdt, ng);
   ta.ws = ctx->arena.get((size_t)ta.sws * nb);
   if (!ta.ws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
-  TCI_CHECK_HIP(hipMemsetAsync(e, 0, sizeof(double) * (size_t)ng * nb, s));
+  TCI_CHECK_HIP(zero_fill(e, sizeof(double) * (size_t)ng * nb, s));
   TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
-  // top eigenvalues and the truncation rule
+  st.d = d; st.e = e; st.e2 = e2;
+  // top eigenvalues
   ARENA(lam, double, (size_t)kmax * nb);
   TCI_CHECK_HIP(tridiag_eigvals_top(d, e, e2, ng, ng, kmax, lam, kmax, nb, s));
-  ARENA(chi, int, nb);
-  ARENA(err, double, nb);
-  ARENA(disc, double, nb);
-  ARENA(sv, double, (size_t)kmax * nb);
-  ARENA(sinv, double, (size_t)kmax * nb);
-  ARENA(sn, double, (size_t)kmax * nb);
-  TCI_CHECK_HIP(trunc_select(lam, kmax, kmax, total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
-  out.chi = chi; out.s = sv; out.sn = sn;
-  out.chi_h.resize(nb); out.err_h.resize(nb); out.disc_h.resize(nb); out.total_h.resize(nb);
-  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), total, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipStreamSynchronize(s));
-  for (int b = 0; b < nb; ++b)
-    if (!std::isfinite(out.total_h[b])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in theta");
-  int kz = 1;
-  for (int b = 0; b < nb; ++b) kz = std::max(kz, out.chi_h[b]);
-  out.kz = kz;
+  st.lam = lam;
+  return TCI_OK;
+}
 
+tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, int kz, const double* sinv,
+                        TsvdOut& out) {
+  hipStream_t s = ctx->stream;
+  const int wdt = st.wdt, nb = st.nb, m = st.m, n = st.n, ng = st.ng, kmax = st.kmax;
+  const size_t es = elem_bytes(wdt);
+  const bool cplx = is_complex(wdt);
+  const long long smn = (long long)m * n;
+  const void* theta = st.theta;
+  out.kz = kz;
   // eigenvectors of T (real), orthonormalised
   ARENA(Z, double, (size_t)ng * kz * nb);
   ARENA(Z2, double, (size_t)ng * kz * nb);
   ARENA(iw, double, (size_t)4 * ng * kz * nb);
   const long long sZ = (long long)ng * kz;
-  TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)sZ * nb, s));
-  TCI_CHECK_HIP(tridiag_invit(d, e, ng, ng, lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
+  TCI_CHECK_HIP(zero_fill(Z, sizeof(double) * (size_t)sZ * nb, s));
+  TCI_CHECK_HIP(tridiag_invit(st.d, st.e, ng, ng, st.lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
   TCI_TRY(cholqr2(ctx, F64, 0, Z, kz, sZ, ng, kz, Z2, nb));
   // back-transformation to eigenvectors of G
   void* Ev;
@@ -143,12 +137,12 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   const int npan = (ng - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB;
   ARENA(Tf, char, es * (size_t)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB * nb);
   ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * kz * nb);
-  TCI_CHECK_HIP(tridiag_backtransform(wdt, ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
+  TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
                                       kz, sZ, kz, btw, nb, s));
   // left factor U (m x kz)
   const long long sU = (long long)m * kz;
   void* U;
-  if (left) {
+  if (st.left) {
     U = Ev;  // m == ng
   } else {
     // U = theta V diag(1/s), then orthonormalise its columns
@@ -177,6 +171,37 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   out.U = U;
   out.Vh = Vh;
   return TCI_OK;
+}
+
+tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, const TruncParams& tp,
+                    TsvdOut& out) {
+  hipStream_t s = ctx->stream;
+  const int ng = std::min(m, n);
+  const int kmax = std::max(1, std::min(tp.chi_max, ng));
+  out.kmax = kmax;
+  TsvdStage st;
+  TCI_TRY(tsvd_eigvals(ctx, wdt, nb, m, n, theta, kmax, st));
+  out.total = st.total;
+  // the truncation rule
+  ARENA(chi, int, nb);
+  ARENA(err, double, nb);
+  ARENA(disc, double, nb);
+  ARENA(sv, double, (size_t)kmax * nb);
+  ARENA(sinv, double, (size_t)kmax * nb);
+  ARENA(sn, double, (size_t)kmax * nb);
+  TCI_CHECK_HIP(trunc_select(st.lam, kmax, kmax, st.total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
+  out.chi = chi; out.s = sv; out.sn = sn;
+  out.chi_h.resize(nb); out.err_h.resize(nb); out.disc_h.resize(nb); out.total_h.resize(nb);
+  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), st.total, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(out.total_h[b])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in theta");
+  int kz = 1;
+  for (int b = 0; b < nb; ++b) kz = std::max(kz, out.chi_h[b]);
+  return tsvd_vectors(ctx, st, chi, kz, sinv, out);
 }
 
 static tci_status matricize(tci_tensor a, int k_rows, int64_t& rows, int64_t& cols) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <vector>
 
+#include "eig.hpp"
 #include "linalg.hpp"
 #include "runtime.hpp"
 
@@ -27,6 +28,23 @@ struct TsvdOut {
 // only for reading.  The rule of trunc_svd form (2) selects chi per problem.
 tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* theta,
                     const TruncParams& tp, TsvdOut& out);
+
+// The two halves of tsvd_run, for callers that choose chi themselves (the
+// block-sparse update truncates across sectors).  tsvd_eigvals: total weight,
+// Gram matrix, tridiagonal reduction and the kmax largest Gram eigenvalues
+// (descending, st.lam, stride kmax).  tsvd_vectors: for chi[b] <= kz kept
+// values with 1/s in sinv (stride kmax), U (m x kz) and V^H (kz x n).
+struct TsvdStage {
+  int wdt = 0, nb = 0, m = 0, n = 0, ng = 0, kmax = 0;
+  bool left = true;
+  const void* theta = nullptr;
+  TriArgs ta{};
+  double *d = nullptr, *e = nullptr, *e2 = nullptr, *lam = nullptr, *total = nullptr;
+};
+tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, int kmax,
+                        TsvdStage& st);
+tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, int kz, const double* sinv,
+                        TsvdOut& out);
 
 }  // namespace tci
 
