@@ -352,6 +352,73 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
                               tci_tensor R, tci_tensor theta_inout, int n_matvec, double* energy);
 
 /* ------------------------------------------------------------------ */
+/* U(1) block-sparse two-site update                                    */
+/* ------------------------------------------------------------------ */
+/* A site tensor of an MPS with a conserved U(1) charge (2 S^z for spin 1/2),
+ * the symmetric-tensor form that the paper names as the extension of its
+ * dense interface (Sec. V, future work).  Its left and right bonds are lists
+ * of sectors (charge q, dimension D); the physical index has d = 2 with
+ * charges +1 (index 0) and -1 (index 1).  Block (a, s, b) is non-zero only
+ * when q_right[b] = q_left[a] + charge(s); each allowed block is a
+ * D_left[a] x D_right[b] row-major matrix, and the blocks are stored back to
+ * back in one device buffer in the order of (a, s) ascending.  The handle
+ * owns the buffer. */
+typedef struct tci_bs_tensor_s* tci_bs_tensor;
+
+/* Create a block-sparse site tensor (F32 or F64; storage uninitialised).
+ * Charges within a bond must be distinct; dimensions >= 0.  n_left = n_right
+ * = 0 gives an empty placeholder for an output argument. */
+tci_status tci_bs_create(tci_context ctx, tci_dtype dtype, int n_left, const int32_t* q_left,
+                         const int64_t* d_left, int n_right, const int32_t* q_right,
+                         const int64_t* d_right, tci_bs_tensor* out);
+tci_status tci_bs_destroy(tci_context ctx, tci_bs_tensor t);
+/* Sector counts of the two bonds and the number of stored blocks. */
+tci_status tci_bs_dims(tci_context ctx, tci_bs_tensor t, int* n_left, int* n_right, int* n_blocks,
+                       int64_t* n_elems);
+/* Charges and dimensions of the bonds (arrays of n_left / n_right entries). */
+tci_status tci_bs_bonds(tci_context ctx, tci_bs_tensor t, int32_t* q_left, int64_t* d_left,
+                        int32_t* q_right, int64_t* d_right);
+/* Block i: sector indices (a, s, b) and its element offset in the buffer. */
+tci_status tci_bs_block_info(tci_context ctx, tci_bs_tensor t, int i, int* a, int* s, int* b,
+                             int64_t* offset);
+/* Whole-buffer host copies (bytes = n_elems * element size); synchronous. */
+tci_status tci_bs_from_host(tci_context ctx, tci_bs_tensor t, const void* host, size_t bytes);
+tci_status tci_bs_to_host(tci_context ctx, tci_bs_tensor t, void* host, size_t bytes);
+
+/* n independent U(1) two-site updates (the block form of
+ * tci_two_site_update_batched; Sec. II.B contraction and decomposition
+ * equations applied sector by sector).  For update i, A[i]'s right bond must
+ * equal B[i]'s left bond.  gates[i] (nullable array or entries) is a 4 x 4
+ * (or 2,2,2,2) charge-conserving gate with rows = outgoing pair, in any real
+ * dtype; off-sector entries are ignored.  Per update:
+ *   theta'(a, s1', s2', b) = sum G[(s1' s2'), (s1 s2)] A[a, s1, m] B[m, s2, b]
+ * built directly into the sector matrices of the new bond (sector Q: rows
+ * (a, s1') with q_a + charge(s1') = Q, columns (s2', b)) by grouped FP32
+ * GEMMs in one launch per accumulation phase for all updates; each sector is
+ * split by the plain FP64 truncated SVD (Gram, tridiagonal eigensolve); the
+ * singular values of all sectors of the update are merged in descending
+ * order (ties: sector charge ascending, then in-sector index) and cut once by
+ * the trunc_svd rule under params (chi_min, chi_max, target, s_min) with the
+ * total weight ||theta'||_F^2; s is renormalised over the kept set.
+ * Outputs: A_out[i] (bonds: A's left, new bond), B_out[i] (new bond, B's
+ * right) re-created by the library in the input dtype, written as in
+ * params.direction; the new bond holds the sectors with a kept value, in
+ * ascending charge.  s_out[i]: F64 vector of the kept values in bond order
+ * (sector by sector, descending within a sector).  chi_max_each (nullable):
+ * per-update caps that replace params->chi_max.  infos (nullable) as for
+ * the dense update.  The tile shape of the grouped GEMM is autotuned per
+ * problem-size signature on first use.  The first half of the update
+ * (products, padding, Gram matrices, eigenvalue stage) is recorded as a HIP
+ * graph the second time a problem structure is seen and replayed from then
+ * on (not while tci_profile_enable is on, nor with TCI_NO_GRAPHS set).
+ * Synchronous. */
+tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_tensor* A,
+                                          const tci_bs_tensor* B, const tci_tensor* gates,
+                                          const tci_update_params* params, const int64_t* chi_max_each,
+                                          tci_bs_tensor* A_out, tci_tensor* s_out, tci_bs_tensor* B_out,
+                                          tci_update_info* infos);
+
+/* ------------------------------------------------------------------ */
 /* Sketch-rank model for TCI_SVD_LEARNED                                */
 /* ------------------------------------------------------------------ */
 /* A perceptron 35 -> 128 -> 128 -> 1 with exact GELU that predicts

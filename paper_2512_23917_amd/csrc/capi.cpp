@@ -173,6 +173,7 @@ tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream)
 tci_status tci_destroy_context(tci_context ctx) {
   TCI_TRY(check_ctx(ctx));
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->bs_graphs.reset();
   ctx->arena.release();
   ctx->magic = 0;
   delete ctx;

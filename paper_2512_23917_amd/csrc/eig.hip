@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "gemm.hpp"
 #include "eig.hpp"
+#include "vecops.hpp"
 #include "prof.hpp"
 
 namespace tci {
@@ -73,12 +74,14 @@ __device__ inline cd bsum(cd v, double* sh) {
 //      w(r) = tau (y(r) - V(r,:) t1 - W(r,:) t2) + alpha v(r),  y(r) = sum_t P[t][r];
 //    update column i: a(r,i) -= V(r,:) conj(W(i,:)) + W(r,:) conj(V(i,:));
 //    d_i = Re a(i,i); partial ||a(i+2:n,i)||^2 reduced by the last workgroup.
-//  colC (lower-triangle tiles TT x TT of the trailing matrix):
+//  colC (lower-triangle tiles TT x TT of the trailing matrix, CH tiles of a
+//    block row per workgroup):
 //    reflector of a(i+1:n,i): beta = -sign(Re a) ||.||, tau = (beta - a)/beta,
-//    v = [1, x / (a - beta)];  tile (R,C), C <= R, adds A_RC v_C to P[C][R rows]
-//    and, for C < R, A_RC^H v_R to P[R][C rows]; partial quadratic form
-//    v^H A v and, on diagonal tiles, t1 = W^H v and t2 = V^H v over its rows;
-//    the last workgroup reduces the partials.
+//    v = [1, x / (a - beta)];  the chunk of tiles (R, cA..cB) adds
+//    sum_C A_RC v_C to P[cA][R rows], and each tile with C < R adds A_RC^H v_R
+//    to P[R][C rows]; partial quadratic form v^H A v and, with the diagonal
+//    tile, t1 = W^H v and t2 = V^H v over its rows; the last workgroup
+//    reduces the partials.
 // Every tile of the lower triangle is read once per column.
 // ---------------------------------------------------------------------------
 constexpr int TT = 64;
@@ -98,6 +101,25 @@ struct TriWs {
   __host__ __device__ static int ntile(int n) { return nbt(n) * (nbt(n) + 1) / 2; }
   __host__ __device__ static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
 };
+
+// Tiles per workgroup of the trailing matvec: band R (rows R*TT ...) is cut
+// into chunks of up to CH consecutive tiles C, and one workgroup handles one
+// chunk, so that the reflector set-up and the final reduction are paid once
+// per chunk.  The row sums of a chunk starting at tile cA go to P[cA][rows];
+// the column sums of an off-diagonal tile (R, C) go to P[R][columns of C].
+constexpr int CH = 4;
+
+__host__ __device__ inline int tri_chunks(int nact) {
+  int k = 0;
+  for (int t = 1; t <= nact; ++t) k += (t + CH - 1) / CH;
+  return k;
+}
+
+// Is P[t][r] written in the column step whose first active block is b0?
+__device__ inline bool tri_slot_used(int t, int r, int b0) {
+  const int Rr = r / TT;
+  return t > Rr || ((t - b0) % CH == 0);
+}
 
 // Sum of a per-thread complex / real value over groups of 4 consecutive lanes.
 template <typename T>
@@ -184,7 +206,8 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     // w for this thread's row (4 threads share a row: each sums a quarter)
     T acc = EigT<T>::zero();
     if (rv) {
-      for (int t = tb0 + part; t < nbt; t += 4) acc = add(acc, P[(long)t * n + r]);
+      for (int t = tb0 + part; t < nbt; t += 4)
+        if (tri_slot_used(t, r, tb0)) acc = add(acc, P[(long)t * n + r]);
       for (int q = part; q < pp; q += 4) {
         acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], s_t1[q]));
         acc = sub(acc, mulr(W[(long)r * NB + q], s_t2[q]));
@@ -227,7 +250,8 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     const int pp = p - 1;
     T acc = EigT<T>::zero();
     const int tb0 = (ifin + 1) / TT, nbt = TriWs<T, NB>::nbt(n);
-    for (int t = tb0 + tid; t < nbt; t += 256) acc = add(acc, P[(long)t * n + i]);
+    for (int t = tb0 + tid; t < nbt; t += 256)
+      if (tri_slot_used(t, i, tb0)) acc = add(acc, P[(long)t * n + i]);
     if (tid < pp) {
       acc = sub(acc, mulr(V[(long)(j0 + tid) * n + i], s_t1[tid]));
       acc = sub(acc, mulr(W[(long)i * NB + tid], s_t2[tid]));
@@ -303,9 +327,9 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
 
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0) {
-  __shared__ T s_vR[TT], s_vC[TT];
+  __shared__ T s_vR[TT];
   __shared__ T s_q[4];
-  __shared__ T s_colsum[4][TT];
+  __shared__ T s_colsum[2][4][TT];
   __shared__ T s_tt[4][2 * NB];
   static_assert(2 * NB == TT, "t1/t2 thread mapping assumes 2 NB == TT");
   __shared__ int s_last;
@@ -322,20 +346,24 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   const T* G = reinterpret_cast<const T*>(a.G) + b * a.sG;
   T* V = reinterpret_cast<T*>(a.Vt) + b * a.sVt;
   const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
-  // tile (R, C), C <= R, among the active blocks [b0, nbt)
+  // chunk -> (band R, first tile cA, last tile cB)
   const int b0 = (i + 1) / TT;
-  int k = blockIdx.x, Rp = 0;
-  while ((Rp + 1) * (Rp + 2) / 2 <= k) ++Rp;
-  const int Cp = k - Rp * (Rp + 1) / 2;
-  const int R = b0 + Rp, C = b0 + Cp;
-  const bool diag = (R == C);
+  int k = blockIdx.x, R = b0;
+  for (;;) {
+    const int nch = (R - b0 + CH) / CH;
+    if (k < nch) break;
+    k -= nch;
+    ++R;
+  }
+  const int cA = b0 + k * CH, cB = min(R, cA + CH - 1);
+  const bool has_diag = (cB == R);
   // reflector scalars (every workgroup computes them from the reduced norm)
   if (tid == 0) {
     double beta;
     T tv, sc;
     reflector(xv[i + 1], fa[0], beta, tv, sc);
     s_scal = sc;
-    if (k == 0) {
+    if (blockIdx.x == 0) {
       a.e[b * a.sde + i] = beta;
       reinterpret_cast<T*>(a.tau)[b * a.stau + i] = tv;
     }
@@ -347,91 +375,110 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
     if (c == i + 1) return EigT<T>::one();
     return mulr(xv[c], scal);
   };
-  if (tid < TT) {
-    s_vR[tid] = vval(R * TT + tid);
-    s_vC[tid] = vval(C * TT + tid);
-  }
+  if (tid < TT) s_vR[tid] = vval(R * TT + tid);
   __syncthreads();
-  // reflector i into Vt (diagonal tiles own their rows; tile 0 zeroes the rows above)
-  if (diag && tid < TT) {
+  // reflector i into Vt (the chunk holding the diagonal tile owns band R's
+  // rows; chunk 0 zeroes the rows above the active blocks)
+  if (has_diag && tid < TT) {
     const int rr = R * TT + tid;
     if (rr < n) V[(long)i * n + rr] = s_vR[tid];
   }
-  if (k == 0)
+  if (blockIdx.x == 0)
     for (int rr = tid; rr < b0 * TT; rr += 256) V[(long)i * n + rr] = EigT<T>::zero();
-  // load the tile: thread (cl, rg) holds rows rg + 4 kk (kk < 16) of column cl
+
   const int cl = tid & 63, rg = tid >> 6;
-  const int c = C * TT + cl;
-  const bool cok = (c > i) && (c < n);
-  T colacc = EigT<T>::zero();
-  T ps[TT / 4];
+  // row-sum accumulators of the two row halves (diagonal / off-diagonal tiles)
+  T rs_off0 = EigT<T>::zero(), rs_off1 = EigT<T>::zero();
+  T rs_dg0 = EigT<T>::zero(), rs_dg1 = EigT<T>::zero();
+#pragma unroll 1
+  for (int C = cA; C <= cB; ++C) {
+    const bool diag = (C == R);
+    const int c = C * TT + cl;
+    const bool cok = (c > i) && (c < n);
+    const T vc = vval(c);
+    T colacc = EigT<T>::zero();
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      T ps[8];
 #pragma unroll
-  for (int kk = 0; kk < TT / 4; ++kk) {
-    const int rl = rg + 4 * kk;
-    const int r = R * TT + rl;
-    T g = EigT<T>::zero();
-    if (cok && r > i && r < n) g = G[(long)r * a.ldg + c];
-    ps[kk] = mulr(g, s_vC[cl]);                       // row-sum term
-    colacc = add(colacc, mulr(cj(g), s_vR[rl]));      // column-sum term
-  }
-  // Row sums: butterfly reduce-scatter over lane bits 5..2 leaves lane l with
-  // the partial of kk = (l >> 2) & 15 over 16 lanes, then bits 1..0 finish it.
+      for (int kk = 0; kk < 8; ++kk) {
+        const int rl = rg + 4 * (kk + 8 * h);
+        const int r = R * TT + rl;
+        T g = EigT<T>::zero();
+        if (cok && r > i && r < n) g = G[(long)r * a.ldg + c];
+        ps[kk] = mulr(g, vc);                           // row-sum term
+        colacc = add(colacc, mulr(cj(g), s_vR[rl]));    // column-sum term
+      }
+      // butterfly over lane bits 5..3 leaves lane l the partial of
+      // kk = (l >> 3) & 7 over 8 lanes; bits 2..0 finish the sum
 #pragma unroll
-  for (int half = 8, bit = 32; half >= 1; half >>= 1, bit >>= 1) {
-    const bool hi = (cl & bit) != 0;
+      for (int half = 4, bit = 32; half >= 1; half >>= 1, bit >>= 1) {
+        const bool hi = (cl & bit) != 0;
 #pragma unroll
-    for (int t = 0; t < half; ++t) {
-      const T mine = hi ? ps[t + half] : ps[t];
-      const T other = hi ? ps[t] : ps[t + half];
-      ps[t] = add(mine, shfl_xor_t(other, bit));
-    }
-  }
-  T rs = add(ps[0], shfl_xor_t(ps[0], 1));
-  rs = add(rs, shfl_xor_t(rs, 2));
-  T qacc = EigT<T>::zero();
-  {
-    const int kk = (cl >> 2) & 15, rl = rg + 4 * kk, r = R * TT + rl;
-    if ((cl & 3) == 0 && r < n) {
-      P[(long)C * n + r] = rs;
-      qacc = mulr(cj(s_vR[rl]), rs);
-    }
-  }
-  qacc = wsum(qacc);
-  if (cl == 0) s_q[rg] = qacc;
-  s_colsum[rg][cl] = colacc;
-  // t1 = W^H v and t2 = V^H v over this diagonal tile's rows: thread (q, part)
-  // with q < NB for W's column q, q >= NB for V's row q - NB, rows part*16 ...
-  if (diag) {
-    const int q = tid & 63, part = tid >> 6, qq = q & (NB - 1);
-    T acc = EigT<T>::zero();
-    if (qq < p) {
-#pragma unroll
-      for (int kk = 0; kk < TT / 4; ++kk) {
-        const int rl = part * (TT / 4) + kk, r = R * TT + rl;
-        if (r > i && r < n) {
-          const T other = q < NB ? W[(long)r * NB + qq] : V[(long)(j0 + qq) * n + r];
-          acc = add(acc, mulr(cj(other), s_vR[rl]));
+        for (int t = 0; t < half; ++t) {
+          const T mine = hi ? ps[t + half] : ps[t];
+          const T other = hi ? ps[t] : ps[t + half];
+          ps[t] = add(mine, shfl_xor_t(other, bit));
         }
       }
+      T v = add(ps[0], shfl_xor_t(ps[0], 4));
+      v = add(v, shfl_xor_t(v, 2));
+      v = add(v, shfl_xor_t(v, 1));
+      if (diag) {
+        if (h == 0) rs_dg0 = add(rs_dg0, v);
+        else rs_dg1 = add(rs_dg1, v);
+      } else {
+        if (h == 0) rs_off0 = add(rs_off0, v);
+        else rs_off1 = add(rs_off1, v);
+      }
     }
-    s_tt[part][q] = acc;
+    if (!diag) {
+      const int sb = (C - cA) & 1;
+      s_colsum[sb][rg][cl] = colacc;
+      __syncthreads();
+      if (tid < TT) {
+        const T cs = add(add(s_colsum[sb][0][tid], s_colsum[sb][1][tid]),
+                         add(s_colsum[sb][2][tid], s_colsum[sb][3][tid]));
+        const int cc = C * TT + tid;
+        if (cc < n) P[(long)R * n + cc] = cs;
+      }
+    } else {
+      // t1 = W^H v and t2 = V^H v over the diagonal tile's rows: thread
+      // (q, part), q < NB for W's column q, q >= NB for V's row q - NB
+      const int q = tid & 63, part = tid >> 6, qq = q & (NB - 1);
+      T acc = EigT<T>::zero();
+      if (qq < p) {
+#pragma unroll 4
+        for (int kk = 0; kk < TT / 4; ++kk) {
+          const int rl = part * (TT / 4) + kk, r = R * TT + rl;
+          if (r > i && r < n) {
+            const T other = q < NB ? W[(long)r * NB + qq] : V[(long)(j0 + qq) * n + r];
+            acc = add(acc, mulr(cj(other), s_vR[rl]));
+          }
+        }
+      }
+      s_tt[part][q] = acc;
+    }
   }
+  // row sums of the chunk -> P[cA][rows]; quadratic-form pieces
+  T qd = EigT<T>::zero(), qo = EigT<T>::zero();
+  if ((cl & 7) == 0) {
+    const int rl0 = rg + 4 * ((cl >> 3) & 7), rl1 = rl0 + 32;
+    const int r0 = R * TT + rl0, r1 = R * TT + rl1;
+    if (r0 < n) P[(long)cA * n + r0] = add(rs_dg0, rs_off0);
+    if (r1 < n) P[(long)cA * n + r1] = add(rs_dg1, rs_off1);
+    qd = add(mulr(cj(s_vR[rl0]), rs_dg0), mulr(cj(s_vR[rl1]), rs_dg1));
+    qo = add(mulr(cj(s_vR[rl0]), rs_off0), mulr(cj(s_vR[rl1]), rs_off1));
+  }
+  qd = wsum(qd);
+  qo = wsum(qo);
+  if (cl == 0) s_q[rg] = add(add(qd, qo), cj(qo));
   __syncthreads();
-  if (!diag && tid < TT) {
-    T cs = add(add(s_colsum[0][tid], s_colsum[1][tid]), add(s_colsum[2][tid], s_colsum[3][tid]));
-    const int cc = C * TT + tid;
-    if (cc < n) P[(long)R * n + cc] = cs;
-  }
-  // partials of this tile: quadratic form, and t1, t2 on diagonal tiles
-  T* mypc = pc + (long)k * (1 + 2 * NB);
-  if (tid == 0) {
-    T q = add(add(s_q[0], s_q[1]), add(s_q[2], s_q[3]));
-    if (!diag) q = add(q, cj(q));
-    mypc[0] = q;
-  }
+  T* mypc = pc + (long)blockIdx.x * (1 + 2 * NB);
+  if (tid == 0) mypc[0] = add(add(s_q[0], s_q[1]), add(s_q[2], s_q[3]));
   if (tid < 2 * NB)
-    mypc[1 + tid] = diag ? add(add(s_tt[0][tid], s_tt[1][tid]), add(s_tt[2][tid], s_tt[3][tid]))
-                         : EigT<T>::zero();
+    mypc[1 + tid] = has_diag ? add(add(s_tt[0][tid], s_tt[1][tid]), add(s_tt[2][tid], s_tt[3][tid]))
+                             : EigT<T>::zero();
   __syncthreads();
   if (tid == 0) {
     __threadfence();
@@ -440,7 +487,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   }
   __syncthreads();
   if (s_last) {
-    // acquire, then 4 lanes per output value sum interleaved tile partials
+    // acquire, then 4 lanes per output value sum interleaved chunk partials
     __threadfence();
     const int g = tid >> 2, j = tid & 3;
     for (int o = g; o < 1 + 2 * NB; o += 64) {
@@ -469,7 +516,7 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
         const int nact = nbt - (i + 1) / TT;
         // algorithmic bytes: the lower triangle of the trailing matrix read once
         ProfScope ps(s, 0.5 * (double)(n - i - 1) * (n - i) * sizeof(T) * batch, "hemv");
-        hipLaunchKernelGGL((tri_colC_kernel<T, NB>), dim3(nact * (nact + 1) / 2, batch), dim3(256), 0, s, a, i, j0);
+        hipLaunchKernelGGL((tri_colC_kernel<T, NB>), dim3(tri_chunks(nact), batch), dim3(256), 0, s, a, i, j0);
       }
     }
     const int t = j0 + pe;
@@ -505,7 +552,7 @@ size_t tridiag_ws_bytes(int dtype, int n) {
 hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s) {
   if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
   if (a.sws < (long long)tridiag_ws_bytes(dtype, a.n)) return hipErrorInvalidValue;
-  hipError_t e = hipMemsetAsync(a.ws, 0, (size_t)a.sws * batch, s);
+  hipError_t e = zero_fill(a.ws, (size_t)a.sws * batch, s);
   if (e != hipSuccess) return e;
   if (dtype == C128) return tridiag_impl<cd, TRIDIAG_NB>(a, batch, s);
   return tridiag_impl<double, TRIDIAG_NB>(a, batch, s);

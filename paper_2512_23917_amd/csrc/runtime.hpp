@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,24 @@ struct Arena {
   }
   void* get(size_t bytes);
   void release();
+  // bytes in use per chunk, and (address, capacity) per chunk, so that a
+  // caller replaying a recorded sequence of allocations can restore the state
+  std::vector<size_t> used_state() const {
+    std::vector<size_t> u;
+    for (const auto& c : chunks) u.push_back(c.used);
+    return u;
+  }
+  void restore(const std::vector<size_t>& u) {
+    for (size_t i = 0; i < chunks.size() && i < u.size(); ++i) chunks[i].used = u[i];
+  }
+  std::vector<long long> layout() const {
+    std::vector<long long> l;
+    for (const auto& c : chunks) {
+      l.push_back((long long)(uintptr_t)c.ptr);
+      l.push_back((long long)c.cap);
+    }
+    return l;
+  }
 };
 
 }  // namespace tci
@@ -45,6 +64,8 @@ struct tci_context_s {
   int verbose = 0;
   int precision = TCI_PREC_FP32;  // mixed precision for F32 / C64 contractions
   tci::Arena arena;
+  // recorded HIP graphs of the block-sparse update (owned; see bsparse.cpp)
+  std::shared_ptr<void> bs_graphs;
   uint32_t magic = 0x7C1C0DE1u;
 };
 

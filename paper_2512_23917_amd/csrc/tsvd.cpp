@@ -21,6 +21,7 @@
 #include "eig.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
+#include "prof.hpp"
 #include "runtime.hpp"
 #include "tsvd.hpp"
 #include "vecops.hpp"
@@ -73,6 +74,7 @@ tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const vo
   ARENA(Gm, char, es * (size_t)ng * ng * nb);
   const long long sG = (long long)ng * ng;
   {
+    ProfTag tag("svd_gram");
     GemmArgs g = st.left ? gemm_args(ng, ng, n, OP_N, OP_C, theta, n, theta, n, Gm, ng)
                          : gemm_args(ng, ng, m, OP_C, OP_N, theta, n, theta, n, Gm, ng);
     g.sA = smn; g.sB = smn; g.sC = sG; g.batch = nb;
@@ -99,7 +101,10 @@ tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const vo
   ta.ws = ctx->arena.get((size_t)ta.sws * nb);
   if (!ta.ws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(zero_fill(e, sizeof(double) * (size_t)ng * nb, s));
-  TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
+  {
+    ProfTag tag("svd_tridiag");
+    TCI_CHECK_HIP(tridiagonalize(wdt, ta, nb, s));
+  }
   st.d = d; st.e = e; st.e2 = e2;
   // top eigenvalues
   ARENA(lam, double, (size_t)kmax * nb);
@@ -137,8 +142,12 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
   const int npan = (ng - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB;
   ARENA(Tf, char, es * (size_t)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB * nb);
   ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * kz * nb);
-  TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
-                                      kz, sZ, kz, btw, nb, s));
+  {
+    ProfTag tag("svd_backtr");
+    TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
+                                        kz, sZ, kz, btw, nb, s));
+  }
+  ProfTag tag_uv("svd_uv");
   // left factor U (m x kz)
   const long long sU = (long long)m * kz;
   void* U;

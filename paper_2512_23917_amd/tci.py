@@ -128,6 +128,15 @@ def lib():
         "tci_profile_enable": (i32, [p, ctypes.c_int]),
         "tci_profile_query": (i32, [p, ctypes.c_char_p, P(i64), P(f64), P(f64)]),
         "tci_profile_tags": (i32, [p, ctypes.c_char_p, ctypes.c_int]),
+        "tci_bs_create": (i32, [p, ctypes.c_int, ctypes.c_int, P(i32), P(i64), ctypes.c_int, P(i32), P(i64), P(p)]),
+        "tci_bs_destroy": (i32, [p, p]),
+        "tci_bs_dims": (i32, [p, p, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(i64)]),
+        "tci_bs_bonds": (i32, [p, p, P(i32), P(i64), P(i32), P(i64)]),
+        "tci_bs_block_info": (i32, [p, p, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(i64)]),
+        "tci_bs_from_host": (i32, [p, p, p, ctypes.c_size_t]),
+        "tci_bs_to_host": (i32, [p, p, p, ctypes.c_size_t]),
+        "tci_bs_two_site_update_batched": (i32, [p, ctypes.c_int, P(p), P(p), P(p), P(UpdateParams), P(i64),
+                                                 P(p), P(p), P(p), P(UpdateInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -531,3 +540,101 @@ def philox_blocks(ctx: Context, seed: int, stream: int, first: int, n: int) -> n
     _check(lib().tci_philox_blocks(ctx.h, seed, stream, first, n, ctypes.c_void_p(out.data_ptr())), "tci_philox_blocks")
     torch.cuda.synchronize(ctx.torch_device)
     return out.cpu().numpy().view(np.uint32)
+
+
+class BsTensor:
+    """tci_bs_tensor: a U(1) block-sparse site tensor (F32).  Bonds are lists
+    of (charge, dim); blocks are {(a, s, b): (D_l[a], D_r[b]) array}."""
+
+    def __init__(self, ctx: Context, left=(), right=()):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ql = (ctypes.c_int32 * max(1, len(left)))(*[q for q, _ in left])
+        dl = (ctypes.c_int64 * max(1, len(left)))(*[d for _, d in left])
+        qr = (ctypes.c_int32 * max(1, len(right)))(*[q for q, _ in right])
+        dr = (ctypes.c_int64 * max(1, len(right)))(*[d for _, d in right])
+        _check(lib().tci_bs_create(ctx.h, F32, len(left), ql, dl, len(right), qr, dr, ctypes.byref(h)),
+               "tci_bs_create")
+        self.h = h
+
+    @classmethod
+    def from_blocks(cls, ctx: Context, left, right, blocks: dict) -> "BsTensor":
+        t = cls(ctx, left, right)
+        buf = np.zeros(t.nelem(), dtype=np.float32)
+        for (a, s, b), off in t.layout().items():
+            blk = blocks.get((a, s, b))
+            if blk is not None:
+                buf[off:off + blk.size] = np.asarray(blk, dtype=np.float32).reshape(-1)
+        _check(lib().tci_bs_from_host(ctx.h, t.h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+               "tci_bs_from_host")
+        return t
+
+    def dims(self):
+        nl, nr, nbk = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ne = ctypes.c_int64()
+        _check(lib().tci_bs_dims(self.ctx.h, self.h, ctypes.byref(nl), ctypes.byref(nr), ctypes.byref(nbk),
+                                 ctypes.byref(ne)), "tci_bs_dims")
+        return nl.value, nr.value, nbk.value, ne.value
+
+    def nelem(self) -> int:
+        return self.dims()[3]
+
+    def bonds(self):
+        nl, nr, _, _ = self.dims()
+        ql, dl = (ctypes.c_int32 * max(1, nl))(), (ctypes.c_int64 * max(1, nl))()
+        qr, dr = (ctypes.c_int32 * max(1, nr))(), (ctypes.c_int64 * max(1, nr))()
+        _check(lib().tci_bs_bonds(self.ctx.h, self.h, ql, dl, qr, dr), "tci_bs_bonds")
+        return [(ql[i], dl[i]) for i in range(nl)], [(qr[i], dr[i]) for i in range(nr)]
+
+    def layout(self) -> dict:
+        _, _, nbk, _ = self.dims()
+        out = {}
+        a, s, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        off = ctypes.c_int64()
+        for i in range(nbk):
+            _check(lib().tci_bs_block_info(self.ctx.h, self.h, i, ctypes.byref(a), ctypes.byref(s), ctypes.byref(b),
+                                           ctypes.byref(off)), "tci_bs_block_info")
+            out[(a.value, s.value, b.value)] = off.value
+        return out
+
+    def blocks(self) -> dict:
+        left, right = self.bonds()
+        buf = np.empty(self.nelem(), dtype=np.float32)
+        if buf.size:
+            _check(lib().tci_bs_to_host(self.ctx.h, self.h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+                   "tci_bs_to_host")
+        out = {}
+        for (a, s, b), off in self.layout().items():
+            r, c = left[a][1], right[b][1]
+            out[(a, s, b)] = buf[off:off + r * c].reshape(r, c).copy()
+        return out
+
+    def close(self):
+        if self.h:
+            lib().tci_bs_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bs_two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, params: UpdateParams,
+                               chi_max_each: list | None = None):
+    """Returns (A_out, s_out, B_out, infos); A_out / B_out are new BsTensor handles.
+    chi_max_each: optional per-update caps (replacing params.chi_max)."""
+    n = len(A)
+    caps = (ctypes.c_int64 * n)(*chi_max_each) if chi_max_each is not None else None
+    P = ctypes.c_void_p * n
+    A_out = [BsTensor(ctx) for _ in range(n)]
+    B_out = [BsTensor(ctx) for _ in range(n)]
+    s_out = [Tensor.empty(ctx, F64, 2 * sum(d for _, d in A[i].bonds()[0]) + 1) for i in range(n)]
+    infos = (UpdateInfo * n)()
+    g = P(*[x.h.value if x is not None else None for x in gates]) if gates is not None else None
+    _check(lib().tci_bs_two_site_update_batched(ctx.h, n, P(*[x.h.value for x in A]), P(*[x.h.value for x in B]), g,
+                                                ctypes.byref(params), caps, P(*[x.h.value for x in A_out]),
+                                                P(*[x.h.value for x in s_out]), P(*[x.h.value for x in B_out]),
+                                                infos), "tci_bs_two_site_update_batched")
+    return A_out, s_out, B_out, list(infos)

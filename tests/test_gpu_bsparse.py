@@ -1,0 +1,141 @@
+"""GPU parity of the U(1) block-sparse batched two-site update against the
+block oracle (itself pinned to the dense embedding): kept singular values,
+chi, truncation error, the truncated two-site tensor, per-sector isometry and
+charge structure, for single updates, a batch of uneven updates in one call,
+and a batch at the full sector profile (chi up to 1024)."""
+import numpy as np
+import pytest
+
+from oracle import u1 as ou1
+from paper_2512_23917_amd import synth
+
+from gpu_util import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2512_23917_amd import tci
+    return tci
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def make_update(chi_l, chi_m, chi_r, seed):
+    g = synth.rng(4, seed)
+    bl, bm, br = synth.u1_bond(chi_l, 21), synth.u1_bond(chi_m, 22), synth.u1_bond(chi_r, 21)
+    A = {k: v.astype(np.float32) for k, v in synth.u1_site_blocks(g, bl, bm).items()}
+    B = {k: v.astype(np.float32) for k, v in synth.u1_site_blocks(g, bm, br).items()}
+    return bl, bm, br, A, B, synth.u1_gate(g)
+
+
+def run_gpu(T, ctx, ups, target, chi_max, direction, with_gate=True):
+    As = [T.BsTensor.from_blocks(ctx, bl, bm, A) for (bl, bm, br, A, B, gm) in ups]
+    Bs = [T.BsTensor.from_blocks(ctx, bm, br, B) for (bl, bm, br, A, B, gm) in ups]
+    gates = [T.Tensor.from_numpy(ctx, gm, T.F64) for (*_, gm) in ups] if with_gate else None
+    p = T.update_params(chi_min=1, chi_max=chi_max, target_trunc_err=target, direction=direction,
+                        precision=T.PREC_FP32)
+    return T.bs_two_site_update_batched(ctx, As, Bs, gates, p)
+
+
+def check_against_oracle(T, Ao, so, Bo, inf, up, target, chi_max, direction, with_gate=True):
+    bl, bm, br, A, B, gm = up
+    A64 = {k: v.astype(np.float64) for k, v in A.items()}
+    B64 = {k: v.astype(np.float64) for k, v in B.items()}
+    ref = ou1.block_update(A64, B64, bl, bm, br, gm if with_gate else None, 1, chi_max, target, 0.0)
+    chi_ref = ref["chi"]
+    assert abs(inf.chi - chi_ref) <= 2
+    s_gpu = np.sort(so.numpy())[::-1]
+    s_ref = np.sort(ref["s"])[::-1]
+    c = min(len(s_gpu), len(s_ref))
+    assert len(s_gpu) == inf.chi
+    assert np.abs(s_gpu[:c] - s_ref[:c]).max() <= 1e-5 * s_ref[0]
+    assert inf.trunc_err == pytest.approx(ref["trunc_err"], rel=1e-3, abs=1e-7)
+    assert inf.norm2 == pytest.approx(ref["total"], rel=1e-5)
+    # structure of the outputs: new bond = kept sectors in ascending charge
+    left, mid = Ao.bonds()
+    mid2, right = Bo.bonds()
+    assert left == bl and right == br and mid == mid2
+    assert [q for q, _ in mid] == sorted(q for q, _ in mid)
+    assert sum(d for _, d in mid) == inf.chi
+    ab, bb = Ao.blocks(), Bo.blocks()
+    for (a, s, b) in ab:
+        assert mid[b][0] == bl[a][0] + ou1.SPIN_CHARGE[s]
+    # per-sector isometry of the unscaled factor
+    iso_blocks = ab if direction == T.DIR_LEFT else bb
+    for k, (q, dq) in enumerate(mid):
+        if direction == T.DIR_LEFT:
+            g = sum(blk.astype(np.float64).T @ blk.astype(np.float64) for (a, s, b), blk in iso_blocks.items() if b == k)
+        else:
+            g = sum(blk.astype(np.float64) @ blk.astype(np.float64).T for (a, s, b), blk in iso_blocks.items() if a == k)
+        np.testing.assert_allclose(g, np.eye(dq), atol=2e-5)
+    if inf.chi == chi_ref:
+        # truncated two-site tensor, gauge free
+        ad = ou1.dense_site(ab, bl, mid)
+        bd = ou1.dense_site(bb, mid, br)
+        th = np.einsum("asm,mtb->astb", ad, bd)
+        th_ref = ou1.truncated_theta_dense(ref, bl, br)
+        assert rel_fro(th, th_ref) < 1e-5
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("target,chi_max", [(1e-3, 10**9), (0.0, 40), (1e-2, 25)])
+def test_single_update_matches_oracle(T, ctx, direction, target, chi_max):
+    up = make_update(32, 32, 32, 7)
+    Ao, so, Bo, inf = run_gpu(T, ctx, [up], target, chi_max, direction)
+    check_against_oracle(T, Ao[0], so[0], Bo[0], inf[0], up, target, min(chi_max, 64), direction)
+
+
+def test_identity_gate_default(T, ctx):
+    up = make_update(24, 40, 28, 11)
+    Ao, so, Bo, inf = run_gpu(T, ctx, [up], 1e-4, 10**9, 0, with_gate=False)
+    check_against_oracle(T, Ao[0], so[0], Bo[0], inf[0], up, 1e-4, 48, 0, with_gate=False)
+
+
+def test_uneven_batch_in_one_call(T, ctx):
+    chis = [32, 64, 96, 128, 48, 80]
+    ups = [make_update(c, c, c, 100 + i) for i, c in enumerate(chis)]
+    Ao, so, Bo, inf = run_gpu(T, ctx, ups, 1e-6, 10**9, 0)
+    for i, up in enumerate(ups):
+        check_against_oracle(T, Ao[i], so[i], Bo[i], inf[i], up, 1e-6, 2 * chis[i], 0)
+
+
+@pytest.mark.slow
+def test_full_profile_batch_sampled(T, ctx):
+    """A batch with chi in {128, 256, 512, 1024} at the 21 / 22 sector profile;
+    the chi = 1024 and chi = 128 updates are checked against the oracle."""
+    chis = [128, 256, 512, 1024, 256, 128, 512, 1024]
+    ups = [make_update(c, c, c, 200 + i) for i, c in enumerate(chis)]
+    Ao, so, Bo, inf = run_gpu(T, ctx, ups, 1e-8, 1024, 0)
+    for i in (0, 3):
+        check_against_oracle(T, Ao[i], so[i], Bo[i], inf[i], ups[i], 1e-8, 1024, 0)
+    for i in range(len(ups)):
+        assert inf[i].chi <= 1024 and np.isfinite(inf[i].trunc_err)
+
+
+def test_recorded_graph_replays_match_oracle(T, ctx):
+    """The same structure four times with different data: the first call runs
+    the kernels directly, the second records the first half of the update as
+    a HIP graph, the later ones replay it.  Every call is checked against the
+    oracle, with unrelated eager GPU work and synchronisations in between."""
+    bl = synth.u1_bond(40, 21)
+    bm = synth.u1_bond(40, 22)
+    br = synth.u1_bond(40, 21)
+    for rep in range(4):
+        g = synth.rng(4, 500 + rep)
+        A = {k: v.astype(np.float32) for k, v in synth.u1_site_blocks(g, bl, bm).items()}
+        B = {k: v.astype(np.float32) for k, v in synth.u1_site_blocks(g, bm, br).items()}
+        up = (bl, bm, br, A, B, synth.u1_gate(g))
+        Ao, so, Bo, inf = run_gpu(T, ctx, [up, up], 1e-5, 10**9, 0)
+        for i in range(2):
+            check_against_oracle(T, Ao[i], so[i], Bo[i], inf[i], up, 1e-5, 80, 0)
+        x = torch.randn(1 << 20, device="cuda")
+        assert torch.isfinite((x * 2).sum())
+        torch.cuda.synchronize()
