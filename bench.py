@@ -150,6 +150,47 @@ def traffic_per_launch(kernel, src):
         return None
 
 
+def bench_blocksparse(tci, ctx, n_upd=64, steps=3, eps=1e-8):
+    """U(1) block-sparse batch: n_upd independent updates with chi drawn from
+    {128, 256, 512, 1024} (21 outer / 22 middle sectors, binomial profile),
+    Gaussian float32 blocks, charge-conserving gates, cap = the update's chi,
+    all in one call.  The first call runs directly (and tunes the grouped GEMM
+    tile), the second records the HIP graph; the timed calls replay it."""
+    import torch
+    from paper_2512_23917_amd import synth
+    g = synth.rng(4, 9999)
+    chis = [int(c) for c in g.choice([128, 256, 512, 1024], size=n_upd)]
+    A, B, G = [], [], []
+    for u, c in enumerate(chis):
+        gu = synth.rng(4, 10000 + u)
+        bl, bm, br = synth.u1_bond(c, 21), synth.u1_bond(c, 22), synth.u1_bond(c, 21)
+        A.append(tci.BsTensor.from_blocks(ctx, bl, bm, {k: v.astype(np.float32)
+                                                        for k, v in synth.u1_site_blocks(gu, bl, bm).items()}))
+        B.append(tci.BsTensor.from_blocks(ctx, bm, br, {k: v.astype(np.float32)
+                                                        for k, v in synth.u1_site_blocks(gu, bm, br).items()}))
+        G.append(tci.Tensor.from_numpy(ctx, synth.u1_gate(gu), tci.F64))
+    p = tci.update_params(chi_min=1, chi_max=1024, target_trunc_err=eps, direction=tci.DIR_LEFT,
+                          precision=tci.PREC_FP32)
+    times = []
+    out = None
+    for i in range(2 + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = tci.bs_two_site_update_batched(ctx, A, B, G, p, chi_max_each=chis)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"  block-sparse call {i + 1}/{2 + steps}: {times[-1] * 1e3:.1f} ms")
+    t = sum(times[2:]) / steps
+    infos = out[3]
+    return {"workload": f"U(1) block-sparse batch: {n_upd} updates, chi in {{128,256,512,1024}}, "
+                        f"21/22 sectors, f32, eps={eps}, cap=chi, one call",
+            "updates_per_s": round(n_upd / t, 3), "ms_per_call": round(1e3 * t, 2),
+            "first_call_ms": round(1e3 * times[0], 2), "recording_call_ms": round(1e3 * times[1], 2),
+            "chi_mix": {str(c): chis.count(c) for c in (128, 256, 512, 1024)},
+            "kept_chi": [min(i.chi for i in infos), max(i.chi for i in infos)],
+            "trunc_err_max": float(max(i.trunc_err for i in infos))}
+
+
 def host_threads():
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     omp = os.environ.get("OMP_NUM_THREADS")
@@ -159,12 +200,12 @@ def host_threads():
 def cpu_baseline(chi, n_matvec, budget_s=20.0):
     """Time the CPU oracle on slices of one update and scale to updates/s.
 
-    Sample: (i) theta = A.B for 16 of the 2048 rows of A (scale 128);
-    (ii) one effective-Hamiltonian matvec restricted to 8 of the 1024 values
-    of the left index a (the L-step and everything after it factor over a;
-    scale 128), times n_matvec; (iii) the oracle's one-sided Jacobi SVD of a
-    complex 384 x 384 Gaussian matrix, scaled by (2048/384)^3 for the
-    2048 x 2048 truncated SVD.  Lanczos vector operations are linear in the
+    Sample: (i) theta = A.B for 96 of the 1024 values of the left index of A
+    (scale chi/96); (ii) one effective-Hamiltonian matvec restricted to 96 of
+    the 1024 values of the left index a (the L-step and everything after it
+    factor over a; scale chi/96), times n_matvec; (iii) the oracle's one-sided
+    Jacobi SVD of a complex 800 x 800 Gaussian matrix, scaled by (2048/800)^3
+    for the 2048 x 2048 truncated SVD.  Lanczos vector operations are linear in the
     vector length and are included in the matvec slice's scaling.
     """
     import oracle
@@ -178,21 +219,21 @@ def cpu_baseline(chi, n_matvec, budget_s=20.0):
     w = synth.heisenberg_mpo()
     x = synth.complex_gaussian(g, (chi, 2, 2, chi))
     oracle.build()
-    rows = 8
+    rows = 96
     t0 = time.perf_counter()
-    oracle.contract(a[: rows * 2 // 2], "asm", b, "mtb", "astb")
-    t_theta = (time.perf_counter() - t0) * (chi / (rows * 2 // 2))
+    oracle.contract(a[:rows], "asm", b, "mtb", "astb")
+    t_theta = (time.perf_counter() - t0) * (chi / rows)
     t0 = time.perf_counter()
     odmrg.heff_apply(np.ascontiguousarray(left[:rows]), w, w, right, x)
     t_mv = (time.perf_counter() - t0) * (chi / rows)
-    n = 384
+    n = 800
     m = synth.complex_gaussian(g, (n, n))
     t0 = time.perf_counter()
     oracle.svd_matrix(m)
     t_svd = (time.perf_counter() - t0) * (2 * chi / n) ** 3
     per_update = t_theta + n_matvec * t_mv + t_svd
     return dict(value=1.0 / per_update, unit="updates/s", cores=host_threads(), kind="oracle",
-                sample=(f"oracle slices of one chi={chi} update: theta rows 1/{chi // (rows * 2 // 2)}, "
+                sample=(f"oracle slices of one chi={chi} update: theta rows {rows}/{chi}, "
                         f"H_eff matvec on {rows}/{chi} left rows x{n_matvec}, Jacobi SVD {n}x{n} scaled "
                         f"(2048/{n})^3; per-update estimate {per_update:.1f}s "
                         f"(theta {t_theta:.1f}s, matvecs {n_matvec * t_mv:.1f}s, svd {t_svd:.1f}s)"))
@@ -215,6 +256,7 @@ def main():
     ap.add_argument("--plain-warmup", type=int, default=1)
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-blocksparse", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -294,6 +336,11 @@ def main():
         if roof:
             roof["time_share_top"] = share
 
+    bs = None
+    if not args.skip_blocksparse:
+        log("U(1) block-sparse batch")
+        bs = bench_blocksparse(tci, ctx)
+
     cpu = None
     if not args.skip_cpu:
         log("cpu baseline (oracle sample)")
@@ -329,6 +376,7 @@ def main():
             float(max(abs(a - b) / abs(b) for a, b in zip(en_m, en_p))),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "blocksparse": bs,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -16,6 +16,8 @@
 // that one barrier per k tile suffices.  Each 64-byte LDS row holds four
 // 16-byte k chunks, chunk c of row r at position c ^ ((r >> 2) & 3): the 16
 // rows that one MFMA operand load touches then fall into distinct banks.
+#include <type_traits>
+
 #include "common.hpp"
 #include "gemm.hpp"
 #include "bf16x3.hpp"
@@ -109,13 +111,18 @@ hipError_t split_planes(int dtype, const void* src, long long ld, long long ssrc
 }
 
 // ---------------------------------------------------------------------------
-// GEMM on planes.  Workgroup tile 128 x 128, waves 2 x 2 (64 x 64 each =
-// 4 x 4 MFMA blocks).  Staging: each plane tile is 128 rows x 32 k = 8 KB =
-// 512 chunks of 16 bytes; thread t moves chunks t and t + 256 of each plane.
+// GEMM on planes.  Workgroup tile 128 x 128 with 8 waves in a 2 x 4 grid,
+// each wave 64 x 32 (4 x 2 MFMA blocks), so that a wave needs at most 256
+// registers and two waves share each SIMD: one wave's LDS and global-load
+// waits are covered by the other's matrix work.  Staging: each plane tile is
+// 128 rows x 32 k = 8 KB = 512 chunks of 16 bytes; thread t moves chunk t of
+// every plane of both operands.
 // ---------------------------------------------------------------------------
+constexpr int XWM = 64, XWN = 32;   // wave tile
 template <bool CPLX>
-__global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
+__global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
   constexpr int NP = CPLX ? 4 : 2;
+  constexpr int IM = XWM / 16, JN = XWN / 16;
   __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][XBM][XBK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][XBN][XBK];
   // tile coordinates, XCD-aware as in the plain GEMM
@@ -123,51 +130,52 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
   const long total = (long)gx * gy * gz;
   long lin = blockIdx.x + (long)gx * (blockIdx.y + (long)gy * blockIdx.z);
   if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
-  const int tn = (int)(lin % gx);
-  lin /= gx;
-  const int tm = (int)(lin % gy);
-  const int b = (int)(lin / gy);
+  // grouped order inside a problem: runs of 8 row tiles share each column
+  // tile, so that the tiles an XCD runs at once re-use both operand panels
+  const long per_b = (long)gx * gy;
+  const int b = (int)(lin / per_b);
+  const int tt = (int)(lin % per_b);
+  constexpr int GM = 8;
+  const int gsize = GM * gx;
+  const int first = (tt / gsize) * GM;
+  const int gm = min(GM, gy - first);
+  const int rr = tt % gsize;
+  const int tm = first + rr % gm, tn = rr / gm;
   const int m0 = tm * XBM, n0 = tn * XBN;
   const __bf16* A = a.Ap + b * a.sAp;
   const __bf16* B = a.Bp + b * a.sBp;
   const long long pa = (long long)a.Mp * a.Kp, pb = (long long)a.Np * a.Kp;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int wm = wid >> 1, wn = wid & 1;
+  const int wm = wid >> 2, wn = wid & 3;
   const int lr = lane & 15, lk = lane >> 4;
   const int rd = 8 * (lk ^ ((lr >> 2) & 3));   // swizzled k offset of this lane's operand chunk
 
-  f4v acc_re[4][4], acc_im[4][4];
+  f4v acc_re[IM][JN], acc_im[IM][JN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JN; ++j) {
       acc_re[i][j] = f4v{0, 0, 0, 0};
       acc_im[i][j] = f4v{0, 0, 0, 0};
     }
 
-  // chunk c in [0, 512): row c >> 2, k chunk c & 3
-  u4v ra[NP][2], rb[NP][2];
+  // chunk t: row t >> 2, k chunk t & 3
+  const int srow = t >> 2, skc = t & 3;
+  const int sko = 8 * (skc ^ ((srow >> 2) & 3));
+  u4v ra[NP], rb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = t + 256 * h;
-        const int row = c >> 2, ko = (c & 3) * 8;
-        ra[p][h] = *reinterpret_cast<const u4v*>(A + p * pa + (long long)(m0 + row) * a.Kp + k0 + ko);
-        rb[p][h] = *reinterpret_cast<const u4v*>(B + p * pb + (long long)(n0 + row) * a.Kp + k0 + ko);
-      }
+    for (int p = 0; p < NP; ++p) {
+      ra[p] = *reinterpret_cast<const u4v*>(A + p * pa + (long long)(m0 + srow) * a.Kp + k0 + skc * 8);
+      rb[p] = *reinterpret_cast<const u4v*>(B + p * pb + (long long)(n0 + srow) * a.Kp + k0 + skc * 8);
+    }
   };
   auto stash = [&](int st) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = t + 256 * h;
-        const int row = c >> 2, ko = 8 * ((c & 3) ^ ((row >> 2) & 3));
-        *reinterpret_cast<u4v*>(&As[st][p][row][ko]) = ra[p][h];
-        *reinterpret_cast<u4v*>(&Bs[st][p][row][ko]) = rb[p][h];
-      }
+    for (int p = 0; p < NP; ++p) {
+      *reinterpret_cast<u4v*>(&As[st][p][srow][sko]) = ra[p];
+      *reinterpret_cast<u4v*>(&Bs[st][p][srow][sko]) = rb[p];
+    }
   };
 
   const int nk = a.Kp / XBK;
@@ -178,23 +186,29 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) fetch((kt + 1) * XBK);
-    bf8v fa[NP][4], fb[NP][4];
+    bf8v fa[NP][IM], fb[NP][JN];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[p][i] = *reinterpret_cast<const bf8v*>(&As[cur][p][wm * 64 + i * 16 + lr][rd]);
+      for (int i = 0; i < IM; ++i)
+        fa[p][i] = *reinterpret_cast<const bf8v*>(&As[cur][p][wm * XWM + i * 16 + lr][rd]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[cur][p][wn * 64 + j * 16 + lr][rd]);
+      for (int j = 0; j < JN; ++j)
+        fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[cur][p][wn * XWN + j * 16 + lr][rd]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < IM; ++i) {
+      bf8v nh, nl;
+      if constexpr (CPLX) {
+        nh = -fa[2][i];
+        nl = -fa[3][i];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < JN; ++j) {
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], acc_re[i][j], 0, 0, 0);
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], acc_re[i][j], 0, 0, 0);
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], acc_re[i][j], 0, 0, 0);
         if constexpr (CPLX) {
-          const bf8v nh = -fa[2][i], nl = -fa[3][i];
           acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[2][j], acc_re[i][j], 0, 0, 0);
           acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[3][j], acc_re[i][j], 0, 0, 0);
           acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nl, fb[2][j], acc_re[i][j], 0, 0, 0);
@@ -206,6 +220,7 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[3][i], fb[0][j], acc_im[i][j], 0, 0, 0);
         }
       }
+    }
     if (more) stash(cur ^ 1);
     __syncthreads();
   }
@@ -214,13 +229,13 @@ __global__ __launch_bounds__(256) void gemm_planes_kernel(PlaneGemmArgs a) {
   const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
   const float ar = (float)a.alpha_re, ai = (float)a.alpha_im, br = (float)a.beta_re, bi = (float)a.beta_im;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * lk + r;
-        const int col = n0 + wn * 64 + j * 16 + lr;
+        const int row = m0 + wm * XWM + i * 16 + 4 * lk + r;
+        const int col = n0 + wn * XWN + j * 16 + lr;
         if (row < a.m && col < a.n) {
           const float vr = acc_re[i][j][r], vi = CPLX ? acc_im[i][j][r] : 0.f;
           float orr = ar * vr - ai * vi, oi = ar * vi + ai * vr;
@@ -248,8 +263,8 @@ hipError_t gemm_planes(int dtype, const PlaneGemmArgs& a, hipStream_t s) {
   const bool cplx = dtype == C64;
   const double flops = (cplx ? 8.0 : 2.0) * 3.0 * a.m * (double)a.n * a.k * a.batch;
   ProfScope ps(s, flops, cplx ? "c64_bf16x3_planes" : "f32_bf16x3_planes");
-  if (cplx) hipLaunchKernelGGL(gemm_planes_kernel<true>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(gemm_planes_kernel<false>, grid, dim3(256), 0, s, a);
+  if (cplx) hipLaunchKernelGGL(gemm_planes_kernel<true>, grid, dim3(512), 0, s, a);
+  else hipLaunchKernelGGL(gemm_planes_kernel<false>, grid, dim3(512), 0, s, a);
   return hipGetLastError();
 }
 
@@ -277,6 +292,80 @@ hipError_t split_b(int dtype, int opB, const void* B, long long ldb, long long s
 
 size_t planes_bytes(int dtype, int rows, int k) {
   return sizeof(__bf16) * (size_t)planes_of(dtype) * pad_rows(rows) * pad_k(k);
+}
+
+}  // namespace tci
+
+namespace tci {
+
+// The middle step of the effective-Hamiltonian matvec fused with the split of
+// its result:  X2[a][j][b] = sum_k W12[k][j] X1[a][k][b]  (k, j < KW), in FP32,
+// written straight into the bf16 planes of the R-step operand, whose row is
+// (a, j / w) and whose k index is (j % w) * chir + b.  One thread per (a, b);
+// W12 sits in LDS.  The padding of the planes is never written (zeroed once).
+template <bool CPLX, int KW>
+__global__ __launch_bounds__(256) void w12_planes_kernel(const void* X1v, const void* W12v, int chil, int chir,
+                                                         int w, __bf16* planes, int Mp, int Kp) {
+  typedef typename std::conditional<CPLX, cf, float>::type T;
+  __shared__ float Wr[KW * KW], Wi[KW * KW];
+  const T* W12 = static_cast<const T*>(W12v);
+  for (int e = threadIdx.x; e < KW * KW; e += 256) {
+    float r, i;
+    getf(W12 + e, r, i);
+    Wr[e] = r;
+    Wi[e] = i;
+  }
+  __syncthreads();
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= (long long)chil * chir) return;
+  const int a = (int)(idx / chir), b = (int)(idx % chir);
+  const T* x1 = static_cast<const T*>(X1v) + (long long)a * KW * chir + b;
+  float xr[KW], xi[KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k) getf(x1 + (long long)k * chir, xr[k], xi[k]);
+  const long long plane = (long long)Mp * Kp;
+  const int dd = KW / w;
+#pragma unroll 4
+  for (int j = 0; j < KW; ++j) {
+    float yr = 0.f, yi = 0.f;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const float wr = Wr[k * KW + j], wi = Wi[k * KW + j];
+      yr += wr * xr[k];
+      if constexpr (CPLX) {
+        yr -= wi * xi[k];
+        yi += wr * xi[k] + wi * xr[k];
+      }
+    }
+    const long long o = (long long)(a * dd + j / w) * Kp + (long long)(j % w) * chir + b;
+    __bf16 h, l;
+    split1(yr, h, l);
+    planes[o] = h;
+    planes[plane + o] = l;
+    if constexpr (CPLX) {
+      split1(yi, h, l);
+      planes[2 * plane + o] = h;
+      planes[3 * plane + o] = l;
+    }
+  }
+}
+
+hipError_t w12_to_planes(int dtype, const void* X1, const void* W12, int chil, int kw, int chir, int w, void* planes,
+                         int Mp, int Kp, hipStream_t s) {
+  if (kw != 20) return hipErrorInvalidValue;
+  const long long tot = (long long)chil * chir;
+  const unsigned grid = (unsigned)((tot + 255) / 256);
+  const double flops = (dtype == C64 ? 8.0 : 2.0) * (double)kw * kw * tot;
+  ProfScope ps(s, flops, dtype == C64 ? "c64_fp32_w12" : "f32_fp32_w12");
+  if (dtype == C64)
+    hipLaunchKernelGGL((w12_planes_kernel<true, 20>), dim3(grid), dim3(256), 0, s, X1, W12, chil, chir, w,
+                       (__bf16*)planes, Mp, Kp);
+  else if (dtype == F32)
+    hipLaunchKernelGGL((w12_planes_kernel<false, 20>), dim3(grid), dim3(256), 0, s, X1, W12, chil, chir, w,
+                       (__bf16*)planes, Mp, Kp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace tci

@@ -24,5 +24,10 @@ hipError_t split_a(int dtype, int opA, const void* A, long long lda, long long s
 hipError_t split_b(int dtype, int opB, const void* B, long long ldb, long long sB, int K, int N, void* dst, int batch,
                    hipStream_t s);
 hipError_t gemm_planes(int dtype, const PlaneGemmArgs& a, hipStream_t s);
+// X2[a][j][b] = sum_k W12[k][j] X1[a][k][b] (FP32) written into the planes of
+// the row-major matrix X2' ((a, j / w) x ((j % w) chir + b)), Mp x Kp padded;
+// kw = w d^2 must be 20 (w = 5, d = 2), else hipErrorInvalidValue.
+hipError_t w12_to_planes(int dtype, const void* X1, const void* W12, int chil, int kw, int chir, int w, void* planes,
+                         int Mp, int Kp, hipStream_t s);
 
 }  // namespace tci

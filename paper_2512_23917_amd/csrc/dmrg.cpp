@@ -84,6 +84,8 @@ static tci_status heff_prepare(tci_context ctx, tci_tensor L, tci_tensor W1, tci
     // L' = L[(a,w),a'] as op(A) of the first product; R'^T as op(B) of the last
     TCI_CHECK_HIP(split_a(p.dt, OP_N, L->data, chil, 0, chil * wd, chil, p.Lp, 1, ctx->stream));
     TCI_CHECK_HIP(split_b(p.dt, OP_T, R->data, (long long)wd * chir, 0, wd * chir, chir, p.Rp, 1, ctx->stream));
+    // the fused middle step writes only the valid part of the X2' planes
+    TCI_CHECK_HIP(zero_fill(p.X2p, planes_bytes(p.dt, chil * dd, wd * chir), ctx->stream));
   }
   return TCI_OK;
 }
@@ -115,6 +117,14 @@ static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, 
   }
   // X2[a] = W12^T X1[a]
   ProfTag t2("heff_W12");
+  if (p.planes && kw == 20) {
+    // fused with the split of X2' for the R-step
+    TCI_CHECK_HIP(w12_to_planes(p.dt, p.X1, p.W12, p.chil, kw, p.chir, p.w, p.X2p, pad_rows(p.chil * dd),
+                                pad_k(p.w * p.chir), s));
+    ProfTag t3("heff_R");
+    TCI_CHECK_HIP(gemm_planes(p.dt, plane_args(p.chil * dd, p.chir, p.w * p.chir, p.X2p, p.Rp, y, p.chir), s));
+    return TCI_OK;
+  }
   GemmArgs g2 = gemm_args(kw, p.chir, kw, OP_T, OP_N, p.W12, kw, p.X1, p.chir, p.X2, p.chir);
   g2.sA = 0; g2.sB = (long long)kw * p.chir; g2.sC = (long long)kw * p.chir; g2.batch = p.chil;
   TCI_CHECK_HIP(gemm(p.dt, p.prec, g2, s));
@@ -176,7 +186,7 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   void* xin = ctx->arena.get(es * (size_t)N);
   void* yout = ctx->arena.get(es * (size_t)N);
   double* part = static_cast<double*>(ctx->arena.get(sizeof(double) * MULTIDOT_PARTIAL_DOUBLES));
-  double* coef = static_cast<double*>(ctx->arena.get(sizeof(double) * 2 * 64));
+  double* coef = static_cast<double*>(ctx->arena.get(sizeof(double) * 3 * 128));
   double* nrm = static_cast<double*>(ctx->arena.get(sizeof(double) * (SUMSQ_PARTIALS + 1)));
   if (!basis || !w || !th || !xin || !yout || !part || !coef || !nrm) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(convert(dt, theta->data, C128, th, N, s));
@@ -210,22 +220,19 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     TCI_CHECK_HIP(hipStreamSynchronize(s));
     const double a = hc[0];
     alpha.push_back(a);
-    // w -= alpha v_j + beta_{j-1} v_{j-1}
-    double c3[4] = {a, 0.0, j > 0 ? beta[j - 1] : 0.0, 0.0};
-    if (j > 0) {
-      double cc[4] = {c3[2], 0.0, a, 0.0};  // basis rows j-1, j
-      TCI_CHECK_HIP(hipMemcpyAsync(coef, cc, sizeof(cc), hipMemcpyHostToDevice, s));
-      TCI_CHECK_HIP(multiaxpy(basis + (size_t)N * (j - 1), 2, coef, -1.0, w, N, s));
-    } else {
-      TCI_CHECK_HIP(hipMemcpyAsync(coef, c3, sizeof(double) * 2, hipMemcpyHostToDevice, s));
-      TCI_CHECK_HIP(multiaxpy(vj, 1, coef, -1.0, w, N, s));
+    // w -= alpha v_j + beta_{j-1} v_{j-1}, then two passes of classical
+    // Gram-Schmidt against v_0..v_j.  Each subtraction sweep also forms the
+    // dot products of its result that the next pass needs, so the basis is
+    // streamed three times per step; the last sweep returns ||w||^2.
+    std::vector<double> c3(2 * (j + 1), 0.0);   // host staging, alive until the sync below
+    {
+      c3[2 * j] = a;
+      if (j > 0) c3[2 * (j - 1)] = beta[j - 1];
+      TCI_CHECK_HIP(hipMemcpyAsync(coef, c3.data(), sizeof(double) * c3.size(), hipMemcpyHostToDevice, s));
+      TCI_CHECK_HIP(axpy_multidot(basis, j + 1, coef, -1.0, w, N, part, coef + 128, s));
+      TCI_CHECK_HIP(axpy_multidot(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 256, s));
+      TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
     }
-    // two passes of classical Gram-Schmidt against v_0..v_j
-    // (the second pass also returns ||w||^2)
-    TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
-    TCI_CHECK_HIP(multiaxpy(basis, j + 1, coef, -1.0, w, N, s));
-    TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef, s));
-    TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
     double b2 = 0.0;
     TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
     TCI_CHECK_HIP(hipStreamSynchronize(s));

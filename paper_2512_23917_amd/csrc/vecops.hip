@@ -297,6 +297,72 @@ hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* 
   return multiaxpy_launch(V, nv, c, sign, w, n, nullptr, s);
 }
 
+// Fused sweep: w += sign * sum_q c_q v_q, then d_q = <v_q, w> of the updated w
+// (block partials in the multidot layout).  The loads of v_q serve both.
+template <int NV>
+__global__ __launch_bounds__(256) void axpy_dot_kernel(const cd* V, int nv, const double* c, double sign, cd* w,
+                                                       long long n, double* partial) {
+  __shared__ double scr[NV], sci[NV];
+  __shared__ double sh[4][2 * NV];
+  if (threadIdx.x < NV) {
+    scr[threadIdx.x] = threadIdx.x < nv ? sign * c[2 * threadIdx.x] : 0.0;
+    sci[threadIdx.x] = threadIdx.x < nv ? sign * c[2 * threadIdx.x + 1] : 0.0;
+  }
+  __syncthreads();
+  double accr[NV], acci[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    cd v[NV];
+    cd y = w[i];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        v[q] = V[(long long)q * n + i];
+        y.x += scr[q] * v[q].x - sci[q] * v[q].y;
+        y.y += scr[q] * v[q].y + sci[q] * v[q].x;
+      }
+    }
+    w[i] = y;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        accr[q] += v[q].x * y.x + v[q].y * y.y;
+        acci[q] += v[q].x * y.y - v[q].y * y.x;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if (q < nv) {
+      const double r = wave_sum64(accr[q]), im = wave_sum64(acci[q]);
+      if (lane == 0) { sh[wv][2 * q] = r; sh[wv][2 * q + 1] = im; }
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * nv) {
+    const double vv = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    partial[((long long)blockIdx.x * MD_MAXV + t / 2) * 2 + (t & 1)] = vv;
+  }
+}
+
+hipError_t axpy_multidot(const void* V, int nv, const double* c, double sign, void* w, long long n,
+                         double* partial, double* out, hipStream_t s) {
+  if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
+  const unsigned g = md_grid(n);
+  const cd* Vc = (const cd*)V;
+  cd* wc = (cd*)w;
+  if (nv <= 2) hipLaunchKernelGGL(axpy_dot_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  else if (nv <= 8) hipLaunchKernelGGL(axpy_dot_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  else if (nv <= 16) hipLaunchKernelGGL(axpy_dot_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  else if (nv <= 24) hipLaunchKernelGGL(axpy_dot_kernel<24>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  else hipLaunchKernelGGL(axpy_dot_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
+  return hipGetLastError();
+}
+
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
                            double* partial, double* out, hipStream_t s) {
   if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
@@ -423,6 +489,27 @@ hipError_t reverse_columns(int dt, void* U, long long ld, int rows, int k, hipSt
   if (dt == C128) hipLaunchKernelGGL(reverse_cols_kernel<cd>, dim3(g), dim3(256), 0, s, (cd*)U, ld, rows, k);
   else if (dt == F64) hipLaunchKernelGGL(reverse_cols_kernel<double>, dim3(g), dim3(256), 0, s, (double*)U, ld, rows, k);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace tci
+
+namespace tci {
+
+// Kernel fill of zeros: safe inside captured HIP graphs (no memset nodes).
+__global__ void zero_fill_kernel(unsigned int* p, long long nwords, unsigned char* tail, int ntail) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < nwords; i += (long long)gridDim.x * 256) p[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (reinterpret_cast<uintptr_t>(p) % 4 != 0) return hipErrorInvalidValue;
+  const long long nwords = (long long)(bytes / 4);
+  const int ntail = (int)(bytes % 4);
+  const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(2048, (nwords + 255) / 256));
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(g), dim3(256), 0, s, static_cast<unsigned int*>(p), nwords,
+                     static_cast<unsigned char*>(p) + nwords * 4, ntail);
   return hipGetLastError();
 }
 

@@ -161,3 +161,41 @@ def test_c5_randomized_power_law_full_size(T, ctx):
         sn = so[0].numpy()
         s_ref = s[:chi_ref] / np.linalg.norm(s[:chi_ref])
         assert np.abs(sn[:c] - s_ref[:c]).max() <= 1e-6 * s_ref[0]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dt", ["C128", "C64"])
+def test_split_batch_of_64_matches_single_problems(T, ctx, dt):
+    """The benchmark's launch configuration: one split of 64 full-size
+    (1024, 2, 2, 1024) two-site tensors.  Sampled problems of the batch must
+    equal the same problem split alone (the batch shares launches, not
+    arithmetic), and every problem's factors are isometric with
+    discarded weight = ||theta - U S V^H||^2."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(251223917 + 2000)
+    tdt = torch.complex128 if dt == "C128" else torch.complex64
+    thetas_t = [torch.randn((1024, 2, 2, 1024), dtype=tdt, device="cuda", generator=g) for _ in range(64)]
+    thetas = [T.Tensor.from_torch(ctx, x) for x in thetas_t]
+    p = T.update_params(chi_min=1, chi_max=1024, target_trunc_err=1e-8, direction=0,
+                        precision=T.PREC_FP64 if dt == "C128" else T.PREC_BF16X3)
+    Ao, so, Bo, inf = T.split_batched(ctx, thetas, p)
+    assert all(i.chi == 1024 for i in inf)
+    for k in (0, 29, 63):
+        A1, s1, B1, i1 = T.split_batched(ctx, [thetas[k]], p)
+        assert i1[0].chi == inf[k].chi
+        assert i1[0].trunc_err == pytest.approx(inf[k].trunc_err, rel=1e-12)
+        np.testing.assert_allclose(s1[0].numpy(), so[k].numpy(), rtol=0, atol=1e-13)
+        ra = Ao[k].numpy().reshape(2048, -1) @ Bo[k].numpy().reshape(-1, 2048)
+        rb = A1[0].numpy().reshape(2048, -1) @ B1[0].numpy().reshape(-1, 2048)
+        assert rel_fro(ra, rb) < (1e-12 if dt == "C128" else 1e-6)
+        U = Ao[k].numpy().reshape(2048, -1).astype(np.complex128)
+        tol = 1e-11 if dt == "C128" else 1e-5
+        assert np.abs(U.conj().T @ U - np.eye(U.shape[1])).max() < tol
+        th = thetas_t[k].cpu().numpy().reshape(2048, 2048).astype(np.complex128)
+        Vh = Bo[k].numpy().reshape(-1, 2048).astype(np.complex128)
+        sn = so[k].numpy()
+        kept = inf[k].norm2 - inf[k].discarded_abs
+        rec = U @ (Vh * math.sqrt(kept))
+        resid2 = np.linalg.norm(th - rec) ** 2
+        assert resid2 == pytest.approx(inf[k].discarded_abs, rel=1e-6 if dt == "C128" else 1e-4)
+        assert np.sum(sn ** 2) == pytest.approx(1.0, rel=1e-12)
