@@ -105,3 +105,25 @@ def lanczos_ground(matvec, theta, n_matvec=20, breakdown=1e-13):
     if abs(ov) > 0:
         psi = psi * (np.conj(ov) / abs(ov))
     return float(evals[0]), psi, np.array(alphas), np.array(betas[: m - 1])
+
+
+def heisenberg_chain_dense(n_sites: int) -> np.ndarray:
+    """Dense Hamiltonian of the open spin-1/2 Heisenberg chain,
+    H = sum_i S_i . S_{i+1} (J = 1), basis index 0 = up, site 0 the most
+    significant factor of the Kronecker products."""
+    sp = np.array([[0.0, 1.0], [0.0, 0.0]])
+    sm = sp.T
+    sz = np.diag([0.5, -0.5])
+    dim = 2 ** n_sites
+    h = np.zeros((dim, dim))
+    for i in range(n_sites - 1):
+        left = np.eye(2 ** i)
+        right = np.eye(2 ** (n_sites - i - 2))
+        bond = 0.5 * (np.kron(sp, sm) + np.kron(sm, sp)) + np.kron(sz, sz)
+        h += np.kron(np.kron(left, bond), right)
+    return h
+
+
+def heisenberg_ground_energy(n_sites: int) -> float:
+    """Exact ground-state energy of the open chain by dense diagonalisation."""
+    return float(np.linalg.eigvalsh(heisenberg_chain_dense(n_sites))[0])

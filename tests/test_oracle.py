@@ -429,3 +429,23 @@ def test_philox_published_known_answers():
 def test_philox_normal_moments():
     z = oracle.philox_normal(1234, 0, 200000)
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
+
+
+def test_heisenberg_chain_exact_energy_and_mpo():
+    """Dense open-chain Hamiltonian: E0(2) = -3/4 and E0(4) = -3/4 - sqrt(3)/2
+    (closed forms); the bond-dimension-5 MPO with the one-dimensional end
+    environments (channel 4 on the left, channel 0 on the right) contracts to
+    the same dense operator."""
+    import math
+    from oracle import dmrg as od
+    assert od.heisenberg_ground_energy(2) == pytest.approx(-0.75, abs=1e-14)
+    assert od.heisenberg_ground_energy(4) == pytest.approx(-0.75 - math.sqrt(3) / 2, abs=1e-13)
+    w = synth.heisenberg_mpo()
+    n = 4
+    vec = np.zeros(5)
+    vec[4] = 1.0
+    op = np.einsum("w,wvst->vst", vec, w)                   # (5, 2, 2) after site 0
+    for _ in range(n - 1):
+        op = np.einsum("vST,vust->uSsTt", op, w).reshape(5, op.shape[1] * 2, op.shape[2] * 2)
+    dense = op[0]
+    np.testing.assert_allclose(dense, od.heisenberg_chain_dense(n), atol=1e-14)
