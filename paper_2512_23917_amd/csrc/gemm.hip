@@ -37,18 +37,10 @@ __device__ inline void tile_coords(int& tm, int& tn, int& b) {
     const long per = total >> 3;
     lin = (lin & 7) * per + (lin >> 3);
   }
-  // grouped order inside a problem: runs of 8 row tiles share each column
-  // tile, so that the tiles an XCD runs at once re-use A and B panels in L2
-  const long per_b = (long)gx * gy;
-  b = (int)(lin / per_b);
-  const int t = (int)(lin % per_b);
-  constexpr int GM = 8;
-  const int gsize = GM * gx;
-  const int first = (t / gsize) * GM;
-  const int gm = min(GM, gy - first);
-  const int r = t % gsize;
-  tm = first + r % gm;
-  tn = r / gm;
+  tn = (int)(lin % gx);
+  lin /= gx;
+  tm = (int)(lin % gy);
+  b = (int)(lin / gy);
 }
 
 template <typename T> struct Elem;
@@ -145,113 +137,6 @@ __device__ inline void stage_cols_tile(const T* __restrict__ B, long ldb, int op
   }
 }
 
-// The same staging in two halves, so that the next tile's global loads are in
-// flight while the current tile feeds the matrix cores: fetch_* reads the
-// thread's PER elements into registers, put_* writes them to LDS.
-template <typename T, typename R, int ROWS, int BK>
-struct RowsStage {
-  static constexpr int PER = ROWS * BK / 256;
-  R vr[PER], vi[PER];
-  __device__ inline void fetch(const T* __restrict__ A, long lda, int op, int M, int K, int m0, int k0) {
-    const int t = threadIdx.x;
-    if (op == OP_N || op == OP_R) {
-      constexpr int TPR = BK / PER;
-      const int r = t / TPR, kk0 = (t % TPR) * PER;
-      const int gm = m0 + r;
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int gk = k0 + kk0 + e;
-        vr[e] = 0; vi[e] = 0;
-        if (gm < M && gk < K) ld(A + (long)gm * lda + gk, vr[e], vi[e]);
-      }
-    } else {
-      constexpr int TPK = ROWS / PER;
-      const int kk = t / TPK, r0 = (t % TPK) * PER;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int gm = m0 + r0 + e;
-        vr[e] = 0; vi[e] = 0;
-        if (gm < M && gk < K) ld(A + (long)gk * lda + gm, vr[e], vi[e]);
-      }
-    }
-  }
-  __device__ inline void put(int op, R (*re)[ROWS + 2], R (*im)[ROWS + 2]) const {
-    const int t = threadIdx.x;
-    if (op == OP_N || op == OP_R) {
-      constexpr int TPR = BK / PER;
-      const int r = t / TPR, kk0 = (t % TPR) * PER;
-      const R sgn = (op == OP_R) ? R(-1) : R(1);
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        re[kk0 + e][r] = vr[e];
-        im[kk0 + e][r] = sgn * vi[e];
-      }
-    } else {
-      constexpr int TPK = ROWS / PER;
-      const int kk = t / TPK, r0 = (t % TPK) * PER;
-      const R sgn = (op == OP_C) ? R(-1) : R(1);
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        re[kk][r0 + e] = vr[e];
-        im[kk][r0 + e] = sgn * vi[e];
-      }
-    }
-  }
-};
-
-template <typename T, typename R, int COLS, int BK>
-struct ColsStage {
-  static constexpr int PER = COLS * BK / 256;
-  R vr[PER], vi[PER];
-  __device__ inline void fetch(const T* __restrict__ B, long ldb, int op, int N, int K, int n0, int k0) {
-    const int t = threadIdx.x;
-    if (op == OP_N || op == OP_R) {
-      constexpr int TPK = COLS / PER;
-      const int kk = t / TPK, c0 = (t % TPK) * PER;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int gn = n0 + c0 + e;
-        vr[e] = 0; vi[e] = 0;
-        if (gn < N && gk < K) ld(B + (long)gk * ldb + gn, vr[e], vi[e]);
-      }
-    } else {
-      constexpr int TPC = BK / PER;
-      const int c = t / TPC, kk0 = (t % TPC) * PER;
-      const int gn = n0 + c;
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int gk = k0 + kk0 + e;
-        vr[e] = 0; vi[e] = 0;
-        if (gn < N && gk < K) ld(B + (long)gn * ldb + gk, vr[e], vi[e]);
-      }
-    }
-  }
-  __device__ inline void put(int op, R (*re)[COLS + 2], R (*im)[COLS + 2]) const {
-    const int t = threadIdx.x;
-    if (op == OP_N || op == OP_R) {
-      constexpr int TPK = COLS / PER;
-      const int kk = t / TPK, c0 = (t % TPK) * PER;
-      const R sgn = (op == OP_R) ? R(-1) : R(1);
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        re[kk][c0 + e] = vr[e];
-        im[kk][c0 + e] = sgn * vi[e];
-      }
-    } else {
-      constexpr int TPC = BK / PER;
-      const int c = t / TPC, kk0 = (t % TPC) * PER;
-      const R sgn = (op == OP_C) ? R(-1) : R(1);
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        re[kk0 + e][c] = vr[e];
-        im[kk0 + e][c] = sgn * vi[e];
-      }
-    }
-  }
-};
-
 __device__ inline void problem_dims(const GemmArgs& a, int b, int& M, int& N, int& K) {
   if (a.dims) {
     M = min(a.dims[3 * b + 0], a.m);
@@ -302,20 +187,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
       if constexpr (CPLX) acc_im[i][j] = d4{0, 0, 0, 0};
     }
 
-  RowsStage<T, double, BM, BK> sa;
-  ColsStage<T, double, BN, BK> sb;
-  sa.fetch(A, a.lda, a.opA, M, K, m0, 0);
-  sb.fetch(B, a.ldb, a.opB, N, K, n0, 0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
-    sa.put(a.opA, As_re, As_im);
-    sb.put(a.opB, Bs_re, Bs_im);
+    stage_rows_tile<T, double, BM, BK>(A, a.lda, a.opA, M, K, m0, k0, As_re, As_im);
+    stage_cols_tile<T, double, BN, BK>(B, a.ldb, a.opB, N, K, n0, k0, Bs_re, Bs_im);
     __syncthreads();
-    if (k0 + BK < K) {
-      // the next tile's loads overlap this tile's matrix work
-      sa.fetch(A, a.lda, a.opA, M, K, m0, k0 + BK);
-      sb.fetch(B, a.ldb, a.opB, N, K, n0, k0 + BK);
-    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double fa_re[FI], fa_im[FI], fb_re[FJ], fb_im[FJ];

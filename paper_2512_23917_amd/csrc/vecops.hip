@@ -2,6 +2,9 @@
 // linear combinations (TCI-spec appendix: convert, cplx_conj, scale,
 // linear_combine), elementwise closeness (close), the Lanczos multi-dot /
 // multi-axpy with FP64 accumulation, and the two-site MPO product W12.
+#include <array>
+#include <utility>
+
 #include "common.hpp"
 #include "vecops.hpp"
 
@@ -217,6 +220,22 @@ static unsigned md_grid(long long n) {
   return (unsigned)std::max<long long>(1, std::min<long long>(MD_BLOCKS, (n + 255) / 256));
 }
 
+// Launch tables with one instantiation per basis size (1..MD_MAXV), so that
+// each kernel holds exactly the registers its basis needs.
+typedef void (*MdLaunch)(unsigned, hipStream_t, const cd*, int, const cd*, long long, double*);
+template <int NV>
+void md_launch(unsigned g, hipStream_t s, const cd* V, int nv, const cd* w, long long n, double* partial) {
+  hipLaunchKernelGGL(multidot_partial_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, w, n, partial);
+}
+template <int... I>
+constexpr std::array<MdLaunch, sizeof...(I)> md_make(std::integer_sequence<int, I...>) {
+  return {&md_launch<I + 1>...};
+}
+static const std::array<MdLaunch, MD_MAXV>& md_table() {
+  static const auto t = md_make(std::make_integer_sequence<int, MD_MAXV>{});
+  return t;
+}
+
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
                     hipStream_t s) {
   if (nv <= 0) return hipSuccess;
@@ -224,10 +243,7 @@ hipError_t multidot(const void* V, int nv, const void* w, long long n, double* p
   const unsigned g = md_grid(n);
   const cd* Vc = (const cd*)V;
   const cd* wc = (const cd*)w;
-  if (nv <= 2) hipLaunchKernelGGL(multidot_partial_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
-  else if (nv <= 8) hipLaunchKernelGGL(multidot_partial_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
-  else if (nv <= 16) hipLaunchKernelGGL(multidot_partial_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
-  else hipLaunchKernelGGL(multidot_partial_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, wc, n, partial);
+  md_table()[nv - 1](g, s, Vc, nv, wc, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
@@ -279,15 +295,27 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int 
   if (t == 0) out[0] = sh[0];
 }
 
+typedef void (*MaLaunch)(unsigned, hipStream_t, const cd*, int, const double*, double, cd*, long long, double*);
+template <int NV>
+void ma_launch(unsigned g, hipStream_t s, const cd* V, int nv, const double* c, double sign, cd* w, long long n,
+               double* nrm_part) {
+  hipLaunchKernelGGL(multiaxpy_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, nrm_part);
+}
+template <int... I>
+constexpr std::array<MaLaunch, sizeof...(I)> ma_make(std::integer_sequence<int, I...>) {
+  return {&ma_launch<I + 1>...};
+}
+static const std::array<MaLaunch, MD_MAXV>& ma_table() {
+  static const auto t = ma_make(std::make_integer_sequence<int, MD_MAXV>{});
+  return t;
+}
+
 static hipError_t multiaxpy_launch(const void* V, int nv, const double* c, double sign, void* w, long long n,
                                    double* nrm_part, hipStream_t s) {
   const unsigned g = md_grid(n);
   const cd* Vc = (const cd*)V;
   cd* wc = (cd*)w;
-  if (nv <= 2) hipLaunchKernelGGL(multiaxpy_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
-  else if (nv <= 8) hipLaunchKernelGGL(multiaxpy_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
-  else if (nv <= 16) hipLaunchKernelGGL(multiaxpy_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
-  else hipLaunchKernelGGL(multiaxpy_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, nrm_part);
+  ma_table()[nv - 1](g, s, Vc, nv, c, sign, wc, n, nrm_part);
   return hipGetLastError();
 }
 
@@ -348,17 +376,28 @@ __global__ __launch_bounds__(256) void axpy_dot_kernel(const cd* V, int nv, cons
   }
 }
 
+typedef void (*AdLaunch)(unsigned, hipStream_t, const cd*, int, const double*, double, cd*, long long, double*);
+template <int NV>
+void ad_launch(unsigned g, hipStream_t s, const cd* V, int nv, const double* c, double sign, cd* w, long long n,
+               double* partial) {
+  hipLaunchKernelGGL(axpy_dot_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, partial);
+}
+template <int... I>
+constexpr std::array<AdLaunch, sizeof...(I)> ad_make(std::integer_sequence<int, I...>) {
+  return {&ad_launch<I + 1>...};
+}
+static const std::array<AdLaunch, MD_MAXV>& ad_table() {
+  static const auto t = ad_make(std::make_integer_sequence<int, MD_MAXV>{});
+  return t;
+}
+
 hipError_t axpy_multidot(const void* V, int nv, const double* c, double sign, void* w, long long n,
                          double* partial, double* out, hipStream_t s) {
   if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
   const cd* Vc = (const cd*)V;
   cd* wc = (cd*)w;
-  if (nv <= 2) hipLaunchKernelGGL(axpy_dot_kernel<2>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
-  else if (nv <= 8) hipLaunchKernelGGL(axpy_dot_kernel<8>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
-  else if (nv <= 16) hipLaunchKernelGGL(axpy_dot_kernel<16>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
-  else if (nv <= 24) hipLaunchKernelGGL(axpy_dot_kernel<24>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
-  else hipLaunchKernelGGL(axpy_dot_kernel<32>, dim3(g), dim3(256), 0, s, Vc, nv, c, sign, wc, n, partial);
+  ad_table()[nv - 1](g, s, Vc, nv, c, sign, wc, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
