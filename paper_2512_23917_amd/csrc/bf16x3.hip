@@ -150,13 +150,16 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
   const int lr = lane & 15, lk = lane >> 4;
   const int rd = 8 * (lk ^ ((lr >> 2) & 3));   // swizzled k offset of this lane's operand chunk
 
-  f4v acc_re[IM][JN], acc_im[IM][JN];
+  // acc_ii collects the im x im products, subtracted from acc_re in the
+  // epilogue (no negated operand copies in the inner loop)
+  f4v acc_re[IM][JN], acc_im[IM][JN], acc_ii[IM][JN];
 #pragma unroll
   for (int i = 0; i < IM; ++i)
 #pragma unroll
     for (int j = 0; j < JN; ++j) {
       acc_re[i][j] = f4v{0, 0, 0, 0};
       acc_im[i][j] = f4v{0, 0, 0, 0};
+      acc_ii[i][j] = f4v{0, 0, 0, 0};
     }
 
   // chunk t: row t >> 2, k chunk t & 3
@@ -198,20 +201,15 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < IM; ++i) {
-      bf8v nh, nl;
-      if constexpr (CPLX) {
-        nh = -fa[2][i];
-        nl = -fa[3][i];
-      }
 #pragma unroll
       for (int j = 0; j < JN; ++j) {
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], acc_re[i][j], 0, 0, 0);
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], acc_re[i][j], 0, 0, 0);
         acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], acc_re[i][j], 0, 0, 0);
         if constexpr (CPLX) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[2][j], acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nh, fb[3][j], acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nl, fb[2][j], acc_re[i][j], 0, 0, 0);
+          acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[2][j], acc_ii[i][j], 0, 0, 0);
+          acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[2][i], fb[3][j], acc_ii[i][j], 0, 0, 0);
+          acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[3][i], fb[2][j], acc_ii[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[2][j], acc_im[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[3][j], acc_im[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[2][j], acc_im[i][j], 0, 0, 0);
@@ -237,7 +235,8 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
         const int row = m0 + wm * XWM + i * 16 + 4 * lk + r;
         const int col = n0 + wn * XWN + j * 16 + lr;
         if (row < a.m && col < a.n) {
-          const float vr = acc_re[i][j][r], vi = CPLX ? acc_im[i][j][r] : 0.f;
+          const float vr = CPLX ? acc_re[i][j][r] - acc_ii[i][j][r] : acc_re[i][j][r];
+          const float vi = CPLX ? acc_im[i][j][r] : 0.f;
           float orr = ar * vr - ai * vi, oi = ar * vi + ai * vr;
           if constexpr (CPLX) {
             cf* p = reinterpret_cast<cf*>(a.C) + b * a.sC + (long long)row * a.ldc + col;

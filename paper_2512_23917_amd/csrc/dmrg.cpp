@@ -213,32 +213,56 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     }
     TCI_TRY(heff_apply(ctx, p, xv, dt == C128 ? (void*)w : yout));
     if (dt != C128) TCI_CHECK_HIP(convert(dt, yout, C128, w, N, s));
-    // alpha_j = Re <v_j, w>
-    double hc[2];
+    // alpha_j = Re <v_j, w> (coef[0], read by the recurrence sweep on the device)
     TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
-    TCI_CHECK_HIP(hipMemcpyAsync(hc, coef, sizeof(hc), hipMemcpyDeviceToHost, s));
+    if (j == n_matvec - 1) {   // the last residual enters neither T nor psi
+      double hc[2];
+      TCI_CHECK_HIP(hipMemcpyAsync(hc, coef, sizeof(hc), hipMemcpyDeviceToHost, s));
+      TCI_CHECK_HIP(hipStreamSynchronize(s));
+      alpha.push_back(hc[0]);
+      break;
+    }
+    // w -= alpha v_j + beta_{j-1} v_{j-1}, then classical Gram-Schmidt
+    // against v_0..v_j.  The first sweep subtracts the three-term part and
+    // forms c = V^H w; the second subtracts V c and returns ||w||^2.  A second
+    // Gram-Schmidt pass (one more dot sweep and one more subtraction sweep)
+    // runs only when the first removed more than half of the norm,
+    // ||w_after||^2 < ||c||^2 (the criterion of Daniel, Gragg, Kaufman and
+    // Stewart, 1976, with ||w_before||^2 = ||w_after||^2 + ||c||^2); in exact
+    // arithmetic the second pass subtracts zero.
+    std::vector<double> c1(2 * (j + 1) + 1, 0.0), hc(2, 0.0);
+    const double vbytes = (double)sizeof(cd) * (double)N;   // one basis vector
+    ProfTag tag("lanczos");
+    {
+      ProfScope ps(s, vbytes * (j + 3), "sweep_dot");
+      TCI_CHECK_HIP(three_term_multidot(basis, j + 1, coef, j > 0 ? beta[j - 1] : 0.0, w, N, part, coef + 128, s));
+    }
+    {
+      ProfScope ps(s, vbytes * (j + 3), "sweep_axpy");
+      TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 128 + 2 * (j + 1), s));
+    }
+    TCI_CHECK_HIP(hipMemcpyAsync(hc.data(), coef, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    TCI_CHECK_HIP(hipMemcpyAsync(c1.data(), coef + 128, sizeof(double) * c1.size(), hipMemcpyDeviceToHost, s));
     TCI_CHECK_HIP(hipStreamSynchronize(s));
     const double a = hc[0];
     alpha.push_back(a);
-    // w -= alpha v_j + beta_{j-1} v_{j-1}, then two passes of classical
-    // Gram-Schmidt against v_0..v_j.  Each subtraction sweep also forms the
-    // dot products of its result that the next pass needs, so the basis is
-    // streamed three times per step; the last sweep returns ||w||^2.
-    std::vector<double> c3(2 * (j + 1), 0.0);   // host staging, alive until the sync below
-    {
-      c3[2 * j] = a;
-      if (j > 0) c3[2 * (j - 1)] = beta[j - 1];
-      TCI_CHECK_HIP(hipMemcpyAsync(coef, c3.data(), sizeof(double) * c3.size(), hipMemcpyHostToDevice, s));
-      TCI_CHECK_HIP(axpy_multidot(basis, j + 1, coef, -1.0, w, N, part, coef + 128, s));
-      TCI_CHECK_HIP(axpy_multidot(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 256, s));
-      TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
+    tmax = std::max(tmax, std::fabs(a));
+    double b2 = c1[2 * (j + 1)], cn2 = 0.0;
+    for (int q = 0; q < 2 * (j + 1); ++q) cn2 += c1[q] * c1[q];
+    if (b2 < cn2) {
+      {
+        ProfScope ps(s, vbytes * (j + 2), "reorth2_dot");
+        TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef + 256, s));
+      }
+      {
+        ProfScope ps(s, vbytes * (j + 3), "reorth2_axpy");
+        TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
+      }
+      TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
+      TCI_CHECK_HIP(hipStreamSynchronize(s));
     }
-    double b2 = 0.0;
-    TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
-    TCI_CHECK_HIP(hipStreamSynchronize(s));
     const double b = std::sqrt(b2);
-    tmax = std::max({tmax, std::fabs(a), b});
-    if (j == n_matvec - 1) break;
+    tmax = std::max(tmax, b);
     if (b <= 1e-13 * tmax) break;
     beta.push_back(b);
     TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, basis + (size_t)N * (j + 1), N, s));

@@ -96,7 +96,11 @@ struct TriWs {
   __host__ __device__ static size_t fa(int n) { return pc(n) + align(sizeof(T) * (size_t)ntile(n) * (1 + 2 * NB)); }
   __host__ __device__ static size_t fc(int n) { return fa(n) + 256; }
   __host__ __device__ static size_t cnt(int n) { return fc(n) + align(sizeof(T) * (1 + 2 * NB)); }
-  __host__ __device__ static size_t bytes(int n) { return cnt(n) + 256; }
+  // [V_panel; W^T] and [W^T; V_panel], 2 NB rows of n each: operands of the
+  // fused rank-2NB trailing update
+  __host__ __device__ static size_t cat1(int n) { return cnt(n) + 256; }
+  __host__ __device__ static size_t cat2(int n) { return cat1(n) + align(sizeof(T) * (size_t)2 * NB * n); }
+  __host__ __device__ static size_t bytes(int n) { return cat2(n) + align(sizeof(T) * (size_t)2 * NB * n); }
   __host__ __device__ static int nbt(int n) { return (n + TT - 1) / TT; }
   __host__ __device__ static int ntile(int n) { return nbt(n) * (nbt(n) + 1) / 2; }
   __host__ __device__ static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
@@ -107,7 +111,7 @@ struct TriWs {
 // chunk, so that the reflector set-up and the final reduction are paid once
 // per chunk.  The row sums of a chunk starting at tile cA go to P[cA][rows];
 // the column sums of an off-diagonal tile (R, C) go to P[R][columns of C].
-constexpr int CH = 4;
+constexpr int CH = 8;
 
 __host__ __device__ inline int tri_chunks(int nact) {
   int k = 0;
@@ -500,6 +504,29 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   }
 }
 
+// Operands of the trailing update G -= V W^H + W V^H = [V W] [W V]^H over
+// rows and columns >= t: cat1 = [V_panel; W^T], cat2 = [W^T; V_panel] (rows
+// q < pe from V_panel = Vt rows j0 .., from W^T = W columns), columns >= t.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void tri_cat_kernel(TriArgs a, int j0, int pe, int t) {
+  const int b = blockIdx.y, n = a.n;
+  char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
+  T* c1 = reinterpret_cast<T*>(ws + TriWs<T, NB>::cat1(n));
+  T* c2 = reinterpret_cast<T*>(ws + TriWs<T, NB>::cat2(n));
+  const T* V = reinterpret_cast<const T*>(a.Vt) + b * a.sVt;
+  const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
+  const long long tot = (long long)pe * (n - t);
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    const int q = (int)(e / (n - t)), r = t + (int)(e % (n - t));
+    const T v = V[(long)(j0 + q) * n + r];
+    const T w = W[(long)r * NB + q];
+    c1[(long)q * n + r] = v;
+    c1[(long)(pe + q) * n + r] = w;
+    c2[(long)q * n + r] = w;
+    c2[(long)(pe + q) * n + r] = v;
+  }
+}
+
 template <typename T, int NB>
 static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
   const int n = a.n;
@@ -525,20 +552,19 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
       hipLaunchKernelGGL((tri_colA_kernel<T, NB>), dim3((n - t + TT - 1) / TT, batch), dim3(256), 0, s, a, t, -1,
                          t - 1, j0);
       const int m = n - t;
+      {
+        const long long tot = (long long)pe * m;
+        const unsigned gx = (unsigned)std::min<long long>(256, (tot + 255) / 256);
+        hipLaunchKernelGGL((tri_cat_kernel<T, NB>), dim3(gx, batch), dim3(256), 0, s, a, j0, pe, t);
+      }
+      // one rank-2pe update: G[t:, t:] -= cat1[:, t:]^T conj(cat2[:, t:])
       char* G = reinterpret_cast<char*>(a.G);
-      char* V = reinterpret_cast<char*>(a.Vt);
-      char* W = reinterpret_cast<char*>(a.Wp);
-      GemmArgs g = gemm_args(m, m, pe, OP_T, OP_C, V + ((long)j0 * n + t) * es, n,
-                             W + (long)t * NB * es, NB, G + ((long)t * a.ldg + t) * es, a.ldg);
-      g.sA = a.sVt; g.sB = a.sWp; g.sC = a.sG;
+      char* ws = reinterpret_cast<char*>(a.ws);
+      GemmArgs g = gemm_args(m, m, 2 * pe, OP_T, OP_R, ws + TriWs<T, NB>::cat1(n) + (size_t)t * es, n,
+                             ws + TriWs<T, NB>::cat2(n) + (size_t)t * es, n, G + ((long)t * a.ldg + t) * es, a.ldg);
+      g.sA = a.sws / (long long)es; g.sB = a.sws / (long long)es; g.sC = a.sG;
       g.alpha_re = -1.0; g.beta_re = 1.0; g.batch = batch;
       hipError_t err = gemm(EigT<T>::dtype, PREC_FP64, g, s);
-      if (err != hipSuccess) return err;
-      GemmArgs h = gemm_args(m, m, pe, OP_N, OP_R, W + (long)t * NB * es, NB,
-                             V + ((long)j0 * n + t) * es, n, G + ((long)t * a.ldg + t) * es, a.ldg);
-      h.sA = a.sWp; h.sB = a.sVt; h.sC = a.sG;
-      h.alpha_re = -1.0; h.beta_re = 1.0; h.batch = batch;
-      err = gemm(EigT<T>::dtype, PREC_FP64, h, s);
       if (err != hipSuccess) return err;
     }
   }
@@ -552,7 +578,11 @@ size_t tridiag_ws_bytes(int dtype, int n) {
 hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s) {
   if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
   if (a.sws < (long long)tridiag_ws_bytes(dtype, a.n)) return hipErrorInvalidValue;
-  hipError_t e = zero_fill(a.ws, (size_t)a.sws * batch, s);
+  // counters, partial sums and the reflector panel start at zero; the
+  // trailing-update operands are written before they are read
+  const size_t zb = dtype == C128 ? TriWs<cd, TRIDIAG_NB>::cat1(a.n) : TriWs<double, TRIDIAG_NB>::cat1(a.n);
+  if (a.sws % 4 != 0) return hipErrorInvalidValue;
+  hipError_t e = zero_fill_rows(a.ws, zb, (size_t)a.sws, batch, s);
   if (e != hipSuccess) return e;
   if (dtype == C128) return tridiag_impl<cd, TRIDIAG_NB>(a, batch, s);
   return tridiag_impl<double, TRIDIAG_NB>(a, batch, s);
@@ -770,106 +800,108 @@ hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n,
 }
 
 // ---------------------------------------------------------------------------
-// Compact-WY factor of each panel (LAPACK larft, forward, columnwise):
-// H_{j0} ... H_{j0+pe-1} = I - V T V^H, T upper triangular pe x pe with
-// T(i,i) = tau_i and T(0:i, i) = -tau_i T(0:i, 0:i) (V(:, 0:i)^H v_i).
-// One workgroup per (panel, problem).
+// Back-transformation U <- Q U with Q = H_0 H_1 ... H_{n-2}, applied in groups
+// of BT_GB consecutive reflectors (several reduction panels), so that the
+// products with the reflector block have 128 rows / inner dimension.
+// Compact-WY factor of a group (LAPACK larft, forward, columnwise):
+// H_{j0} ... H_{j0+g-1} = I - V T V^H, T upper triangular g x g with
+// T(i,i) = tau_i and T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i),
+// S = V^H V from a GEMM.  T is built column by column in LDS, packed by
+// columns (column i holds rows 0..i at offset i(i+1)/2).
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void larft_kernel(TriArgs a, void* Tf, long long sTf) {
-  __shared__ T S[NB][NB];
-  __shared__ T Tl[NB][NB];
-  __shared__ double sh[16];
-  const int panel = blockIdx.x, b = blockIdx.y, n = a.n;
-  const int j0 = panel * NB;
-  if (j0 >= n - 1) return;
-  const int pe = min(NB, n - 1 - j0);  // reflectors exist for columns < n-1
-  const T* V = reinterpret_cast<const T*>(a.Vt) + b * a.sVt;
+constexpr int BT_GB = 128;
+
+template <typename T>
+__global__ __launch_bounds__(BT_GB) void larft_group_kernel(TriArgs a, const void* Sg, long long sS, int j0, int g,
+                                                            void* Tg, long long sT) {
+  __shared__ T Tp[BT_GB * (BT_GB + 1) / 2];
+  __shared__ T scol[BT_GB];
+  const int b = blockIdx.x, q = threadIdx.x;
+  const T* S = reinterpret_cast<const T*>(Sg) + b * sS;   // g x g, ld BT_GB
   const T* tau = reinterpret_cast<const T*>(a.tau) + b * a.stau;
-  T* Tout = reinterpret_cast<T*>(Tf) + b * sTf + (long)panel * NB * NB;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // S[q][i] = v_q^H v_i for q < i (one wave per pair, round robin)
-  for (int pair = wid; pair < pe * pe; pair += 4) {
-    const int q = pair / pe, i = pair % pe;
-    if (q >= i) continue;
-    const T* vq = V + (long)(j0 + q) * n;
-    const T* vi = V + (long)(j0 + i) * n;
-    T acc = EigT<T>::zero();
-    for (int r = j0 + 1 + lane; r < n; r += 64) acc = add(acc, mulr(cj(vq[r]), vi[r]));
-    acc = wsum(acc);
-    if (lane == 0) S[q][i] = acc;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < pe; ++i) {
-      const T ti = tau[j0 + i];
-      for (int q = 0; q < i; ++q) {
-        T acc = EigT<T>::zero();
-        for (int r = q; r < i; ++r) acc = add(acc, mulr(Tl[q][r], S[r][i]));
-        Tl[q][i] = mulr(scl(-1.0, ti), acc);
-      }
-      Tl[i][i] = ti;
-      for (int q = i + 1; q < NB; ++q) Tl[q][i] = EigT<T>::zero();
+  T* Tout = reinterpret_cast<T*>(Tg) + b * sT;             // BT_GB x BT_GB, ld BT_GB
+  for (int i = 0; i < g; ++i) {
+    if (q < i) scol[q] = S[(long)q * BT_GB + i];
+    __syncthreads();
+    const T ti = tau[j0 + i];
+    T* coli = Tp + i * (i + 1) / 2;
+    if (q < i) {
+      T acc = EigT<T>::zero();
+      for (int r = q; r < i; ++r) acc = add(acc, mulr(Tp[r * (r + 1) / 2 + q], scol[r]));
+      coli[q] = mulr(scl(-1.0, ti), acc);
+    } else if (q == i) {
+      coli[i] = ti;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  (void)sh;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx % NB;
-    Tout[idx] = (r < pe && c < pe && r <= c) ? Tl[r][c] : EigT<T>::zero();
+  for (int r = 0; r < BT_GB; ++r) {
+    const int c = q;
+    Tout[(long)r * BT_GB + c] = (r < g && c < g && r <= c) ? Tp[c * (c + 1) / 2 + r] : EigT<T>::zero();
   }
 }
 
-// U (n x kmax) <- Q U with Q = H_0 ... H_{n-2}: panels applied last to first,
-// U <- U - V_p (T_p (V_p^H U)).  work: per problem NB x kmax twice.
-template <typename T, int NB>
+static int bt_groups(int n) { return (n - 1 + BT_GB - 1) / BT_GB; }
+
+template <typename T>
 static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, void* U, long long ldu,
-                                     long long sU, int kmax, const int* dims, void* work, int batch,
-                                     hipStream_t s) {
+                                     long long sU, int kmax, void* work, int batch, hipStream_t s) {
   const int n = a.n;
-  const int npanels = (n - 1 + NB - 1) / NB;
-  if (npanels <= 0 || kmax <= 0) return hipSuccess;
-  hipLaunchKernelGGL((larft_kernel<T, NB>), dim3(npanels, batch), dim3(256), 0, s, a, Tf, sTf);
+  const int ng = bt_groups(n);
+  if (ng <= 0 || kmax <= 0) return hipSuccess;
   const size_t es = sizeof(T);
-  char* W1 = reinterpret_cast<char*>(work);
-  char* W2 = W1 + (size_t)batch * NB * kmax * es;
+  const int dt = EigT<T>::dtype;
   char* V = reinterpret_cast<char*>(a.Vt);
   char* Uc = reinterpret_cast<char*>(U);
   char* Tc = reinterpret_cast<char*>(Tf);
-  (void)dims;
-  for (int p = npanels - 1; p >= 0; --p) {
-    const int j0 = p * NB;
-    const int pe = min(NB, n - 1 - j0);
-    const int rows = n - j0 - 1;
-    // W1 = V_p^H U(j0+1:n, :)
-    GemmArgs g1 = gemm_args(pe, kmax, rows, OP_R, OP_N, V + ((long)j0 * n + j0 + 1) * es, n,
+  char* Sc = Tc + (size_t)ng * BT_GB * BT_GB * es;   // per-problem S scratch after the T factors
+  char* W1 = reinterpret_cast<char*>(work);
+  char* W2 = W1 + (size_t)batch * BT_GB * kmax * es;
+  const long long sW = (long long)BT_GB * kmax;
+  hipError_t err = hipSuccess;
+  // T factor of every group
+  for (int grp = 0; grp < ng; ++grp) {
+    const int j0 = grp * BT_GB, g = min(BT_GB, n - 1 - j0), rows = n - j0 - 1;
+    // S = V_g^H V_g over rows j0+1 .. n-1 (V_g = columns of Vt rows j0 ..)
+    GemmArgs gs = gemm_args(g, g, rows, OP_R, OP_T, V + ((long)j0 * n + j0 + 1) * es, n,
+                            V + ((long)j0 * n + j0 + 1) * es, n, Sc, BT_GB);
+    gs.sA = a.sVt; gs.sB = a.sVt; gs.sC = sTf; gs.batch = batch;
+    err = gemm(dt, PREC_FP64, gs, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(larft_group_kernel<T>, dim3(batch), dim3(BT_GB), 0, s, a, (const void*)Sc, sTf, j0, g,
+                       (void*)(Tc + (size_t)grp * BT_GB * BT_GB * es), sTf);
+  }
+  // groups applied last to first: U <- U - V_g (T_g (V_g^H U))
+  for (int grp = ng - 1; grp >= 0; --grp) {
+    const int j0 = grp * BT_GB, g = min(BT_GB, n - 1 - j0), rows = n - j0 - 1;
+    GemmArgs g1 = gemm_args(g, kmax, rows, OP_R, OP_N, V + ((long)j0 * n + j0 + 1) * es, n,
                             Uc + (long)(j0 + 1) * ldu * es, ldu, W1, kmax);
-    g1.sA = a.sVt; g1.sB = sU; g1.sC = (long long)NB * kmax; g1.batch = batch;
-    hipError_t err = gemm(EigT<T>::dtype, PREC_FP64, g1, s);
+    g1.sA = a.sVt; g1.sB = sU; g1.sC = sW; g1.batch = batch;
+    err = gemm(dt, PREC_FP64, g1, s);
     if (err != hipSuccess) return err;
-    // W2 = T_p W1
-    GemmArgs g2 = gemm_args(pe, kmax, pe, OP_N, OP_N, Tc + (long)p * NB * NB * es, NB, W1, kmax, W2, kmax);
-    g2.sA = sTf; g2.sB = (long long)NB * kmax; g2.sC = (long long)NB * kmax; g2.batch = batch;
-    err = gemm(EigT<T>::dtype, PREC_FP64, g2, s);
+    GemmArgs g2 = gemm_args(g, kmax, g, OP_N, OP_N, Tc + (size_t)grp * BT_GB * BT_GB * es, BT_GB, W1, kmax, W2,
+                            kmax);
+    g2.sA = sTf; g2.sB = sW; g2.sC = sW; g2.batch = batch;
+    err = gemm(dt, PREC_FP64, g2, s);
     if (err != hipSuccess) return err;
-    // U(j0+1:n, :) -= V_p W2
-    GemmArgs g3 = gemm_args(rows, kmax, pe, OP_T, OP_N, V + ((long)j0 * n + j0 + 1) * es, n, W2, kmax,
+    GemmArgs g3 = gemm_args(rows, kmax, g, OP_T, OP_N, V + ((long)j0 * n + j0 + 1) * es, n, W2, kmax,
                             Uc + (long)(j0 + 1) * ldu * es, ldu);
-    g3.sA = a.sVt; g3.sB = (long long)NB * kmax; g3.sC = sU;
+    g3.sA = a.sVt; g3.sB = sW; g3.sC = sU;
     g3.alpha_re = -1.0; g3.beta_re = 1.0; g3.batch = batch;
-    err = gemm(EigT<T>::dtype, PREC_FP64, g3, s);
+    err = gemm(dt, PREC_FP64, g3, s);
     if (err != hipSuccess) return err;
   }
   return hipGetLastError();
 }
 
+size_t tridiag_backtransform_tf_elems(int n) { return (size_t)(std::max(1, bt_groups(n)) + 1) * BT_GB * BT_GB; }
+size_t tridiag_backtransform_work_elems(int kmax) { return (size_t)2 * BT_GB * kmax; }
+
 hipError_t tridiag_backtransform(int dtype, const TriArgs& a, void* Tf, long long sTf, void* U,
                                  long long ldu, long long sU, int kmax, void* work, int batch,
                                  hipStream_t s) {
-  if (dtype == C128)
-    return backtransform_impl<cd, TRIDIAG_NB>(a, Tf, sTf, U, ldu, sU, kmax, nullptr, work, batch, s);
-  if (dtype == F64)
-    return backtransform_impl<double, TRIDIAG_NB>(a, Tf, sTf, U, ldu, sU, kmax, nullptr, work, batch, s);
+  if (batch > 1 && sTf < (long long)tridiag_backtransform_tf_elems(a.n)) return hipErrorInvalidValue;
+  if (dtype == C128) return backtransform_impl<cd>(a, Tf, sTf, U, ldu, sU, kmax, work, batch, s);
+  if (dtype == F64) return backtransform_impl<double>(a, Tf, sTf, U, ldu, sU, kmax, work, batch, s);
   return hipErrorInvalidValue;
 }
 

@@ -36,8 +36,11 @@ hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, lon
 hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n, const double* lam,
                          long long slam, const int* chi, int kmax, double* Z, long long ldz, long long sZ,
                          double* work, int batch, hipStream_t s);
-// U[b] (n x kmax, ld ldu, dtype) <- Q U[b].  Tf: batch x npanels x NB x NB (stride sTf);
-// work: 2 * batch * NB * kmax elements of dtype.
+// U[b] (n x kmax, ld ldu, dtype) <- Q U[b].  Tf: per problem
+// tridiag_backtransform_tf_elems(n) elements of dtype (stride sTf); work:
+// batch * tridiag_backtransform_work_elems(kmax) elements of dtype.
+size_t tridiag_backtransform_tf_elems(int n);
+size_t tridiag_backtransform_work_elems(int kmax);
 hipError_t tridiag_backtransform(int dtype, const TriArgs& a, void* Tf, long long sTf, void* U,
                                  long long ldu, long long sU, int kmax, void* work, int batch,
                                  hipStream_t s);

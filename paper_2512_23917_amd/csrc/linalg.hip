@@ -550,19 +550,123 @@ __global__ void diag_copy_kernel(const T* G, long long ldg, long long sG, int k,
     diag0[b * sdiag + j] = creal_(G[b * sG + (long long)j * ldg + j]);
 }
 
+__device__ inline void ld2(const double* p, long long i, double& r, double& im) { r = p[i]; im = 0.0; }
+__device__ inline void ld2(const cd* p, long long i, double& r, double& im) { r = p[i].x; im = p[i].y; }
+__device__ inline void st2(double* p, long long i, double r, double) { p[i] = r; }
+__device__ inline void st2(cd* p, long long i, double r, double im) { p[i] = cd{r, im}; }
+
+// G = Y^H Y (column mode) or Y Y^H (row mode), k x k per problem
+static hipError_t gram_into(int dt, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
+                            int batch, hipStream_t s) {
+  GemmArgs g = mode == 0 ? gemm_args(k, k, m, OP_C, OP_N, Y, ldy, Y, ldy, G, k)
+                         : gemm_args(k, k, m, OP_N, OP_C, Y, ldy, Y, ldy, G, k);
+  g.sA = sY; g.sB = sY; g.sC = (long long)k * k; g.batch = batch;
+  return gemm(dt, PREC_FP64, g, s);
+}
+
+// Squared Frobenius distance of G from the identity over the entries whose
+// row and column both belong to non-zero vectors (G_ii > 0 and G_jj > 0):
+// block (x, b) sums rows x, x + gridDim.x, ... of problem b into
+// part[b * gridDim.x + x].
+template <typename T>
+__global__ __launch_bounds__(256) void ortho_defect_kernel(const T* G, int k, double* part) {
+  __shared__ double sh[4];
+  const int b = blockIdx.y;
+  const T* g = G + (long long)b * k * k;
+  double acc = 0.0;
+  for (int i = blockIdx.x; i < k; i += gridDim.x) {
+    if (!(creal_(g[(long long)i * k + i]) > 0.0)) continue;
+    for (int j = threadIdx.x; j < k; j += 256) {
+      if (!(creal_(g[(long long)j * k + j]) > 0.0)) continue;
+      double re, im;
+      ld2(g, (long long)i * k + j, re, im);
+      if (i == j) re -= 1.0;
+      acc += re * re + im * im;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// out[0] = max over problems of the sum of that problem's nparts partials
+__global__ void ortho_defect_final_kernel(const double* part, int nparts, int batch, double* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double mx = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    double t = 0.0;
+    for (int x = 0; x < nparts; ++x) t += part[(long long)b * nparts + x];
+    mx = fmax(mx, t);
+  }
+  out[0] = mx;
+}
+
+// G <- M = strict upper triangle of G + (diag(G) - 1) / 2, lower triangle zero
+// (R - I to first order, for the Cholesky factor R of G = I + E)
+template <typename T>
+__global__ void first_order_factor_kernel(T* G, int k) {
+  T* g = G + (long long)blockIdx.y * k * k;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)k * k; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    if (i > j) {
+      st2(g, e, 0.0, 0.0);
+    } else if (i == j) {
+      double re, im;
+      ld2(g, e, re, im);
+      st2(g, e, 0.5 * (re - 1.0), 0.0);
+    }
+  }
+}
+
+hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
+                        double* part, double* out, int batch, hipStream_t s) {
+  if (k <= 0 || m <= 0 || batch <= 0) return hipErrorInvalidValue;
+  if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
+  hipError_t e = gram_into(dtype, mode, Y, ldy, sY, m, k, G, batch, s);
+  if (e != hipSuccess) return e;
+  const int np = ORTHO_DEFECT_PARTS;
+  if (dtype == C128)
+    hipLaunchKernelGGL(ortho_defect_kernel<cd>, dim3(np, batch), dim3(256), 0, s, (const cd*)G, k, part);
+  else
+    hipLaunchKernelGGL(ortho_defect_kernel<double>, dim3(np, batch), dim3(256), 0, s, (const double*)G, k, part);
+  hipLaunchKernelGGL(ortho_defect_final_kernel, dim3(1), dim3(64), 0, s, part, np, batch, out);
+  return hipGetLastError();
+}
+
+hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
+                                      void* G, void* X, int batch, hipStream_t s) {
+  if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min<long long>(1024, ((long long)k * k + 255) / 256);
+  if (dtype == C128)
+    hipLaunchKernelGGL(first_order_factor_kernel<cd>, dim3(gx, batch), dim3(256), 0, s, (cd*)G, k);
+  else if (dtype == F64)
+    hipLaunchKernelGGL(first_order_factor_kernel<double>, dim3(gx, batch), dim3(256), 0, s, (double*)G, k);
+  else
+    return hipErrorInvalidValue;
+  // column mode: X = Y - Y M; row mode: X = Y - M^H Y (X holds Y on entry)
+  GemmArgs g = mode == 0 ? gemm_args(m, k, k, OP_N, OP_N, Y, ldy, G, k, X, ldy)
+                         : gemm_args(k, m, k, OP_C, OP_N, G, k, Y, ldy, X, ldy);
+  g.sA = mode == 0 ? sY : (long long)k * k;
+  g.sB = mode == 0 ? (long long)k * k : sY;
+  g.sC = sY; g.batch = batch;
+  g.alpha_re = -1.0; g.beta_re = 1.0;
+  return gemm(dtype, PREC_FP64, g, s);
+}
+
 template <typename T>
 static hipError_t cholqr_impl(int mode, void* Y, long long ldy, long long sY, int m, int k, void* Q,
-                              long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s) {
+                              long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s,
+                              bool have_gram) {
   const int dt = LT<T>::dtype;
   const size_t es = sizeof(T);
   char* G = reinterpret_cast<char*>(w.G);
   const long long ldg = k, sG = (long long)k * k;
-  // G = Y^H Y (column mode) or X X^H (row mode)
-  GemmArgs g = mode == 0 ? gemm_args(k, k, m, OP_C, OP_N, Y, ldy, Y, ldy, G, ldg)
-                         : gemm_args(k, k, m, OP_N, OP_C, Y, ldy, Y, ldy, G, ldg);
-  g.sA = sY; g.sB = sY; g.sC = sG; g.batch = batch;
-  hipError_t err = gemm(dt, PREC_FP64, g, s);
-  if (err != hipSuccess) return err;
+  hipError_t err = hipSuccess;
+  if (!have_gram) {
+    err = gram_into(dt, mode, Y, ldy, sY, m, k, G, batch, s);
+    if (err != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(diag_copy_kernel<T>, dim3((k + 255) / 256, batch), dim3(256), 0, s, (const T*)G, ldg, sG,
                      k, w.diag0, (long long)k);
   const int nblk = (k + CB - 1) / CB;
@@ -635,10 +739,10 @@ static hipError_t cholqr_impl(int mode, void* Y, long long ldy, long long sY, in
 }
 
 hipError_t cholqr(int dtype, int mode, void* Y, long long ldy, long long sY, int m, int k, void* Q,
-                  long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s) {
+                  long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s, bool have_gram) {
   if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
-  if (dtype == C128) return cholqr_impl<cd>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s);
-  if (dtype == F64) return cholqr_impl<double>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s);
+  if (dtype == C128) return cholqr_impl<cd>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s, have_gram);
+  if (dtype == F64) return cholqr_impl<double>(mode, Y, ldy, sY, m, k, Q, ldq, sQ, w, tau, batch, s, have_gram);
   return hipErrorInvalidValue;
 }
 

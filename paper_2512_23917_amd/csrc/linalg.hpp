@@ -49,7 +49,21 @@ hipError_t permute(int dtype, const void* in, void* out, int order, const long l
 
 // mode 0: columns of Y (m x k) orthonormalised; mode 1: rows of X (k x m).
 // Y is consumed as workspace.  Q receives the result (dropped columns/rows zero).
+// have_gram: w.G already holds the Gram matrix of Y (ortho_defect).
 hipError_t cholqr(int dtype, int mode, void* Y, long long ldy, long long sY, int m, int k, void* Q,
-                  long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s);
+                  long long ldq, long long sQ, CholWork w, double tau, int batch, hipStream_t s,
+                  bool have_gram = false);
+// Gram matrix of the columns (mode 0) or rows (mode 1) of Y into G (k x k per
+// problem), then out[0] = max over problems of ||G - I||_F^2 restricted to the
+// non-zero vectors (part: batch * ORTHO_DEFECT_PARTS doubles).  C128 / F64.
+constexpr int ORTHO_DEFECT_PARTS = 64;
+hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
+                        double* part, double* out, int batch, hipStream_t s);
+// Cholesky QR to first order for G = I + E with small E: R = I + M + O(E^2)
+// with M = strict upper triangle of E + diag(E) / 2, so that
+// X = Y - Y M (mode 0) or X = Y - M^H Y (mode 1).  G (from ortho_defect) is
+// overwritten by M; X must hold a copy of Y on entry and must not alias it.
+hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
+                                      void* G, void* X, int batch, hipStream_t s);
 
 }  // namespace tci

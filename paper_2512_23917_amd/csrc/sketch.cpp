@@ -204,11 +204,10 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     if (!Wv) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
     TCI_CHECK_HIP(real_to_complex(Zr, Wv, sW, sW, sW, nb, s));
   }
-  const int npan = std::max(1, (ng - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB);
-  SK_ARENA(Tf, char, ew * (size_t)npan * TRIDIAG_NB * TRIDIAG_NB * nb);
-  SK_ARENA(btw, char, ew * (size_t)2 * TRIDIAG_NB * kz * nb);
-  TCI_CHECK_HIP(tridiag_backtransform(wdt, ta, Tf, (long long)npan * TRIDIAG_NB * TRIDIAG_NB, Wv, kz, sW, kz, btw,
-                                      nb, s));
+  const size_t tfe = tridiag_backtransform_tf_elems(ng);
+  SK_ARENA(Tf, char, ew * tfe * nb);
+  SK_ARENA(btw, char, ew * tridiag_backtransform_work_elems(kz) * nb);
+  TCI_CHECK_HIP(tridiag_backtransform(wdt, ta, Tf, (long long)tfe, Wv, kz, sW, kz, btw, nb, s));
   // U = Q W, gauge, V^H = diag(1/s) U^H theta (rows re-orthonormalised)
   const long long sU = (long long)m * kz, sV = (long long)kz * n;
   void* U = ctx->arena.get(ew * (size_t)sU * nb);

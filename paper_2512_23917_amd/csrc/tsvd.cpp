@@ -36,21 +36,50 @@ static int work_dtype(int dt) { return dt == C64 ? C128 : dt == F32 ? F64 : dt; 
   type* ptr = static_cast<type*>(ctx->arena.get(sizeof(type) * (size_t)(count)));      \
   if (!ptr) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace allocation failed: " #ptr)
 
+// Squared Frobenius bound on ||G - I|| below which one first-order Cholesky-QR
+// step leaves an orthogonality defect of order ||G - I||^2, below rounding.
+static constexpr double FIRST_ORDER_DEFECT2 = 1e-16;
+
 static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long ldx, long long sX, int m,
                           int k, void* tmp, int nb) {
   // X (column mode m x k, or row mode k x m) is orthonormalised in place; tmp is
-  // a buffer of the same size.  Two Cholesky-QR passes.
+  // a buffer of the same size.  Cholesky-QR passes until the Gram matrix is
+  // within FIRST_ORDER_DEFECT2 of the identity, then one first-order step
+  // (at most two full passes, as in CholeskyQR2).
+  hipStream_t s = ctx->stream;
   const size_t es = elem_bytes(wdt);
+  const size_t bytes = es * (size_t)sX * nb;
   CholWork w{};
   w.G = ctx->arena.get(es * cholqr_work_elems(k) * nb);
   w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
   w.diag0 = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
-  if (!w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
-  // the RI region is addressed per problem with stride nblk*32*32 from w.RI;
-  // G with stride k*k from w.G (see cholqr_impl)
-  TCI_CHECK_HIP(cholqr(wdt, mode, X, ldx, sX, m, k, tmp, ldx, sX, w, CHOL_DROP_TAU, nb, ctx->stream));
-  TCI_CHECK_HIP(cholqr(wdt, mode, tmp, ldx, sX, m, k, X, ldx, sX, w, CHOL_DROP_TAU, nb, ctx->stream));
+  double* part = static_cast<double*>(ctx->arena.get(sizeof(double) * ((size_t)nb * ORTHO_DEFECT_PARTS + 1)));
+  if (!w.G || !w.diag0 || !w.mask || !part) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
+  double* dout = part + (size_t)nb * ORTHO_DEFECT_PARTS;
+  auto defect = [&](const void* Y, double& d) -> tci_status {
+    TCI_CHECK_HIP(ortho_defect(wdt, mode, Y, ldx, sX, m, k, w.G, part, dout, nb, s));
+    TCI_CHECK_HIP(hipMemcpyAsync(&d, dout, sizeof(double), hipMemcpyDeviceToHost, s));
+    TCI_CHECK_HIP(hipStreamSynchronize(s));
+    return TCI_OK;
+  };
+  // first-order step from Y (Gram in w.G) into X
+  auto finish = [&](const void* Y) -> tci_status {
+    TCI_CHECK_HIP(hipMemcpyAsync(X, Y, bytes, hipMemcpyDeviceToDevice, s));
+    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, Y, ldx, sX, m, k, w.G, X, nb, s));
+    return TCI_OK;
+  };
+  double d = 0.0;
+  TCI_TRY(defect(X, d));
+  if (d <= FIRST_ORDER_DEFECT2) {   // X already holds the copy the step updates
+    TCI_CHECK_HIP(hipMemcpyAsync(tmp, X, bytes, hipMemcpyDeviceToDevice, s));
+    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, tmp, ldx, sX, m, k, w.G, X, nb, s));
+    return TCI_OK;
+  }
+  TCI_CHECK_HIP(cholqr(wdt, mode, X, ldx, sX, m, k, tmp, ldx, sX, w, CHOL_DROP_TAU, nb, s, true));
+  TCI_TRY(defect(tmp, d));
+  if (d <= FIRST_ORDER_DEFECT2) return finish(tmp);
+  TCI_CHECK_HIP(cholqr(wdt, mode, tmp, ldx, sX, m, k, X, ldx, sX, w, CHOL_DROP_TAU, nb, s, true));
   return TCI_OK;
 }
 
@@ -129,7 +158,10 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
   const long long sZ = (long long)ng * kz;
   TCI_CHECK_HIP(zero_fill(Z, sizeof(double) * (size_t)sZ * nb, s));
   TCI_CHECK_HIP(tridiag_invit(st.d, st.e, ng, ng, st.lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
-  TCI_TRY(cholqr2(ctx, F64, 0, Z, kz, sZ, ng, kz, Z2, nb));
+  {
+    ProfTag tag("svd_zqr");
+    TCI_TRY(cholqr2(ctx, F64, 0, Z, kz, sZ, ng, kz, Z2, nb));
+  }
   // back-transformation to eigenvectors of G
   void* Ev;
   if (cplx) {
@@ -139,13 +171,12 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
   } else {
     Ev = Z;
   }
-  const int npan = (ng - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB;
-  ARENA(Tf, char, es * (size_t)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB * nb);
-  ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * kz * nb);
+  const size_t tfe = tridiag_backtransform_tf_elems(ng);
+  ARENA(Tf, char, es * tfe * nb);
+  ARENA(btw, char, es * tridiag_backtransform_work_elems(kz) * nb);
   {
     ProfTag tag("svd_backtr");
-    TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)std::max(1, npan) * TRIDIAG_NB * TRIDIAG_NB, Ev,
-                                        kz, sZ, kz, btw, nb, s));
+    TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)tfe, Ev, kz, sZ, kz, btw, nb, s));
   }
   ProfTag tag_uv("svd_uv");
   // left factor U (m x kz)
@@ -176,6 +207,7 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
     g.rs = sinv; g.s_rs = kmax;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
+  ProfTag tag_vqr("svd_vqr");
   TCI_TRY(cholqr2(ctx, wdt, 1, Vh, n, sV, n, kz, Vt2, nb));
   out.U = U;
   out.Vh = Vh;
@@ -542,10 +574,10 @@ tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v) {
     if (!Ev) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
     TCI_CHECK_HIP(real_to_complex(Z, Ev, (long long)n * n, 0, 0, 1, s));
   }
-  const int npan = std::max(1, (n - 1 + TRIDIAG_NB - 1) / TRIDIAG_NB);
-  ARENA(Tf, char, es * (size_t)npan * TRIDIAG_NB * TRIDIAG_NB);
-  ARENA(btw, char, es * (size_t)2 * TRIDIAG_NB * n);
-  TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, 0, Ev, n, 0, n, btw, 1, s));
+  const size_t tfe = tridiag_backtransform_tf_elems(n);
+  ARENA(Tf, char, es * tfe);
+  ARENA(btw, char, es * tridiag_backtransform_work_elems(n));
+  TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, (long long)tfe, Ev, n, 0, n, btw, 1, s));
   // ascending order: reverse the descending bisection order
   TCI_CHECK_HIP(reverse_columns(dt, Ev, n, n, n, s));
   TCI_CHECK_HIP(gauge_columns(dt, Ev, n, 0, n, n, nullptr, 1, s));

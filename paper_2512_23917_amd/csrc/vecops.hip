@@ -325,79 +325,72 @@ hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* 
   return multiaxpy_launch(V, nv, c, sign, w, n, nullptr, s);
 }
 
-// Fused sweep: w += sign * sum_q c_q v_q, then d_q = <v_q, w> of the updated w
-// (block partials in the multidot layout).  The loads of v_q serve both.
+// Fused sweep of one Lanczos step: w -= alpha v_{NV-1} + beta v_{NV-2} (the
+// beta term for NV >= 2; alpha = *palpha, on the device), then
+// d_q = <v_q, w> of the updated w for q < NV (block partials in the multidot
+// layout).  Only the two recurrence vectors are held across the update; the
+// others are streamed once for their dot.
 template <int NV>
-__global__ __launch_bounds__(256) void axpy_dot_kernel(const cd* V, int nv, const double* c, double sign, cd* w,
-                                                       long long n, double* partial) {
-  __shared__ double scr[NV], sci[NV];
+__global__ __launch_bounds__(256) void three_term_dot_kernel(const cd* V, const double* palpha, double beta, cd* w,
+                                                             long long n, double* partial) {
   __shared__ double sh[4][2 * NV];
-  if (threadIdx.x < NV) {
-    scr[threadIdx.x] = threadIdx.x < nv ? sign * c[2 * threadIdx.x] : 0.0;
-    sci[threadIdx.x] = threadIdx.x < nv ? sign * c[2 * threadIdx.x + 1] : 0.0;
-  }
-  __syncthreads();
+  const double alpha = *palpha;
   double accr[NV], acci[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-    cd v[NV];
     cd y = w[i];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      if (q < nv) {
-        v[q] = V[(long long)q * n + i];
-        y.x += scr[q] * v[q].x - sci[q] * v[q].y;
-        y.y += scr[q] * v[q].y + sci[q] * v[q].x;
-      }
+    const cd vj = V[(long long)(NV - 1) * n + i];
+    y.x -= alpha * vj.x;
+    y.y -= alpha * vj.y;
+    cd vp{0.0, 0.0};
+    if constexpr (NV >= 2) {
+      vp = V[(long long)(NV - 2) * n + i];
+      y.x -= beta * vp.x;
+      y.y -= beta * vp.y;
     }
     w[i] = y;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      if (q < nv) {
-        accr[q] += v[q].x * y.x + v[q].y * y.y;
-        acci[q] += v[q].x * y.y - v[q].y * y.x;
-      }
+      const cd v = q == NV - 1 ? vj : (q == NV - 2 ? vp : V[(long long)q * n + i]);
+      accr[q] += v.x * y.x + v.y * y.y;
+      acci[q] += v.x * y.y - v.y * y.x;
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    if (q < nv) {
-      const double r = wave_sum64(accr[q]), im = wave_sum64(acci[q]);
-      if (lane == 0) { sh[wv][2 * q] = r; sh[wv][2 * q + 1] = im; }
-    }
+    const double r = wave_sum64(accr[q]), im = wave_sum64(acci[q]);
+    if (lane == 0) { sh[wv][2 * q] = r; sh[wv][2 * q + 1] = im; }
   }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < 2 * nv) {
+  if (t < 2 * NV) {
     const double vv = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
     partial[((long long)blockIdx.x * MD_MAXV + t / 2) * 2 + (t & 1)] = vv;
   }
 }
 
-typedef void (*AdLaunch)(unsigned, hipStream_t, const cd*, int, const double*, double, cd*, long long, double*);
+typedef void (*TtLaunch)(unsigned, hipStream_t, const cd*, const double*, double, cd*, long long, double*);
 template <int NV>
-void ad_launch(unsigned g, hipStream_t s, const cd* V, int nv, const double* c, double sign, cd* w, long long n,
+void tt_launch(unsigned g, hipStream_t s, const cd* V, const double* alpha, double beta, cd* w, long long n,
                double* partial) {
-  hipLaunchKernelGGL(axpy_dot_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, partial);
+  hipLaunchKernelGGL(three_term_dot_kernel<NV>, dim3(g), dim3(256), 0, s, V, alpha, beta, w, n, partial);
 }
 template <int... I>
-constexpr std::array<AdLaunch, sizeof...(I)> ad_make(std::integer_sequence<int, I...>) {
-  return {&ad_launch<I + 1>...};
+constexpr std::array<TtLaunch, sizeof...(I)> tt_make(std::integer_sequence<int, I...>) {
+  return {&tt_launch<I + 1>...};
 }
-static const std::array<AdLaunch, MD_MAXV>& ad_table() {
-  static const auto t = ad_make(std::make_integer_sequence<int, MD_MAXV>{});
+static const std::array<TtLaunch, MD_MAXV>& tt_table() {
+  static const auto t = tt_make(std::make_integer_sequence<int, MD_MAXV>{});
   return t;
 }
 
-hipError_t axpy_multidot(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                         double* partial, double* out, hipStream_t s) {
+hipError_t three_term_multidot(const void* V, int nv, const double* alpha, double beta, void* w, long long n,
+                               double* partial, double* out, hipStream_t s) {
   if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
-  const cd* Vc = (const cd*)V;
-  cd* wc = (cd*)w;
-  ad_table()[nv - 1](g, s, Vc, nv, c, sign, wc, n, partial);
+  tt_table()[nv - 1](g, s, (const cd*)V, alpha, beta, (cd*)w, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
@@ -549,6 +542,22 @@ hipError_t zero_fill(void* p, size_t bytes, hipStream_t s) {
   const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(2048, (nwords + 255) / 256));
   hipLaunchKernelGGL(zero_fill_kernel, dim3(g), dim3(256), 0, s, static_cast<unsigned int*>(p), nwords,
                      static_cast<unsigned char*>(p) + nwords * 4, ntail);
+  return hipGetLastError();
+}
+
+__global__ void zero_fill_rows_kernel(unsigned char* p, long long words, long long stride) {
+  unsigned int* q = reinterpret_cast<unsigned int*>(p + blockIdx.y * stride);
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < words; i += (long long)gridDim.x * 256) q[i] = 0u;
+}
+
+hipError_t zero_fill_rows(void* p, size_t bytes, size_t stride, int count, hipStream_t s) {
+  if (bytes == 0 || count <= 0) return hipSuccess;
+  if (reinterpret_cast<uintptr_t>(p) % 4 != 0 || bytes % 4 != 0 || stride % 4 != 0 || bytes > stride)
+    return hipErrorInvalidValue;
+  const long long words = (long long)(bytes / 4);
+  const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(256, (words + 255) / 256));
+  hipLaunchKernelGGL(zero_fill_rows_kernel, dim3(g, count), dim3(256), 0, s, static_cast<unsigned char*>(p), words,
+                     (long long)stride);
   return hipGetLastError();
 }
 

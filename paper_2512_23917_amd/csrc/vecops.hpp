@@ -21,10 +21,12 @@ constexpr int MULTIDOT_PARTIAL_DOUBLES = 1024 * 32 * 2;
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
                     hipStream_t s);
 hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s);
-// multiaxpy fused with the multidot of the updated w: out[2q], out[2q+1] =
-// <v_q, w_new> for q < nv (partial: MULTIDOT_PARTIAL_DOUBLES doubles)
-hipError_t axpy_multidot(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                         double* partial, double* out, hipStream_t s);
+// Lanczos recurrence fused with the multidot of its result:
+// w -= alpha v_{nv-1} + beta v_{nv-2} (alpha: one device double; beta
+// ignored for nv = 1), then out[2q], out[2q+1] = <v_q, w> for q < nv
+// (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
+hipError_t three_term_multidot(const void* V, int nv, const double* alpha, double beta, void* w, long long n,
+                               double* partial, double* out, hipStream_t s);
 // multiaxpy, then out[0] = ||w||^2 (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
                            double* partial, double* out, hipStream_t s);
@@ -35,6 +37,9 @@ hipError_t triu_mask(int dt, void* R, long long ld, long long sR, int k, const d
                      int batch, hipStream_t s);
 // Zero `bytes` bytes at p (4-byte aligned) with a kernel, usable under graph capture.
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t s);
+// Zero the first `bytes` of each of `count` regions `stride` bytes apart
+// (4-byte aligned sizes).
+hipError_t zero_fill_rows(void* p, size_t bytes, size_t stride, int count, hipStream_t s);
 hipError_t reverse_columns(int dt, void* U, long long ld, int rows, int k, hipStream_t s);
 
 }  // namespace tci
