@@ -85,6 +85,7 @@ __device__ inline cd bsum(cd v, double* sh) {
 // Every tile of the lower triangle is read once per column.
 // ---------------------------------------------------------------------------
 constexpr int TT = 64;
+static_assert(TRIDIAG_BAND >= TT, "the reduction reads whole diagonal tiles");
 
 template <typename T, int NB>
 struct TriWs {
@@ -111,7 +112,7 @@ struct TriWs {
 // chunk, so that the reflector set-up and the final reduction are paid once
 // per chunk.  The row sums of a chunk starting at tile cA go to P[cA][rows];
 // the column sums of an off-diagonal tile (R, C) go to P[R][columns of C].
-constexpr int CH = 8;
+constexpr int CH = 16;
 
 __host__ __device__ inline int tri_chunks(int nact) {
   int k = 0;
@@ -564,6 +565,7 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
                              ws + TriWs<T, NB>::cat2(n) + (size_t)t * es, n, G + ((long)t * a.ldg + t) * es, a.ldg);
       g.sA = a.sws / (long long)es; g.sB = a.sws / (long long)es; g.sC = a.sG;
       g.alpha_re = -1.0; g.beta_re = 1.0; g.batch = batch;
+      g.lower_band = TRIDIAG_BAND;
       hipError_t err = gemm(EigT<T>::dtype, PREC_FP64, g, s);
       if (err != hipSuccess) return err;
     }

@@ -5,9 +5,12 @@
 namespace tci {
 
 constexpr int TRIDIAG_NB = 32;
+// The reduction reads G only at entries with col - row < TRIDIAG_BAND (the
+// lower triangle and the 64 x 64 diagonal tiles); producers may skip the rest.
+constexpr int TRIDIAG_BAND = 64;
 
 // Layout per problem (row-major unless stated), problems strided by s*:
-//   G    n x n, ld ldg      the Hermitian matrix (full storage); overwritten
+//   G    n x n, ld ldg      the Hermitian matrix; read (and overwritten) only at col - row < TRIDIAG_BAND
 //   Vt   n x n, ld n        Vt[c * n + r] = reflector c at row r (0 for r <= c, 1 at r = c+1)
 //   Wp   n x NB, ld NB      panel W of the blocked reduction
 //   y    n                  Hermitian matrix-vector product

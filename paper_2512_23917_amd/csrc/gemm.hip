@@ -155,7 +155,7 @@ __device__ inline void problem_dims(const GemmArgs& a, int b, int& M, int& N, in
 // row (l/16) + 4r, column l%16 of the block.
 // ---------------------------------------------------------------------------
 template <typename T, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
   constexpr bool CPLX = Elem<T>::cplx;
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -169,6 +169,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
   problem_dims(a, b, M, N, K);
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
+  if (a.lower_band > 0 && n0 - (m0 + BM - 1) >= a.lower_band) return;
 
   const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
   const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
@@ -222,8 +223,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
   const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
   const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
   const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+  // one 16-row block row at a time: all of its C loads are issued before
+  // any store, so their latencies overlap (short-K updates are bound by them)
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int i = 0; i < FI; ++i) {
+    double c_re[FJ][4], c_im[FJ][4];
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
+        const int col = n0 + wn * WN + j * 16 + lr;
+        c_re[j][r] = 0.0;
+        c_im[j][r] = 0.0;
+        if (!beta0 && row < M && col < N) ld(C + (long)row * a.ldc + col, c_re[j][r], c_im[j][r]);
+      }
 #pragma unroll
     for (int j = 0; j < FJ; ++j)
 #pragma unroll
@@ -239,16 +253,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs a) {
           vr *= sc; vi *= sc;
           double outr = a.alpha_re * vr - a.alpha_im * vi;
           double outi = a.alpha_re * vi + a.alpha_im * vr;
-          T* p = C + (long)row * a.ldc + col;
           if (!beta0) {
-            double cr, ci;
-            ld(p, cr, ci);
-            outr += a.beta_re * cr - a.beta_im * ci;
-            outi += a.beta_re * ci + a.beta_im * cr;
+            outr += a.beta_re * c_re[j][r] - a.beta_im * c_im[j][r];
+            outi += a.beta_re * c_im[j][r] + a.beta_im * c_re[j][r];
           }
-          st(p, outr, outi);
+          st(C + (long)row * a.ldc + col, outr, outi);
         }
       }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -270,6 +282,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs a) {
   problem_dims(a, b, M, N, K);
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
+  if (a.lower_band > 0 && n0 - (m0 + BM - 1) >= a.lower_band) return;
   const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
   const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
   T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
@@ -376,6 +389,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs a) {
   problem_dims(a, b, M, N, K);
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
+  if (a.lower_band > 0 && n0 - (m0 + BM - 1) >= a.lower_band) return;
   const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
   const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
   T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
@@ -538,6 +552,15 @@ hipError_t gemm(int dtype, int prec, const GemmArgs& a, hipStream_t s) {
   // real one; split-BF16x3 executes three bf16 products per multiply-add
   const bool cplx = dtype == C64 || dtype == C128;
   double flops = (cplx ? 8.0 : 2.0) * a.m * (double)a.n * a.k * a.batch;
+  if (a.lower_band > 0 && !a.dims) {
+    // only the output tiles the kernel computes (FP64 tiles: 128 x 64 complex, 128 x 128 real)
+    const int bm = 128, bn = cplx ? 64 : 128;
+    double cells = 0.0;
+    for (int m0 = 0; m0 < a.m; m0 += bm)
+      for (int n0 = 0; n0 < a.n; n0 += bn)
+        if (n0 - (m0 + bm - 1) < a.lower_band) cells += (double)std::min(bm, a.m - m0) * std::min(bn, a.n - n0);
+    flops *= cells / ((double)a.m * a.n);
+  }
   if ((dtype == C64 || dtype == F32) && prec == PREC_BF16X3) flops *= 3.0;
   const char* cls = dtype == C128 ? "c128_fp64" : dtype == F64 ? "f64_fp64"
                   : prec == PREC_BF16X3 ? (dtype == C64 ? "c64_bf16x3" : "f32_bf16x3")

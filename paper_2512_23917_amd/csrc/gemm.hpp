@@ -19,6 +19,10 @@ struct GemmArgs {
   const double* rs; long long s_rs;
   const double* cs; long long s_cs;
   int batch;
+  // > 0: only entries with col - row < lower_band are needed;
+  // output tiles whose every entry has col - row >= lower_band are skipped
+  // and left unchanged (Hermitian results read from the lower triangle).
+  int lower_band;
 };
 
 inline GemmArgs gemm_args(int m, int n, int k, int opA, int opB, const void* A, long long lda,

@@ -107,6 +107,7 @@ tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const vo
     GemmArgs g = st.left ? gemm_args(ng, ng, n, OP_N, OP_C, theta, n, theta, n, Gm, ng)
                          : gemm_args(ng, ng, m, OP_C, OP_N, theta, n, theta, n, Gm, ng);
     g.sA = smn; g.sB = smn; g.sC = sG; g.batch = nb;
+    g.lower_band = TRIDIAG_BAND;   // the reduction reads the lower triangle and the diagonal tiles
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   // tridiagonal reduction
