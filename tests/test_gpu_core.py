@@ -193,6 +193,22 @@ def test_eigh_matches_oracle(T, ctx):
     assert isometry_err(vv) < 1e-12
 
 
+def test_eigh_degenerate_clusters(T, ctx):
+    """Eigenvalues of multiplicity 20: inverse iteration returns nearly
+    parallel vectors inside each cluster, so the orthonormalisation takes
+    full Cholesky-QR passes before its first-order finish."""
+    g = np.random.default_rng(25)
+    q, _ = np.linalg.qr(cg(g, (60, 60)))
+    lam = np.concatenate([np.full(20, 1.0), np.full(20, 2.0), np.linspace(3.0, 4.0, 20)])
+    h = (q * lam) @ q.conj().T
+    h = 0.5 * (h + h.conj().T)
+    w, v = T.eigh(ctx, up(T, ctx, h, T.C128))
+    assert np.abs(w.numpy() - np.sort(lam)).max() < 1e-12 * 4.0
+    vv = v.numpy()
+    assert isometry_err(vv) < 1e-12
+    assert rel_fro(vv @ np.diag(w.numpy()) @ vv.conj().T, h) < 1e-12
+
+
 # ------------------------------------------------------------------ two-site update
 @pytest.mark.parametrize("direction", [0, 1])
 @pytest.mark.parametrize("chi", [8, 32, 45])
