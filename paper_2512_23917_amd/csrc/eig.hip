@@ -165,10 +165,36 @@ __device__ inline void reflector(T alpha, double xn2, double& beta, T& tau, T& s
   }
 }
 
+// Sum of one value per thread over a 256-thread block (wave shuffles, then
+// the four wave sums through LDS); every thread receives the total.
+template <typename T>
+__device__ inline T block_sum256(T v, T* sh4) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return add(add(sh4[0], sh4[1]), add(sh4[2], sh4[3]));
+}
+
+// Sum over the four thread groups part = tid >> 6 that share a row
+// (tid & 63): the result is valid in part 0.
+template <typename T>
+__device__ inline T parts_sum(T v, T* sh256) {
+  __syncthreads();
+  sh256[threadIdx.x] = v;
+  __syncthreads();
+  T r = v;
+  if (threadIdx.x < 64) r = add(add(sh256[threadIdx.x], sh256[threadIdx.x + 64]),
+                                add(sh256[threadIdx.x + 128], sh256[threadIdx.x + 192]));
+  return r;
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int icol, int ifin, int j0) {
   __shared__ T s_t1[NB], s_t2[NB], s_vrow[NB], s_wrow[NB];
   __shared__ T s_alpha, s_wi;
+  __shared__ T s_red[256];
+  __shared__ T s_sh4[4];
   __shared__ double red[256];
   __shared__ int s_last;
   const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
@@ -211,27 +237,17 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     // w for this thread's row (4 threads share a row: each sums a quarter)
     T acc = EigT<T>::zero();
     if (rv) {
+#pragma unroll 4
       for (int t = tb0 + part; t < nbt; t += 4)
         if (tri_slot_used(t, r, tb0)) acc = add(acc, P[(long)t * n + r]);
+#pragma unroll 4
       for (int q = part; q < pp; q += 4) {
         acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], s_t1[q]));
         acc = sub(acc, mulr(W[(long)r * NB + q], s_t2[q]));
       }
     }
-    // combine the 4 parts through LDS (complex as two doubles)
-    double* rr = red;
-    __syncthreads();
-    rr[tid] = re(acc);
-    __syncthreads();
-    double sre = 0.0, sim = 0.0;
-    if (part == 0) sre = rr[tid] + rr[tid + 64] + rr[tid + 128] + rr[tid + 192];
-    __syncthreads();
-    rr[tid] = im(acc);
-    __syncthreads();
-    if (part == 0) sim = rr[tid] + rr[tid + 64] + rr[tid + 128] + rr[tid + 192];
+    const T yy = parts_sum(acc, s_red);
     if (part == 0 && rv) {
-      T yy;
-      if constexpr (sizeof(T) == 16) yy = cd{sre, sim}; else yy = sre;
       const T w = add(mulr(taup, yy), mulr(alpha, vfin[r]));
       W[(long)r * NB + pp] = w;
     }
@@ -261,52 +277,38 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
       acc = sub(acc, mulr(V[(long)(j0 + tid) * n + i], s_t1[tid]));
       acc = sub(acc, mulr(W[(long)i * NB + tid], s_t2[tid]));
     }
-    __syncthreads();
-    red[tid] = re(acc);
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
-    const double sr = red[0];
-    __syncthreads();
-    red[tid] = im(acc);
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
+    const T yy = block_sum256(acc, s_sh4);
     if (tid == 0) {
       const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ifin];
-      T yy;
-      if constexpr (sizeof(T) == 16) yy = cd{sr, red[0]}; else yy = sr;
       s_wi = add(mulr(taup, yy), mulr(s_alpha, V[(long)ifin * n + i]));
       s_wrow[pp] = s_wi;
     }
   }
   __syncthreads();
   double xn2 = 0.0;
-  if (part == 0 && rv) {
-    T acc = G[(long)r * ldg + i];
-    for (int q = 0; q < p; ++q) {
-      acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], cj(s_wrow[q])));
-      acc = sub(acc, mulr(W[(long)r * NB + q], cj(s_vrow[q])));
+  {
+    // the four groups of a row share the p panel terms
+    T acc = (part == 0 && rv) ? G[(long)r * ldg + i] : EigT<T>::zero();
+    if (rv) {
+#pragma unroll 4
+      for (int q = part; q < p; q += 4) {
+        acc = sub(acc, mulr(V[(long)(j0 + q) * n + r], cj(s_wrow[q])));
+        acc = sub(acc, mulr(W[(long)r * NB + q], cj(s_vrow[q])));
+      }
     }
-    G[(long)r * ldg + i] = acc;
-    if (r >= i + 1) xv[r] = acc;
-    if (r >= i + 2) xn2 = nrm2(acc);
-    if (r == i) a.d[b * a.sde + i] = re(acc);
+    acc = parts_sum(acc, s_red);
+    if (part == 0 && rv) {
+      G[(long)r * ldg + i] = acc;
+      if (r >= i + 1) xv[r] = acc;
+      if (r >= i + 2) xn2 = nrm2(acc);
+      if (r == i) a.d[b * a.sde + i] = re(acc);
+    }
   }
   // ||x||^2 partial of this block, then the last block reduces all partials
-  red[tid] = xn2;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
+  const double xsum = block_sum256(xn2, red);
   if (i + 1 >= n) return;
   if (tid == 0) {
-    pa[blockIdx.x] = red[0];
+    pa[blockIdx.x] = xsum;
     __threadfence();
     const int ticket = atomicAdd(&cnt[0], 1);
     s_last = (ticket == (int)gridDim.x - 1);
@@ -317,14 +319,9 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     __threadfence();
     double tot = 0.0;
     for (int k = tid; k < (int)gridDim.x; k += 256) tot += pa[k];
-    red[tid] = tot;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
+    tot = block_sum256(tot, red);
     if (tid == 0) {
-      fa[0] = red[0];
+      fa[0] = tot;
       cnt[0] = 0;
     }
   }
