@@ -336,7 +336,8 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   static_assert(2 * NB == TT, "t1/t2 thread mapping assumes 2 NB == TT");
   __shared__ int s_last;
   __shared__ T s_scal;
-  const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
+  const int b = blockIdx.x, n = a.n, tid = threadIdx.x;
+  const int wg = (int)gridDim.y - 1 - (int)blockIdx.y, nwg = (int)gridDim.y;   // chunk: largest bands first
   const int p = i - j0;
   char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
   const T* xv = reinterpret_cast<const T*>(ws + TriWs<T, NB>::xv(n));
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
   // chunk -> (band R, first tile cA, last tile cB)
   const int b0 = (i + 1) / TT;
-  int k = blockIdx.x, R = b0;
+  int k = wg, R = b0;
   for (;;) {
     const int nch = (R - b0 + CH) / CH;
     if (k < nch) break;
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
     T tv, sc;
     reflector(xv[i + 1], fa[0], beta, tv, sc);
     s_scal = sc;
-    if (blockIdx.x == 0) {
+    if (wg == 0) {
       a.e[b * a.sde + i] = beta;
       reinterpret_cast<T*>(a.tau)[b * a.stau + i] = tv;
     }
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
     const int rr = R * TT + tid;
     if (rr < n) V[(long)i * n + rr] = s_vR[tid];
   }
-  if (blockIdx.x == 0)
+  if (wg == 0)
     for (int rr = tid; rr < b0 * TT; rr += 256) V[(long)i * n + rr] = EigT<T>::zero();
 
   const int cl = tid & 63, rg = tid >> 6;
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   qo = wsum(qo);
   if (cl == 0) s_q[rg] = add(add(qd, qo), cj(qo));
   __syncthreads();
-  T* mypc = pc + (long)blockIdx.x * (1 + 2 * NB);
+  T* mypc = pc + (long)wg * (1 + 2 * NB);
   if (tid == 0) mypc[0] = add(add(s_q[0], s_q[1]), add(s_q[2], s_q[3]));
   if (tid < 2 * NB)
     mypc[1 + tid] = has_diag ? add(add(s_tt[0][tid], s_tt[1][tid]), add(s_tt[2][tid], s_tt[3][tid]))
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   if (tid == 0) {
     __threadfence();
     const int ticket = atomicAdd(&cnt[1], 1);
-    s_last = (ticket == (int)gridDim.x - 1);
+    s_last = (ticket == nwg - 1);
   }
   __syncthreads();
   if (s_last) {
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
     const int g = tid >> 2, j = tid & 3;
     for (int o = g; o < 1 + 2 * NB; o += 64) {
       T acc = EigT<T>::zero();
-      for (int kk = j; kk < (int)gridDim.x; kk += 4) acc = add(acc, pc[(long)kk * (1 + 2 * NB) + o]);
+      for (int kk = j; kk < nwg; kk += 4) acc = add(acc, pc[(long)kk * (1 + 2 * NB) + o]);
       acc = quad_sum(acc);
       if (j == 0) fc[o] = acc;
     }
@@ -541,7 +542,7 @@ static hipError_t tridiag_impl(const TriArgs& a, int batch, hipStream_t s) {
         const int nact = nbt - (i + 1) / TT;
         // algorithmic bytes: the lower triangle of the trailing matrix read once
         ProfScope ps(s, 0.5 * (double)(n - i - 1) * (n - i) * sizeof(T) * batch, "hemv");
-        hipLaunchKernelGGL((tri_colC_kernel<T, NB>), dim3(tri_chunks(nact), batch), dim3(256), 0, s, a, i, j0);
+        hipLaunchKernelGGL((tri_colC_kernel<T, NB>), dim3(batch, tri_chunks(nact)), dim3(256), 0, s, a, i, j0);
       }
     }
     const int t = j0 + pe;
