@@ -200,7 +200,11 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   TCI_TRY(norm2(th, n0));
   n0 = std::sqrt(n0);
   if (!(n0 > 0.0) || !std::isfinite(n0)) TCI_RET(TCI_ERR_NUMERIC, "starting vector has zero or non-finite norm");
-  TCI_CHECK_HIP(scale_copy(th, 1.0 / n0, 0.0, basis, N, s));
+  // complex64 operands: the complex64 copy of each new basis vector is made in
+  // the same sweep that writes it, and the widening of H v fused with alpha
+  const bool c64 = dt == C64;
+  if (c64) TCI_CHECK_HIP(scale_copy_dual(th, 1.0 / n0, basis, xin, N, s));
+  else TCI_CHECK_HIP(scale_copy(th, 1.0 / n0, 0.0, basis, N, s));
   std::vector<double> alpha, beta;
   double tmax = 0.0;
   for (int j = 0; j < n_matvec; ++j) {
@@ -208,13 +212,17 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     // w = H v_j (in the operands' dtype / precision)
     const void* xv = vj;
     if (dt != C128) {
-      TCI_CHECK_HIP(convert(C128, vj, dt, xin, N, s));
+      if (!c64) TCI_CHECK_HIP(convert(C128, vj, dt, xin, N, s));
       xv = xin;
     }
     TCI_TRY(heff_apply(ctx, p, xv, dt == C128 ? (void*)w : yout));
-    if (dt != C128) TCI_CHECK_HIP(convert(dt, yout, C128, w, N, s));
     // alpha_j = Re <v_j, w> (coef[0], read by the recurrence sweep on the device)
-    TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
+    if (c64) {
+      TCI_CHECK_HIP(widen_multidot_c64(yout, vj, w, N, part, coef, s));
+    } else {
+      if (dt != C128) TCI_CHECK_HIP(convert(dt, yout, C128, w, N, s));
+      TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
+    }
     if (j == n_matvec - 1) {   // the last residual enters neither T nor psi
       double hc[2];
       TCI_CHECK_HIP(hipMemcpyAsync(hc, coef, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -265,7 +273,8 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     tmax = std::max(tmax, b);
     if (b <= 1e-13 * tmax) break;
     beta.push_back(b);
-    TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, basis + (size_t)N * (j + 1), N, s));
+    if (c64) TCI_CHECK_HIP(scale_copy_dual(w, 1.0 / b, basis + (size_t)N * (j + 1), xin, N, s));
+    else TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, basis + (size_t)N * (j + 1), N, s));
   }
   const int m = (int)alpha.size();
   // lowest eigenpair of T = tridiag(alpha, beta): top eigenpair of -T on the device

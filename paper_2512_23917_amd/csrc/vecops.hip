@@ -248,6 +248,53 @@ hipError_t multidot(const void* V, int nv, const void* w, long long n, double* p
   return hipGetLastError();
 }
 
+// w = y (complex64 widened to complex128) and d = <v, w> in one sweep (block
+// partials in the multidot layout, q = 0).
+__global__ __launch_bounds__(256) void widen_dot_kernel(const cf* y, const cd* v, cd* w, long long n,
+                                                       double* partial) {
+  __shared__ double sh[4][2];
+  double ar = 0.0, ai = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cf yv = y[i];
+    const cd x{(double)yv.x, (double)yv.y};
+    w[i] = x;
+    const cd vv = v[i];
+    ar += vv.x * x.x + vv.y * x.y;
+    ai += vv.x * x.y - vv.y * x.x;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  ar = wave_sum64(ar);
+  ai = wave_sum64(ai);
+  if (lane == 0) { sh[wv][0] = ar; sh[wv][1] = ai; }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2) partial[(long long)blockIdx.x * MD_MAXV * 2 + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+hipError_t widen_multidot_c64(const void* y, const void* v, void* w, long long n, double* partial, double* out,
+                              hipStream_t s) {
+  const unsigned g = md_grid(n);
+  hipLaunchKernelGGL(widen_dot_kernel, dim3(g), dim3(256), 0, s, (const cf*)y, (const cd*)v, (cd*)w, n, partial);
+  hipLaunchKernelGGL(multidot_final_kernel, dim3(1), dim3(256), 0, s, partial, (int)g, 1, out);
+  return hipGetLastError();
+}
+
+// v = x * sr (complex128) and its complex64 copy in one sweep
+__global__ void scale_copy_dual_kernel(const cd* x, double sr, cd* v, cf* v32, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cd a = x[i];
+    const cd r{sr * a.x, sr * a.y};
+    v[i] = r;
+    v32[i] = cf{(float)r.x, (float)r.y};
+  }
+}
+
+hipError_t scale_copy_dual(const void* x, double sr, void* v, void* v32, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_copy_dual_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, sr, (cd*)v, (cf*)v32,
+                     n);
+  return hipGetLastError();
+}
+
 // w += sign * sum_q c_q v_q; with nrm_part, block b also stores its part of ||w||^2.
 template <int NV>
 __global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, const double* c, double sign, cd* w,

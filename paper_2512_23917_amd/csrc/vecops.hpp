@@ -31,6 +31,12 @@ hipError_t three_term_multidot(const void* V, int nv, const double* alpha, doubl
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
                            double* partial, double* out, hipStream_t s);
 hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s);
+// w (complex128) = y (complex64), then out[0], out[1] = <v, w> (partial:
+// MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
+hipError_t widen_multidot_c64(const void* y, const void* v, void* w, long long n, double* partial, double* out,
+                              hipStream_t s);
+// v = sr * x (complex128) and v32 = v rounded to complex64
+hipError_t scale_copy_dual(const void* x, double sr, void* v, void* v32, long long n, hipStream_t s);
 hipError_t scale_inplace(int dt, void* x, long long n, double sr, double si, hipStream_t s);
 hipError_t mpo_pair(int dt, const void* W1, const void* W2, void* W12, int wd, int d, hipStream_t s);
 hipError_t triu_mask(int dt, void* R, long long ld, long long sR, int k, const double* mask, long long smask,
