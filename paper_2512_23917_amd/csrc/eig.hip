@@ -70,19 +70,22 @@ __device__ inline cd bsum(cd v, double* sh) {
 //
 //  colA (row blocks of TT rows over [row0, n)):
 //    finish w_ip (ip = i-1): with t1 = W^H v, t2 = V^H v and yv = v^H A22 v
-//      (reduced by the previous colC),  alpha = -|tau|^2/2 (yv - t1^H t2 - t2^H t1),
+//      (summed here from the chunk partials of the previous colC),  alpha = -|tau|^2/2 (yv - t1^H t2 - t2^H t1),
 //      w(r) = tau (y(r) - V(r,:) t1 - W(r,:) t2) + alpha v(r),  y(r) = sum_t P[t][r];
 //    update column i: a(r,i) -= V(r,:) conj(W(i,:)) + W(r,:) conj(V(i,:));
-//    d_i = Re a(i,i); partial ||a(i+2:n,i)||^2 reduced by the last workgroup.
+//    d_i = Re a(i,i); one partial of ||a(i+2:n,i)||^2 per workgroup.
 //  colC (lower-triangle tiles TT x TT of the trailing matrix, CH tiles of a
 //    block row per workgroup):
 //    reflector of a(i+1:n,i): beta = -sign(Re a) ||.||, tau = (beta - a)/beta,
 //    v = [1, x / (a - beta)];  the chunk of tiles (R, cA..cB) adds
 //    sum_C A_RC v_C to P[cA][R rows], and each tile with C < R adds A_RC^H v_R
 //    to P[R][C rows]; partial quadratic form v^H A v and, with the diagonal
-//    tile, t1 = W^H v and t2 = V^H v over its rows; the last workgroup
-//    reduces the partials.
-// Every tile of the lower triangle is read once per column.
+//    tile, t1 = W^H v and t2 = V^H v over its rows, one partial per chunk.
+// Every tile of the lower triangle is read once per column.  Partials are
+// summed by the kernel that consumes them (colC sums colA's norm partials,
+// colA the chunk partials of colC): the kernel boundary makes them visible,
+// and no workgroup waits on a device-scope fence, which on this chip writes
+// back the L2 of its XCD.
 // ---------------------------------------------------------------------------
 constexpr int TT = 64;
 static_assert(TRIDIAG_BAND >= TT, "the reduction reads whole diagonal tiles");
@@ -94,12 +97,9 @@ struct TriWs {
   __host__ __device__ static size_t P(int n) { return align(sizeof(T) * (size_t)n); }
   __host__ __device__ static size_t pa(int n) { return P(n) + align(sizeof(T) * (size_t)nbt(n) * n); }
   __host__ __device__ static size_t pc(int n) { return pa(n) + align(sizeof(double) * (size_t)nbt(n)); }
-  __host__ __device__ static size_t fa(int n) { return pc(n) + align(sizeof(T) * (size_t)ntile(n) * (1 + 2 * NB)); }
-  __host__ __device__ static size_t fc(int n) { return fa(n) + 256; }
-  __host__ __device__ static size_t cnt(int n) { return fc(n) + align(sizeof(T) * (1 + 2 * NB)); }
   // [V_panel; W^T] and [W^T; V_panel], 2 NB rows of n each: operands of the
   // fused rank-2NB trailing update
-  __host__ __device__ static size_t cat1(int n) { return cnt(n) + 256; }
+  __host__ __device__ static size_t cat1(int n) { return pc(n) + align(sizeof(T) * (size_t)ntile(n) * (1 + 2 * NB)); }
   __host__ __device__ static size_t cat2(int n) { return cat1(n) + align(sizeof(T) * (size_t)2 * NB * n); }
   __host__ __device__ static size_t bytes(int n) { return cat2(n) + align(sizeof(T) * (size_t)2 * NB * n); }
   __host__ __device__ static int nbt(int n) { return (n + TT - 1) / TT; }
@@ -193,18 +193,16 @@ template <typename T, int NB>
 __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int icol, int ifin, int j0) {
   __shared__ T s_t1[NB], s_t2[NB], s_vrow[NB], s_wrow[NB];
   __shared__ T s_alpha, s_wi;
+  __shared__ T s_fc[1 + 2 * NB];
   __shared__ T s_red[256];
   __shared__ T s_sh4[4];
   __shared__ double red[256];
-  __shared__ int s_last;
   const int b = blockIdx.y, n = a.n, tid = threadIdx.x;
   char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
   T* xv = reinterpret_cast<T*>(ws + TriWs<T, NB>::xv(n));
   const T* P = reinterpret_cast<const T*>(ws + TriWs<T, NB>::P(n));
   double* pa = reinterpret_cast<double*>(ws + TriWs<T, NB>::pa(n));
-  double* fa = reinterpret_cast<double*>(ws + TriWs<T, NB>::fa(n));
-  const T* fc = reinterpret_cast<const T*>(ws + TriWs<T, NB>::fc(n));
-  int* cnt = reinterpret_cast<int*>(ws + TriWs<T, NB>::cnt(n));
+  const T* pc_in = reinterpret_cast<const T*>(ws + TriWs<T, NB>::pc(n));
   T* G = reinterpret_cast<T*>(a.G) + b * a.sG;
   T* V = reinterpret_cast<T*>(a.Vt) + b * a.sVt;
   T* W = reinterpret_cast<T*>(a.Wp) + b * a.sWp;
@@ -218,11 +216,20 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
   // ---- finish w_ifin (panel column pp = ifin - j0) on rows >= ifin + 1 = row0
   if (ifin >= 0) {
     const int pp = ifin - j0;
-    if (tid < pp) { s_t1[tid] = fc[1 + tid]; s_t2[tid] = fc[1 + NB + tid]; }
+    // reduce the chunk partials of the trailing matvec of column ifin (one
+    // value per thread; the kernel boundary made them visible)
+    if (tid < 1 + 2 * NB) {
+      const int nwg = tri_chunks(TriWs<T, NB>::nbt(n) - (ifin + 1) / TT);
+      T acc = EigT<T>::zero();
+      for (int k = 0; k < nwg; ++k) acc = add(acc, pc_in[(long)k * (1 + 2 * NB) + tid]);
+      s_fc[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < pp) { s_t1[tid] = s_fc[1 + tid]; s_t2[tid] = s_fc[1 + NB + tid]; }
     __syncthreads();
     if (tid == 0) {
       const T taup = reinterpret_cast<const T*>(a.tau)[b * a.stau + ifin];
-      T yv = fc[0];
+      T yv = s_fc[0];
       for (int q = 0; q < pp; ++q) {
         yv = sub(yv, mulr(cj(s_t1[q]), s_t2[q]));
         yv = sub(yv, mulr(cj(s_t2[q]), s_t1[q]));
@@ -304,27 +311,9 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
       if (r == i) a.d[b * a.sde + i] = re(acc);
     }
   }
-  // ||x||^2 partial of this block, then the last block reduces all partials
+  // ||x||^2 partial of this block (summed by the next kernel)
   const double xsum = block_sum256(xn2, red);
-  if (i + 1 >= n) return;
-  if (tid == 0) {
-    pa[blockIdx.x] = xsum;
-    __threadfence();
-    const int ticket = atomicAdd(&cnt[0], 1);
-    s_last = (ticket == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) {
-    // acquire: the partials of the other workgroups are visible after the fence
-    __threadfence();
-    double tot = 0.0;
-    for (int k = tid; k < (int)gridDim.x; k += 256) tot += pa[k];
-    tot = block_sum256(tot, red);
-    if (tid == 0) {
-      fa[0] = tot;
-      cnt[0] = 0;
-    }
-  }
+  if (tid == 0 && i + 1 < n) pa[blockIdx.x] = xsum;
 }
 
 template <typename T, int NB>
@@ -334,18 +323,15 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   __shared__ T s_colsum[2][4][TT];
   __shared__ T s_tt[4][2 * NB];
   static_assert(2 * NB == TT, "t1/t2 thread mapping assumes 2 NB == TT");
-  __shared__ int s_last;
   __shared__ T s_scal;
   const int b = blockIdx.x, n = a.n, tid = threadIdx.x;
-  const int wg = (int)gridDim.y - 1 - (int)blockIdx.y, nwg = (int)gridDim.y;   // chunk: largest bands first
+  const int wg = (int)gridDim.y - 1 - (int)blockIdx.y;   // chunk: largest bands first
   const int p = i - j0;
   char* ws = reinterpret_cast<char*>(a.ws) + b * a.sws;
   const T* xv = reinterpret_cast<const T*>(ws + TriWs<T, NB>::xv(n));
   T* P = reinterpret_cast<T*>(ws + TriWs<T, NB>::P(n));
   T* pc = reinterpret_cast<T*>(ws + TriWs<T, NB>::pc(n));
-  const double* fa = reinterpret_cast<const double*>(ws + TriWs<T, NB>::fa(n));
-  T* fc = reinterpret_cast<T*>(ws + TriWs<T, NB>::fc(n));
-  int* cnt = reinterpret_cast<int*>(ws + TriWs<T, NB>::cnt(n));
+  const double* pa = reinterpret_cast<const double*>(ws + TriWs<T, NB>::pa(n));
   const T* G = reinterpret_cast<const T*>(a.G) + b * a.sG;
   T* V = reinterpret_cast<T*>(a.Vt) + b * a.sVt;
   const T* W = reinterpret_cast<const T*>(a.Wp) + b * a.sWp;
@@ -360,11 +346,18 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   }
   const int cA = b0 + k * CH, cB = min(R, cA + CH - 1);
   const bool has_diag = (cB == R);
-  // reflector scalars (every workgroup computes them from the reduced norm)
+  // reflector scalars (every workgroup computes them from the norm partials of
+  // the column kernel, one per block of TT rows from row i)
+  double xn2 = 0.0;
+  if (tid < 64) {
+    const int na = (n - i + TT - 1) / TT;
+    for (int k = tid; k < na; k += 64) xn2 += pa[k];
+    xn2 = wave_sum(xn2);
+  }
   if (tid == 0) {
     double beta;
     T tv, sc;
-    reflector(xv[i + 1], fa[0], beta, tv, sc);
+    reflector(xv[i + 1], xn2, beta, tv, sc);
     s_scal = sc;
     if (wg == 0) {
       a.e[b * a.sde + i] = beta;
@@ -482,25 +475,6 @@ __global__ __launch_bounds__(256) void tri_colC_kernel(TriArgs a, int i, int j0)
   if (tid < 2 * NB)
     mypc[1 + tid] = has_diag ? add(add(s_tt[0][tid], s_tt[1][tid]), add(s_tt[2][tid], s_tt[3][tid]))
                              : EigT<T>::zero();
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const int ticket = atomicAdd(&cnt[1], 1);
-    s_last = (ticket == nwg - 1);
-  }
-  __syncthreads();
-  if (s_last) {
-    // acquire, then 4 lanes per output value sum interleaved chunk partials
-    __threadfence();
-    const int g = tid >> 2, j = tid & 3;
-    for (int o = g; o < 1 + 2 * NB; o += 64) {
-      T acc = EigT<T>::zero();
-      for (int kk = j; kk < nwg; kk += 4) acc = add(acc, pc[(long)kk * (1 + 2 * NB) + o]);
-      acc = quad_sum(acc);
-      if (j == 0) fc[o] = acc;
-    }
-    if (tid == 0) cnt[1] = 0;
-  }
 }
 
 // Operands of the trailing update G -= V W^H + W V^H = [V W] [W V]^H over
@@ -578,7 +552,7 @@ size_t tridiag_ws_bytes(int dtype, int n) {
 hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s) {
   if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
   if (a.sws < (long long)tridiag_ws_bytes(dtype, a.n)) return hipErrorInvalidValue;
-  // counters, partial sums and the reflector panel start at zero; the
+  // partial sums and the reflector panel start at zero; the
   // trailing-update operands are written before they are read
   const size_t zb = dtype == C128 ? TriWs<cd, TRIDIAG_NB>::cat1(a.n) : TriWs<double, TRIDIAG_NB>::cat1(a.n);
   if (a.sws % 4 != 0) return hipErrorInvalidValue;

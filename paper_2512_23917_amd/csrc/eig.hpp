@@ -23,7 +23,7 @@ struct TriArgs {
   void* Vt; long long sVt;
   void* Wp; long long sWp;
   void* y; long long sy;
-  void* ws; long long sws;   // per-problem workspace of tridiag_ws_bytes(n) bytes, counters zeroed
+  void* ws; long long sws;   // per-problem workspace of tridiag_ws_bytes(n) bytes
 };
 
 // Bytes of the per-problem workspace of the reduction (zero-fill before use).
