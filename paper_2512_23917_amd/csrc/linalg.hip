@@ -221,47 +221,71 @@ hipError_t trunc_select(const double* lam, long long slam, int kmax, const doubl
 // One wave per column.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(64) void gauge_cols_kernel(T* U, long long ldu, long long sU, int m,
-                                                        int ncol, const int* chi) {
-  const int j = blockIdx.x, b = blockIdx.y;
-  if (j >= ncol || (chi && j >= chi[b])) return;
+__device__ inline T scale_phase(T u, double pr, double pi_) {
+  if constexpr (sizeof(T) == 16) return T{u.x * pr - u.y * pi_, u.x * pi_ + u.y * pr};
+  else if constexpr (sizeof(T) == 8 && !std::is_same<T, double>::value)
+    return T{(float)(u.x * pr - u.y * pi_), (float)(u.x * pi_ + u.y * pr)};
+  else return (T)(u * pr);
+}
+
+// Phase of each column j < chi[b]: the entry of largest modulus (first row on
+// ties) is made real positive.  Workgroup (column block, b): lane -> column
+// (coalesced rows), four row groups combined through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void gauge_cols_kernel(T* U, long long ldu, long long sU, int m, int ncol,
+                                                         const int* chi) {
+  __shared__ double s_best[4][64];
+  __shared__ int s_idx[4][64];
+  __shared__ double s_ph[2][64];
+  const int b = blockIdx.y, lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const int nc = chi ? min(chi[b], ncol) : ncol;
+  const bool cj = j < nc;
   T* u = U + b * sU;
-  const int lane = threadIdx.x;
   double best = -1.0;
   int bi = 0;
-  for (int r = lane; r < m; r += 64) {
-    const double v = sqmod(u[(long long)r * ldu + j]);
-    if (v > best) { best = v; bi = r; }
+  if (cj)
+    for (int r = rg; r < m; r += 4) {
+      const double v = sqmod(u[(long long)r * ldu + j]);
+      if (v > best) { best = v; bi = r; }
+    }
+  s_best[rg][lane] = best;
+  s_idx[rg][lane] = bi;
+  __syncthreads();
+  if (rg == 0) {
+    for (int g = 1; g < 4; ++g) {
+      const double ob = s_best[g][lane];
+      const int oi = s_idx[g][lane];
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    double pr = 1.0, pi_ = 0.0;
+    if (cj) {
+      const T piv = u[(long long)bi * ldu + j];
+      if constexpr (sizeof(T) == 16 || (sizeof(T) == 8 && !std::is_same<T, double>::value)) {
+        const double md = sqrt((double)piv.x * piv.x + (double)piv.y * piv.y);
+        if (md > 0.0) { pr = piv.x / md; pi_ = -piv.y / md; }
+      } else {
+        if (piv < 0) pr = -1.0;
+      }
+    }
+    s_ph[0][lane] = pr;
+    s_ph[1][lane] = pi_;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_xor(best, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
-  const T piv = u[(long long)bi * ldu + j];
-  if constexpr (sizeof(T) == 16) {
-    const double md = sqrt(piv.x * piv.x + piv.y * piv.y);
-    if (md == 0.0) return;
-    const cd ph{piv.x / md, -piv.y / md};
-    for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = u[(long long)r * ldu + j] * ph;
-  } else if constexpr (sizeof(T) == 8 && !std::is_same<T, double>::value) {
-    const double md = sqrt((double)piv.x * piv.x + (double)piv.y * piv.y);
-    if (md == 0.0) return;
-    const cf ph{(float)(piv.x / md), (float)(-piv.y / md)};
-    for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = u[(long long)r * ldu + j] * ph;
-  } else {
-    if (piv < 0) for (int r = lane; r < m; r += 64) u[(long long)r * ldu + j] = -u[(long long)r * ldu + j];
-  }
+  __syncthreads();
+  if (!cj) return;
+  const double pr = s_ph[0][lane], pi_ = s_ph[1][lane];
+  if (pr == 1.0 && pi_ == 0.0) return;
+  for (int r = rg; r < m; r += 4) u[(long long)r * ldu + j] = scale_phase(u[(long long)r * ldu + j], pr, pi_);
 }
 
 hipError_t gauge_columns(int dtype, void* U, long long ldu, long long sU, int m, int ncol,
                          const int* chi, int batch, hipStream_t s) {
-  dim3 grid(ncol, batch);
+  dim3 grid((ncol + 63) / 64, batch);
   switch (dtype) {
-    case C128: hipLaunchKernelGGL(gauge_cols_kernel<cd>, grid, dim3(64), 0, s, (cd*)U, ldu, sU, m, ncol, chi); break;
-    case F64: hipLaunchKernelGGL(gauge_cols_kernel<double>, grid, dim3(64), 0, s, (double*)U, ldu, sU, m, ncol, chi); break;
-    case C64: hipLaunchKernelGGL(gauge_cols_kernel<cf>, grid, dim3(64), 0, s, (cf*)U, ldu, sU, m, ncol, chi); break;
-    case F32: hipLaunchKernelGGL(gauge_cols_kernel<float>, grid, dim3(64), 0, s, (float*)U, ldu, sU, m, ncol, chi); break;
+    case C128: hipLaunchKernelGGL(gauge_cols_kernel<cd>, grid, dim3(256), 0, s, (cd*)U, ldu, sU, m, ncol, chi); break;
+    case F64: hipLaunchKernelGGL(gauge_cols_kernel<double>, grid, dim3(256), 0, s, (double*)U, ldu, sU, m, ncol, chi); break;
+    case C64: hipLaunchKernelGGL(gauge_cols_kernel<cf>, grid, dim3(256), 0, s, (cf*)U, ldu, sU, m, ncol, chi); break;
+    case F32: hipLaunchKernelGGL(gauge_cols_kernel<float>, grid, dim3(256), 0, s, (float*)U, ldu, sU, m, ncol, chi); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
