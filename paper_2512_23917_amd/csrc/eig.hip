@@ -587,16 +587,20 @@ __global__ void e2_kernel(const double* e, double* e2, long long sde, int n, int
   e2[b * sde + i] = v * v;
 }
 
-// Multisection: one wave per wanted eigenvalue; each round the 64 lanes
-// evaluate the Sturm count at 64 interior points of the current interval
-// [lo, hi] (count(lo) <= t < count(hi)), which shrinks it 65-fold.
-__global__ __launch_bounds__(256) void bisect_kernel(const double* d, const double* e, const double* e2,
-                                                     long long sde, int n, int kmax, double* lam,
-                                                     long long slam, int batch) {
+// Bisection, one lane per wanted eigenvalue (64 per wave): lane j halves its
+// own interval [lo, hi] (count(lo) <= t < count(hi), t the ascending index)
+// until it is at rounding level.  All lanes walk the same Sturm recurrence
+// over i at their own shift, so the loop is uniform and d, e^2 are read at
+// the same address by every lane.  One evaluation per step and eigenvalue
+// keeps the arithmetic 10x below a 64-point multisection per eigenvalue; the
+// many independent lanes hide the latency of the division chain.
+__global__ __launch_bounds__(64) void bisect_kernel(const double* d, const double* e, const double* e2,
+                                                    long long sde, int n, int kmax, double* lam, long long slam,
+                                                    int batch) {
   const int b = blockIdx.y;
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= kmax || b >= batch) return;  // whole waves leave together
+  const int lane = threadIdx.x;
+  const int j = blockIdx.x * 64 + lane;
+  if (b >= batch) return;
   const double* db = d + b * sde;
   const double* eb = e + b * sde;
   const double* e2b = e2 + b * sde;
@@ -616,21 +620,18 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* d, const doub
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) * 64.0;
   lo -= 4.0 * 2.220446049250313e-16 * scale + pivmin;
   hi += 4.0 * 2.220446049250313e-16 * scale + pivmin;
-  const int t = n - 1 - j;  // ascending index of the wanted eigenvalue
-  for (int it = 0; it < 64; ++it) {
-    if (hi - lo <= 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
-    const bool below = (x > lo && x < hi) ? sturm_count(db, e2b, n, x, pivmin) <= t : (x <= lo);
-    const unsigned long long m = __ballot(below);
-    // first lane whose point has more than t eigenvalues below it
-    const int k = (~m == 0ull) ? 64 : __ffsll((long long)~m) - 1;
-    const double xl = __shfl(x, k > 0 ? k - 1 : 0), xh = __shfl(x, k < 64 ? k : 63);
-    const double nlo = k > 0 ? xl : lo, nhi = k < 64 ? xh : hi;
-    if (nlo == lo && nhi == hi) break;
-    lo = nlo;
-    hi = nhi;
+  const int t = n - 1 - min(j, kmax - 1);  // ascending index of this lane's eigenvalue
+  for (int it = 0; it < 128; ++it) {
+    const bool done = hi - lo <= 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin;
+    if (__ballot(!done) == 0ull) break;
+    const double x = 0.5 * (lo + hi);
+    const bool below = sturm_count(db, e2b, n, x, pivmin) <= t;
+    if (!done && x > lo && x < hi) {
+      if (below) lo = x;
+      else hi = x;
+    }
   }
-  if (lane == 0) lam[b * slam + j] = 0.5 * (lo + hi);
+  if (j < kmax) lam[b * slam + j] = 0.5 * (lo + hi);
 }
 
 hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, long long sde, int n,
@@ -638,8 +639,8 @@ hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, lon
   if (kmax <= 0 || batch <= 0) return hipSuccess;
   const long tot = (long)batch * n;
   hipLaunchKernelGGL(e2_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, e, e2, sde, n, batch);
-  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 3) / 4, batch), dim3(256), 0, s, d, e, e2, sde, n,
-                     kmax, lam, slam, batch);
+  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 63) / 64, batch), dim3(64), 0, s, d, e, e2, sde, n, kmax, lam,
+                     slam, batch);
   return hipGetLastError();
 }
 
@@ -663,6 +664,7 @@ __device__ inline double invit_solve(double* z, long ld, int j, int n, const dou
                                      const double* du2, const double* dl, double pre) {
   // forward: b <- L^-1 P b, writing the intermediate into z
   double bi = z[j] * pre;
+  #pragma unroll 8
   for (int i = 0; i < n - 1; ++i) {
     const double bn = z[(long)(i + 1) * ld + j] * pre;
     const double s = dl[(long)i * ld + j];
@@ -678,6 +680,7 @@ __device__ inline double invit_solve(double* z, long ld, int j, int n, const dou
   z[(long)(n - 1) * ld + j] = bi;
   // backward: U x = b
   double x1 = 0.0, x2 = 0.0, amax = 0.0;
+  #pragma unroll 8
   for (int i = n - 1; i >= 0; --i) {
     const double x = (z[(long)i * ld + j] - du[(long)i * ld + j] * x1 - du2[(long)i * ld + j] * x2) /
                      du1[(long)i * ld + j];
@@ -718,6 +721,7 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   // the rows were interchanged (|multiplier| <= 1 in both cases).
   double a_i = db[0] - lamj;       // current diagonal entry of the active row i
   double c_i = (n > 1) ? eb[0] : 0.0;  // super-diagonal of active row
+  #pragma unroll 8
   for (int i = 0; i < n - 1; ++i) {
     const double sub = eb[i];                 // entry (i+1, i)
     const double a_n = db[i + 1] - lamj;      // entry (i+1, i+1)
@@ -863,15 +867,18 @@ hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n,
 // ---------------------------------------------------------------------------
 constexpr int BT_GB = 128;
 
+// One workgroup per (problem, group): block (b, grp) reads S of the group at
+// Sg + b * sF + grp * BT_GB^2 and writes T at Tg + b * sF + grp * BT_GB^2.
 template <typename T>
-__global__ __launch_bounds__(BT_GB) void larft_group_kernel(TriArgs a, const void* Sg, long long sS, int j0, int g,
-                                                            void* Tg, long long sT) {
+__global__ __launch_bounds__(BT_GB) void larft_group_kernel(TriArgs a, const void* Sg, void* Tg, long long sF) {
   __shared__ T Tp[BT_GB * (BT_GB + 1) / 2];
   __shared__ T scol[BT_GB];
-  const int b = blockIdx.x, q = threadIdx.x;
-  const T* S = reinterpret_cast<const T*>(Sg) + b * sS;   // g x g, ld BT_GB
+  const int b = blockIdx.x, grp = blockIdx.y, q = threadIdx.x;
+  const int j0 = grp * BT_GB, g = min(BT_GB, a.n - 1 - j0);
+  const long long off = b * sF + (long long)grp * BT_GB * BT_GB;
+  const T* S = reinterpret_cast<const T*>(Sg) + off;   // g x g, ld BT_GB
   const T* tau = reinterpret_cast<const T*>(a.tau) + b * a.stau;
-  T* Tout = reinterpret_cast<T*>(Tg) + b * sT;             // BT_GB x BT_GB, ld BT_GB
+  T* Tout = reinterpret_cast<T*>(Tg) + off;             // BT_GB x BT_GB, ld BT_GB
   for (int i = 0; i < g; ++i) {
     if (q < i) scol[q] = S[(long)q * BT_GB + i];
     __syncthreads();
@@ -905,23 +912,22 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
   char* V = reinterpret_cast<char*>(a.Vt);
   char* Uc = reinterpret_cast<char*>(U);
   char* Tc = reinterpret_cast<char*>(Tf);
-  char* Sc = Tc + (size_t)ng * BT_GB * BT_GB * es;   // per-problem S scratch after the T factors
+  char* Sc = Tc + (size_t)ng * BT_GB * BT_GB * es;   // per-problem S of every group after the T factors
   char* W1 = reinterpret_cast<char*>(work);
   char* W2 = W1 + (size_t)batch * BT_GB * kmax * es;
   const long long sW = (long long)BT_GB * kmax;
   hipError_t err = hipSuccess;
-  // T factor of every group
+  // S = V_g^H V_g of every group (over rows j0+1 .. n-1; V_g = columns of Vt
+  // rows j0 ..), then the T factors of all groups in one launch
   for (int grp = 0; grp < ng; ++grp) {
     const int j0 = grp * BT_GB, g = min(BT_GB, n - 1 - j0), rows = n - j0 - 1;
-    // S = V_g^H V_g over rows j0+1 .. n-1 (V_g = columns of Vt rows j0 ..)
     GemmArgs gs = gemm_args(g, g, rows, OP_R, OP_T, V + ((long)j0 * n + j0 + 1) * es, n,
-                            V + ((long)j0 * n + j0 + 1) * es, n, Sc, BT_GB);
+                            V + ((long)j0 * n + j0 + 1) * es, n, Sc + (size_t)grp * BT_GB * BT_GB * es, BT_GB);
     gs.sA = a.sVt; gs.sB = a.sVt; gs.sC = sTf; gs.batch = batch;
     err = gemm(dt, PREC_FP64, gs, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(larft_group_kernel<T>, dim3(batch), dim3(BT_GB), 0, s, a, (const void*)Sc, sTf, j0, g,
-                       (void*)(Tc + (size_t)grp * BT_GB * BT_GB * es), sTf);
   }
+  hipLaunchKernelGGL(larft_group_kernel<T>, dim3(batch, ng), dim3(BT_GB), 0, s, a, (const void*)Sc, (void*)Tc, sTf);
   // groups applied last to first: U <- U - V_g (T_g (V_g^H U))
   for (int grp = ng - 1; grp >= 0; --grp) {
     const int j0 = grp * BT_GB, g = min(BT_GB, n - 1 - j0), rows = n - j0 - 1;
@@ -945,7 +951,7 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
   return hipGetLastError();
 }
 
-size_t tridiag_backtransform_tf_elems(int n) { return (size_t)(std::max(1, bt_groups(n)) + 1) * BT_GB * BT_GB; }
+size_t tridiag_backtransform_tf_elems(int n) { return (size_t)2 * std::max(1, bt_groups(n)) * BT_GB * BT_GB; }
 size_t tridiag_backtransform_work_elems(int kmax) { return (size_t)2 * BT_GB * kmax; }
 
 hipError_t tridiag_backtransform(int dtype, const TriArgs& a, void* Tf, long long sTf, void* U,
