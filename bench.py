@@ -9,8 +9,9 @@ Workload (dense two-site update, chi = 1024, d = 2): per update
 A step is one pass over a batch of `--updates` (default 64) independent
 updates with seeded synthetic inputs already resident in HBM.  Two paths run
 on the same inputs: plain FP64 (complex128 everywhere) and mixed (complex64
-storage, split-BF16x3 contractions with FP32 accumulation, FP64 Krylov
-vectors, FP64 Gram / orthogonalisation / eigensolve); the learned sketch
+storage, split-BF16x3 contractions with FP32 accumulation, complex64-stored
+Krylov vectors with FP64 recurrence and orthogonalisation arithmetic, FP64
+Gram / orthogonalisation / eigensolve); the learned sketch
 predicts the sketch rank of the randomized SVD and falls back to the plain
 SVD when the discarded weight misses eps (always here: the cap binds).
 
@@ -371,7 +372,8 @@ def main():
                    "fallback_rate": float(np.mean([i.used_fallback for i in infos_m])),
                    "mean_sketch_rank": float(np.mean([i.sketch_rank for i in infos_m]))},
         "precision_detail": "c64 storage; split-BF16x3 MFMA contractions with FP32 accumulation; "
-                            "FP64 Krylov basis, Gram, orthogonalisation and eigensolve",
+                            "Krylov basis stored in c64 with FP64 recurrence and orthogonalisation "
+                            "arithmetic; FP64 Gram, orthogonalisation and eigensolve of the SVD",
         "energy_parity_mixed_vs_plain": None if en_p is None else
             float(max(abs(a - b) / abs(b) for a, b in zip(en_m, en_p))),
         "roofline": roof,

@@ -343,14 +343,15 @@ tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_ten
                            tci_tensor R, tci_tensor x, tci_tensor y);
 
 /* Lowest Ritz pair after at most n_matvec matvecs of Lanczos with full
- * re-orthogonalisation (FP64 basis and scalars): after the three-term
- * recurrence, one classical Gram-Schmidt pass against the whole basis, and
- * a second pass when the first removed more than half of the residual's
- * norm.  Started at theta_inout,
- * which receives the normalised Ritz vector (phase: <theta_in, psi> real
- * positive).  *energy receives the Ritz value.  For F32/C64 operands the
- * matvecs run in the context's mixed precision and the Krylov vectors are
- * kept in FP64.  Synchronous. */
+ * re-orthogonalisation (FP64 scalars and vector arithmetic): after the
+ * three-term recurrence, one classical Gram-Schmidt pass against the whole
+ * basis, and a second pass when the first removed more than half of the
+ * residual's norm.  Started at theta_inout, which receives the normalised
+ * Ritz vector (phase: <theta_in, psi> real positive).  *energy receives the
+ * Ritz value.  For F32/C64 operands the matvecs run in the context's mixed
+ * precision.  The Krylov vectors are stored in FP64 (complex128), except for
+ * C64 operands, where they are stored in complex64 (the operand precision of
+ * their matvec) and combined in FP64.  Synchronous. */
 tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
                               tci_tensor R, tci_tensor theta_inout, int n_matvec, double* energy);
 

@@ -179,8 +179,14 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   const int dt = L->dtype;
   const long long N = (long long)chil * d * d * chir;
   const size_t es = elem_bytes(dt);
-  // Krylov basis and scalars in complex128
-  cd* basis = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N * (n_matvec + 1)));
+  // Krylov scalars, the working vector and all arithmetic in complex128.  The
+  // basis is stored in complex128, or in complex64 for complex64 operands:
+  // there each stored vector is the operand of its matvec, and the sweeps
+  // over the basis move half the bytes.
+  const bool c64 = dt == C64;
+  const int vdt = c64 ? C64 : C128;
+  const size_t ves = c64 ? sizeof(cf) : sizeof(cd);
+  char* basis = static_cast<char*>(ctx->arena.get(ves * (size_t)N * (n_matvec + 1)));
   cd* w = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N));
   cd* th = static_cast<cd*>(ctx->arena.get(sizeof(cd) * (size_t)N));
   void* xin = ctx->arena.get(es * (size_t)N);
@@ -200,25 +206,22 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   TCI_TRY(norm2(th, n0));
   n0 = std::sqrt(n0);
   if (!(n0 > 0.0) || !std::isfinite(n0)) TCI_RET(TCI_ERR_NUMERIC, "starting vector has zero or non-finite norm");
-  // complex64 operands: the complex64 copy of each new basis vector is made in
-  // the same sweep that writes it, and the widening of H v fused with alpha
-  const bool c64 = dt == C64;
-  if (c64) TCI_CHECK_HIP(scale_copy_dual(th, 1.0 / n0, basis, xin, N, s));
+  if (c64) TCI_CHECK_HIP(scale_to_c64(th, 1.0 / n0, 0.0, basis, N, s));
   else TCI_CHECK_HIP(scale_copy(th, 1.0 / n0, 0.0, basis, N, s));
   std::vector<double> alpha, beta;
   double tmax = 0.0;
   for (int j = 0; j < n_matvec; ++j) {
-    cd* vj = basis + (size_t)N * j;
+    const void* vj = basis + ves * (size_t)N * j;
     // w = H v_j (in the operands' dtype / precision)
     const void* xv = vj;
-    if (dt != C128) {
-      if (!c64) TCI_CHECK_HIP(convert(C128, vj, dt, xin, N, s));
+    if (dt != C128 && !c64) {
+      TCI_CHECK_HIP(convert(C128, vj, dt, xin, N, s));
       xv = xin;
     }
     TCI_TRY(heff_apply(ctx, p, xv, dt == C128 ? (void*)w : yout));
     // alpha_j = Re <v_j, w> (coef[0], read by the recurrence sweep on the device)
     if (c64) {
-      TCI_CHECK_HIP(widen_multidot_c64(yout, vj, w, N, part, coef, s));
+      TCI_CHECK_HIP(widen_multidot_c64(yout, vj, w, N, part, coef, s, vdt));
     } else {
       if (dt != C128) TCI_CHECK_HIP(convert(dt, yout, C128, w, N, s));
       TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
@@ -239,15 +242,16 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     // Stewart, 1976, with ||w_before||^2 = ||w_after||^2 + ||c||^2); in exact
     // arithmetic the second pass subtracts zero.
     std::vector<double> c1(2 * (j + 1) + 1, 0.0), hc(2, 0.0);
-    const double vbytes = (double)sizeof(cd) * (double)N;   // one basis vector
+    // bytes of one stored basis vector and of the working vector
+    const double vbytes = (double)ves * (double)N, wbytes = (double)sizeof(cd) * (double)N;
     ProfTag tag("lanczos");
     {
-      ProfScope ps(s, vbytes * (j + 3), "sweep_dot");
-      TCI_CHECK_HIP(three_term_multidot(basis, j + 1, coef, j > 0 ? beta[j - 1] : 0.0, w, N, part, coef + 128, s));
+      ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "sweep_dot");
+      TCI_CHECK_HIP(three_term_multidot(basis, j + 1, coef, j > 0 ? beta[j - 1] : 0.0, w, N, part, coef + 128, s, vdt));
     }
     {
-      ProfScope ps(s, vbytes * (j + 3), "sweep_axpy");
-      TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 128 + 2 * (j + 1), s));
+      ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "sweep_axpy");
+      TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 128 + 2 * (j + 1), s, vdt));
     }
     TCI_CHECK_HIP(hipMemcpyAsync(hc.data(), coef, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
     TCI_CHECK_HIP(hipMemcpyAsync(c1.data(), coef + 128, sizeof(double) * c1.size(), hipMemcpyDeviceToHost, s));
@@ -259,12 +263,12 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     for (int q = 0; q < 2 * (j + 1); ++q) cn2 += c1[q] * c1[q];
     if (b2 < cn2) {
       {
-        ProfScope ps(s, vbytes * (j + 2), "reorth2_dot");
-        TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef + 256, s));
+        ProfScope ps(s, vbytes * (j + 1) + wbytes, "reorth2_dot");
+        TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef + 256, s, vdt));
       }
       {
-        ProfScope ps(s, vbytes * (j + 3), "reorth2_axpy");
-        TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s));
+        ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "reorth2_axpy");
+        TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s, vdt));
       }
       TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
       TCI_CHECK_HIP(hipStreamSynchronize(s));
@@ -273,8 +277,9 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     tmax = std::max(tmax, b);
     if (b <= 1e-13 * tmax) break;
     beta.push_back(b);
-    if (c64) TCI_CHECK_HIP(scale_copy_dual(w, 1.0 / b, basis + (size_t)N * (j + 1), xin, N, s));
-    else TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, basis + (size_t)N * (j + 1), N, s));
+    void* vnext = basis + ves * (size_t)N * (j + 1);
+    if (c64) TCI_CHECK_HIP(scale_to_c64(w, 1.0 / b, 0.0, vnext, N, s));
+    else TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, vnext, N, s));
   }
   const int m = (int)alpha.size();
   // lowest eigenpair of T = tridiag(alpha, beta): top eigenpair of -T on the device
@@ -303,7 +308,7 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   for (int i = 0; i < m; ++i) cy[2 * i] = hz[i];
   TCI_CHECK_HIP(hipMemsetAsync(w, 0, sizeof(cd) * (size_t)N, s));
   TCI_CHECK_HIP(hipMemcpyAsync(coef, cy.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, s));
-  TCI_CHECK_HIP(multiaxpy(basis, m, coef, 1.0, w, N, s));
+  TCI_CHECK_HIP(multiaxpy(basis, m, coef, 1.0, w, N, s, vdt));
   double pn2 = 0.0;
   TCI_TRY(norm2(w, pn2));
   const double pn = std::sqrt(pn2);
@@ -318,8 +323,12 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
     pr = ov[0] / om / pn;
     pi = -ov[1] / om / pn;
   }
-  TCI_CHECK_HIP(scale_copy(w, pr, pi, basis, N, s));
-  TCI_CHECK_HIP(convert(C128, basis, dt, theta->data, N, s));
+  if (c64) {
+    TCI_CHECK_HIP(scale_to_c64(w, pr, pi, theta->data, N, s));
+  } else {
+    TCI_CHECK_HIP(scale_copy(w, pr, pi, th, N, s));
+    TCI_CHECK_HIP(convert(C128, th, dt, theta->data, N, s));
+  }
   TCI_CHECK_HIP(hipStreamSynchronize(s));
   *energy = -hl;
   return TCI_OK;

@@ -162,9 +162,17 @@ __device__ inline double wave_sum64(double v) {
   return v;
 }
 
+// Basis vectors are complex128, or complex64 for the complex64 operands
+// (arithmetic in FP64 either way).
+__device__ inline cd ldv(const cd* p) { return *p; }
+__device__ inline cd ldv(const cf* p) {
+  const cf v = *p;
+  return cd{(double)v.x, (double)v.y};
+}
+
 // NV is a compile-time bound on nv so that the accumulators stay in registers.
-template <int NV>
-__global__ __launch_bounds__(256) void multidot_partial_kernel(const cd* V, int nv, const cd* w, long long n,
+template <int NV, typename VT>
+__global__ __launch_bounds__(256) void multidot_partial_kernel(const VT* V, int nv, const cd* w, long long n,
                                                                double* partial) {
   __shared__ double sh[4][2 * NV];
   double accr[NV], acci[NV];
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(256) void multidot_partial_kernel(const cd* V, int 
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       if (q < nv) {
-        const cd v = V[(long long)q * n + i];
+        const cd v = ldv(V + (long long)q * n + i);
         accr[q] += v.x * x.x + v.y * x.y;
         acci[q] += v.x * x.y - v.y * x.x;
       }
@@ -222,35 +230,38 @@ static unsigned md_grid(long long n) {
 
 // Launch tables with one instantiation per basis size (1..MD_MAXV), so that
 // each kernel holds exactly the registers its basis needs.
-typedef void (*MdLaunch)(unsigned, hipStream_t, const cd*, int, const cd*, long long, double*);
-template <int NV>
-void md_launch(unsigned g, hipStream_t s, const cd* V, int nv, const cd* w, long long n, double* partial) {
-  hipLaunchKernelGGL(multidot_partial_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, w, n, partial);
+template <typename VT>
+using MdLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const cd*, long long, double*);
+template <int NV, typename VT>
+void md_launch(unsigned g, hipStream_t s, const VT* V, int nv, const cd* w, long long n, double* partial) {
+  hipLaunchKernelGGL((multidot_partial_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, w, n, partial);
 }
-template <int... I>
-constexpr std::array<MdLaunch, sizeof...(I)> md_make(std::integer_sequence<int, I...>) {
-  return {&md_launch<I + 1>...};
+template <typename VT, int... I>
+constexpr std::array<MdLaunch<VT>, sizeof...(I)> md_make(std::integer_sequence<int, I...>) {
+  return {&md_launch<I + 1, VT>...};
 }
-static const std::array<MdLaunch, MD_MAXV>& md_table() {
-  static const auto t = md_make(std::make_integer_sequence<int, MD_MAXV>{});
+template <typename VT>
+static const std::array<MdLaunch<VT>, MD_MAXV>& md_table() {
+  static const auto t = md_make<VT>(std::make_integer_sequence<int, MD_MAXV>{});
   return t;
 }
 
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
-                    hipStream_t s) {
+                    hipStream_t s, int vdt) {
   if (nv <= 0) return hipSuccess;
-  if (nv > MD_MAXV) return hipErrorInvalidValue;
+  if (nv > MD_MAXV || (vdt != C128 && vdt != C64)) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
-  const cd* Vc = (const cd*)V;
   const cd* wc = (const cd*)w;
-  md_table()[nv - 1](g, s, Vc, nv, wc, n, partial);
+  if (vdt == C64) md_table<cf>()[nv - 1](g, s, (const cf*)V, nv, wc, n, partial);
+  else md_table<cd>()[nv - 1](g, s, (const cd*)V, nv, wc, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
 
 // w = y (complex64 widened to complex128) and d = <v, w> in one sweep (block
 // partials in the multidot layout, q = 0).
-__global__ __launch_bounds__(256) void widen_dot_kernel(const cf* y, const cd* v, cd* w, long long n,
+template <typename VT>
+__global__ __launch_bounds__(256) void widen_dot_kernel(const cf* y, const VT* v, cd* w, long long n,
                                                        double* partial) {
   __shared__ double sh[4][2];
   double ar = 0.0, ai = 0.0;
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(256) void widen_dot_kernel(const cf* y, const cd* v
     const cf yv = y[i];
     const cd x{(double)yv.x, (double)yv.y};
     w[i] = x;
-    const cd vv = v[i];
+    const cd vv = ldv(v + i);
     ar += vv.x * x.x + vv.y * x.y;
     ai += vv.x * x.y - vv.y * x.x;
   }
@@ -272,32 +283,33 @@ __global__ __launch_bounds__(256) void widen_dot_kernel(const cf* y, const cd* v
 }
 
 hipError_t widen_multidot_c64(const void* y, const void* v, void* w, long long n, double* partial, double* out,
-                              hipStream_t s) {
+                              hipStream_t s, int vdt) {
   const unsigned g = md_grid(n);
-  hipLaunchKernelGGL(widen_dot_kernel, dim3(g), dim3(256), 0, s, (const cf*)y, (const cd*)v, (cd*)w, n, partial);
+  if (vdt == C64)
+    hipLaunchKernelGGL(widen_dot_kernel<cf>, dim3(g), dim3(256), 0, s, (const cf*)y, (const cf*)v, (cd*)w, n, partial);
+  else
+    hipLaunchKernelGGL(widen_dot_kernel<cd>, dim3(g), dim3(256), 0, s, (const cf*)y, (const cd*)v, (cd*)w, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(1), dim3(256), 0, s, partial, (int)g, 1, out);
   return hipGetLastError();
 }
 
-// v = x * sr (complex128) and its complex64 copy in one sweep
-__global__ void scale_copy_dual_kernel(const cd* x, double sr, cd* v, cf* v32, long long n) {
+// out (complex64) = x * (sr + i si) rounded
+__global__ void scale_to_c64_kernel(const cd* x, double sr, double si, cf* out, long long n) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
     const cd a = x[i];
-    const cd r{sr * a.x, sr * a.y};
-    v[i] = r;
-    v32[i] = cf{(float)r.x, (float)r.y};
+    out[i] = cf{(float)(sr * a.x - si * a.y), (float)(sr * a.y + si * a.x)};
   }
 }
 
-hipError_t scale_copy_dual(const void* x, double sr, void* v, void* v32, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(scale_copy_dual_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, sr, (cd*)v, (cf*)v32,
-                     n);
+hipError_t scale_to_c64(const void* x, double sr, double si, void* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_to_c64_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, sr, si, (cf*)out, n);
   return hipGetLastError();
 }
 
+
 // w += sign * sum_q c_q v_q; with nrm_part, block b also stores its part of ||w||^2.
-template <int NV>
-__global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, const double* c, double sign, cd* w,
+template <int NV, typename VT>
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const VT* V, int nv, const double* c, double sign, cd* w,
                                                         long long n, double* nrm_part) {
   __shared__ double sh[4];
   double cr[NV], ci[NV];
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* V, int nv, con
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       if (q < nv) {
-        const cd v = V[(long long)q * n + i];
+        const cd v = ldv(V + (long long)q * n + i);
         acc.x += cr[q] * v.x - ci[q] * v.y;
         acc.y += cr[q] * v.y + ci[q] * v.x;
       }
@@ -342,34 +354,38 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int 
   if (t == 0) out[0] = sh[0];
 }
 
-typedef void (*MaLaunch)(unsigned, hipStream_t, const cd*, int, const double*, double, cd*, long long, double*);
-template <int NV>
-void ma_launch(unsigned g, hipStream_t s, const cd* V, int nv, const double* c, double sign, cd* w, long long n,
+template <typename VT>
+using MaLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const double*, double, cd*, long long, double*);
+template <int NV, typename VT>
+void ma_launch(unsigned g, hipStream_t s, const VT* V, int nv, const double* c, double sign, cd* w, long long n,
                double* nrm_part) {
-  hipLaunchKernelGGL(multiaxpy_kernel<NV>, dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, nrm_part);
+  hipLaunchKernelGGL((multiaxpy_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, nrm_part);
 }
-template <int... I>
-constexpr std::array<MaLaunch, sizeof...(I)> ma_make(std::integer_sequence<int, I...>) {
-  return {&ma_launch<I + 1>...};
+template <typename VT, int... I>
+constexpr std::array<MaLaunch<VT>, sizeof...(I)> ma_make(std::integer_sequence<int, I...>) {
+  return {&ma_launch<I + 1, VT>...};
 }
-static const std::array<MaLaunch, MD_MAXV>& ma_table() {
-  static const auto t = ma_make(std::make_integer_sequence<int, MD_MAXV>{});
+template <typename VT>
+static const std::array<MaLaunch<VT>, MD_MAXV>& ma_table() {
+  static const auto t = ma_make<VT>(std::make_integer_sequence<int, MD_MAXV>{});
   return t;
 }
 
 static hipError_t multiaxpy_launch(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                                   double* nrm_part, hipStream_t s) {
+                                   double* nrm_part, hipStream_t s, int vdt) {
+  if (vdt != C128 && vdt != C64) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
-  const cd* Vc = (const cd*)V;
   cd* wc = (cd*)w;
-  ma_table()[nv - 1](g, s, Vc, nv, c, sign, wc, n, nrm_part);
+  if (vdt == C64) ma_table<cf>()[nv - 1](g, s, (const cf*)V, nv, c, sign, wc, n, nrm_part);
+  else ma_table<cd>()[nv - 1](g, s, (const cd*)V, nv, c, sign, wc, n, nrm_part);
   return hipGetLastError();
 }
 
-hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s) {
+hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s,
+                     int vdt) {
   if (nv <= 0) return hipSuccess;
   if (nv > MD_MAXV) return hipErrorInvalidValue;
-  return multiaxpy_launch(V, nv, c, sign, w, n, nullptr, s);
+  return multiaxpy_launch(V, nv, c, sign, w, n, nullptr, s, vdt);
 }
 
 // Fused sweep of one Lanczos step: w -= alpha v_{NV-1} + beta v_{NV-2} (the
@@ -377,8 +393,8 @@ hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* 
 // d_q = <v_q, w> of the updated w for q < NV (block partials in the multidot
 // layout).  Only the two recurrence vectors are held across the update; the
 // others are streamed once for their dot.
-template <int NV>
-__global__ __launch_bounds__(256) void three_term_dot_kernel(const cd* V, const double* palpha, double beta, cd* w,
+template <int NV, typename VT>
+__global__ __launch_bounds__(256) void three_term_dot_kernel(const VT* V, const double* palpha, double beta, cd* w,
                                                              long long n, double* partial) {
   __shared__ double sh[4][2 * NV];
   const double alpha = *palpha;
@@ -387,19 +403,19 @@ __global__ __launch_bounds__(256) void three_term_dot_kernel(const cd* V, const 
   for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
     cd y = w[i];
-    const cd vj = V[(long long)(NV - 1) * n + i];
+    const cd vj = ldv(V + (long long)(NV - 1) * n + i);
     y.x -= alpha * vj.x;
     y.y -= alpha * vj.y;
     cd vp{0.0, 0.0};
     if constexpr (NV >= 2) {
-      vp = V[(long long)(NV - 2) * n + i];
+      vp = ldv(V + (long long)(NV - 2) * n + i);
       y.x -= beta * vp.x;
       y.y -= beta * vp.y;
     }
     w[i] = y;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const cd v = q == NV - 1 ? vj : (q == NV - 2 ? vp : V[(long long)q * n + i]);
+      const cd v = q == NV - 1 ? vj : (q == NV - 2 ? vp : ldv(V + (long long)q * n + i));
       accr[q] += v.x * y.x + v.y * y.y;
       acci[q] += v.x * y.y - v.y * y.x;
     }
@@ -418,34 +434,37 @@ __global__ __launch_bounds__(256) void three_term_dot_kernel(const cd* V, const 
   }
 }
 
-typedef void (*TtLaunch)(unsigned, hipStream_t, const cd*, const double*, double, cd*, long long, double*);
-template <int NV>
-void tt_launch(unsigned g, hipStream_t s, const cd* V, const double* alpha, double beta, cd* w, long long n,
+template <typename VT>
+using TtLaunch = void (*)(unsigned, hipStream_t, const VT*, const double*, double, cd*, long long, double*);
+template <int NV, typename VT>
+void tt_launch(unsigned g, hipStream_t s, const VT* V, const double* alpha, double beta, cd* w, long long n,
                double* partial) {
-  hipLaunchKernelGGL(three_term_dot_kernel<NV>, dim3(g), dim3(256), 0, s, V, alpha, beta, w, n, partial);
+  hipLaunchKernelGGL((three_term_dot_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, alpha, beta, w, n, partial);
 }
-template <int... I>
-constexpr std::array<TtLaunch, sizeof...(I)> tt_make(std::integer_sequence<int, I...>) {
-  return {&tt_launch<I + 1>...};
+template <typename VT, int... I>
+constexpr std::array<TtLaunch<VT>, sizeof...(I)> tt_make(std::integer_sequence<int, I...>) {
+  return {&tt_launch<I + 1, VT>...};
 }
-static const std::array<TtLaunch, MD_MAXV>& tt_table() {
-  static const auto t = tt_make(std::make_integer_sequence<int, MD_MAXV>{});
+template <typename VT>
+static const std::array<TtLaunch<VT>, MD_MAXV>& tt_table() {
+  static const auto t = tt_make<VT>(std::make_integer_sequence<int, MD_MAXV>{});
   return t;
 }
 
 hipError_t three_term_multidot(const void* V, int nv, const double* alpha, double beta, void* w, long long n,
-                               double* partial, double* out, hipStream_t s) {
-  if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
+                               double* partial, double* out, hipStream_t s, int vdt) {
+  if (nv <= 0 || nv > MD_MAXV || (vdt != C128 && vdt != C64)) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
-  tt_table()[nv - 1](g, s, (const cd*)V, alpha, beta, (cd*)w, n, partial);
+  if (vdt == C64) tt_table<cf>()[nv - 1](g, s, (const cf*)V, alpha, beta, (cd*)w, n, partial);
+  else tt_table<cd>()[nv - 1](g, s, (const cd*)V, alpha, beta, (cd*)w, n, partial);
   hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
   return hipGetLastError();
 }
 
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                           double* partial, double* out, hipStream_t s) {
+                           double* partial, double* out, hipStream_t s, int vdt) {
   if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
-  hipError_t e = multiaxpy_launch(V, nv, c, sign, w, n, partial, s);
+  hipError_t e = multiaxpy_launch(V, nv, c, sign, w, n, partial, s, vdt);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, partial, (int)md_grid(n), out);
   return hipGetLastError();

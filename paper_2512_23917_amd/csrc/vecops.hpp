@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
+
 namespace tci {
 
 constexpr int LINCOMB_MAX = 16;
@@ -18,25 +20,29 @@ hipError_t linear_combine(int dt, const LinCombArgs& a, void* out, long long n, 
 hipError_t max_abs_diff(int dt, const void* a, const void* b, long long n, double* partial, int nparts,
                         hipStream_t s);
 constexpr int MULTIDOT_PARTIAL_DOUBLES = 1024 * 32 * 2;
+// V: nv basis vectors of length n, complex128 (vdt = C128) or complex64 (C64);
+// w and the arithmetic are complex128.
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
-                    hipStream_t s);
-hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s);
+                    hipStream_t s, int vdt = C128);
+hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s,
+                     int vdt = C128);
 // Lanczos recurrence fused with the multidot of its result:
 // w -= alpha v_{nv-1} + beta v_{nv-2} (alpha: one device double; beta
 // ignored for nv = 1), then out[2q], out[2q+1] = <v_q, w> for q < nv
 // (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
 hipError_t three_term_multidot(const void* V, int nv, const double* alpha, double beta, void* w, long long n,
-                               double* partial, double* out, hipStream_t s);
+                               double* partial, double* out, hipStream_t s, int vdt = C128);
 // multiaxpy, then out[0] = ||w||^2 (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                           double* partial, double* out, hipStream_t s);
+                           double* partial, double* out, hipStream_t s, int vdt = C128);
 hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s);
 // w (complex128) = y (complex64), then out[0], out[1] = <v, w> (partial:
 // MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
 hipError_t widen_multidot_c64(const void* y, const void* v, void* w, long long n, double* partial, double* out,
-                              hipStream_t s);
-// v = sr * x (complex128) and v32 = v rounded to complex64
-hipError_t scale_copy_dual(const void* x, double sr, void* v, void* v32, long long n, hipStream_t s);
+                              hipStream_t s, int vdt = C128);
+// out (complex64) = (sr + i si) x, x complex128
+hipError_t scale_to_c64(const void* x, double sr, double si, void* out, long long n, hipStream_t s);
+
 hipError_t scale_inplace(int dt, void* x, long long n, double sr, double si, hipStream_t s);
 hipError_t mpo_pair(int dt, const void* W1, const void* W2, void* W12, int wd, int d, hipStream_t s);
 hipError_t triu_mask(int dt, void* R, long long ld, long long sR, int k, const double* mask, long long smask,
