@@ -14,7 +14,9 @@ arrays, in the bond order of the input (row-major, bond 0 slowest):
     concatenate, stack        Spec, manipulation: concatenate, stack
     trace                     Spec, linear algebra: trace (partial trace)
     expm                      Spec, linear algebra: exp (matricised exponential)
+    inverse                   Spec, linear algebra: inverse (matricised)
     lq                        Spec, linear algebra: lq
+    to_cplx, real, imag       Spec, manipulation: to_cplx, real, imag
 """
 from __future__ import annotations
 
@@ -198,3 +200,51 @@ def lq(a, k_rows: int):
     l, q = lq_matrix(a.reshape(rows, cols))
     rho = l.shape[1]
     return l.reshape(tuple(rshape) + (rho,)), q.reshape((rho,) + tuple(cshape))
+
+
+def inverse(a, k_rows: int) -> np.ndarray:
+    """Spec, inverse: matricise (first k_rows bonds as rows), take the X with
+    A X = I (LAPACK's solve as the step), fold back to the input shape."""
+    a = np.asarray(a)
+    rows = int(np.prod(a.shape[:k_rows]))
+    cols = int(np.prod(a.shape[k_rows:]))
+    if rows != cols:
+        raise ValueError("inverse needs a square matricisation")
+    m = a.reshape(rows, cols).astype(np.complex128)
+    return np.linalg.solve(m, np.eye(rows, dtype=np.complex128)).reshape(a.shape)
+
+
+def to_cplx(a) -> np.ndarray:
+    """Spec, to_cplx: real elements embedded with zero imaginary part."""
+    a = np.asarray(a)
+    out = np.zeros(a.shape, dtype=np.complex64 if a.dtype in (np.float32, np.complex64) else np.complex128)
+    out.real = a.real
+    if np.iscomplexobj(a):
+        out.imag = a.imag
+    return out
+
+
+def real(a) -> np.ndarray:
+    """Spec, real: elementwise real part (a copy for real input)."""
+    a = np.asarray(a)
+    return a.real.copy()
+
+
+def imag(a) -> np.ndarray:
+    """Spec, imag: elementwise imaginary part (zeros for real input)."""
+    a = np.asarray(a)
+    return a.imag.copy() if np.iscomplexobj(a) else np.zeros_like(a)
+
+
+def diag(a) -> np.ndarray:
+    """Spec, diag: a vector becomes the diagonal matrix; a matrix gives its
+    main diagonal of length min(d0, d1)."""
+    a = np.asarray(a)
+    if a.ndim == 1:
+        out = np.zeros((a.shape[0], a.shape[0]), dtype=a.dtype)
+        for i in range(a.shape[0]):
+            out[i, i] = a[i]
+        return out
+    if a.ndim == 2:
+        return np.array([a[i, i] for i in range(min(a.shape))], dtype=a.dtype)
+    raise ValueError("diag needs a first- or second-order tensor")

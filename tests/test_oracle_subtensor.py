@@ -219,3 +219,66 @@ def test_lq_paper_shapes():
     ex = EX["lq_shapes"]
     l, q = st.lq(cg(70, ex["shape"]), ex["k_rows"])
     assert list(l.shape) == ex["l"] and list(q.shape) == ex["q"]
+
+
+# ---------------------------------------------------------------- inverse
+def test_inverse_paper_example_and_special_cases():
+    ex = EX["inverse_eye3"]
+    out = st.inverse(np.eye(ex["n"]), ex["k_rows"])
+    assert out[tuple(ex["coord"])] == ex["expected"] and np.array_equal(out, np.eye(3))
+    # 2 x 2 closed form
+    a, b, c, d = 2.0, -1.5, 0.5, 3.0
+    det = a * d - b * c
+    assert np.abs(st.inverse(np.array([[a, b], [c, d]]), 1) - np.array([[d, -b], [-c, a]]) / det).max() < 1e-15
+    # unitary: the inverse is the conjugate transpose
+    q, _ = np.linalg.qr(cg(80, (9, 9)))
+    assert np.abs(st.inverse(q, 1) - q.conj().T).max() < 1e-13
+
+
+def test_inverse_hilbert_integer_closed_form():
+    n = 6
+    h = np.array([[1.0 / (i + j + 1) for j in range(n)] for i in range(n)])
+    exact = np.zeros((n, n))
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            exact[i - 1, j - 1] = ((-1) ** (i + j) * (i + j - 1) * math.comb(n + i - 1, n - j)
+                                   * math.comb(n + j - 1, n - i) * math.comb(i + j - 2, i - 1) ** 2)
+    out = st.inverse(h, 1)
+    assert np.abs(out - exact).max() / np.abs(exact).max() < 1e-8   # cond(H_6) ~ 1.5e7
+
+
+def test_inverse_tensor_fold_and_errors():
+    a = cg(81, (2, 3, 6)) + 4 * np.eye(6).reshape(2, 3, 6)
+    out = st.inverse(a, 2)
+    assert out.shape == a.shape
+    assert np.abs(a.reshape(6, 6) @ out.reshape(6, 6) - np.eye(6)).max() < 1e-13
+    with pytest.raises(ValueError):
+        st.inverse(np.zeros((2, 3)), 1)
+
+
+# ---------------------------------------------------------------- to_cplx / real / imag
+def test_to_cplx_real_imag_paper_examples():
+    ex = EX["to_cplx_eye3"]
+    c = st.to_cplx(np.eye(ex["n"]))
+    assert c.dtype == np.complex128 and c[tuple(ex["coord"])] == complex(*ex["expected"])
+    ex = EX["real_imag"]
+    a = cg(90, ex["shape"])
+    el = a[tuple(ex["coord"])]
+    assert st.real(a)[tuple(ex["coord"])] == el.real and st.imag(a)[tuple(ex["coord"])] == el.imag
+    assert np.array_equal(st.real(a) + 1j * st.imag(a), a)
+    r = np.arange(6, dtype=np.float32).reshape(2, 3)
+    assert np.array_equal(st.real(r), r) and np.array_equal(st.imag(r), np.zeros((2, 3), np.float32))
+    assert st.to_cplx(r).dtype == np.complex64 and np.array_equal(st.to_cplx(r).real, r)
+    assert np.array_equal(st.to_cplx(a), a)
+
+
+def test_diag_paper_example_and_numpy():
+    e = np.eye(3)
+    d = st.diag(e)
+    assert d.ndim == 1 and np.array_equal(st.diag(d), e)
+    v = cg(91, (5,))
+    assert np.array_equal(st.diag(v), np.diag(v))
+    m = cg(92, (4, 7))
+    assert np.array_equal(st.diag(m), np.diagonal(m))
+    with pytest.raises(ValueError):
+        st.diag(np.zeros((2, 2, 2)))
