@@ -126,6 +126,18 @@ tci_status tci_zeros(tci_context ctx, tci_dtype dtype, int order, const int64_t*
 tci_status tci_wrap(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape,
                     void* dev_ptr, tci_tensor* out);
 
+/* Spec, construction: fill.  New owning tensor of the given shape with every
+ * element equal to *value (one host scalar of `dtype`).  Asynchronous on the
+ * context stream.  Errors as tci_allocate; TCI_ERR_INVALID_ARGUMENT for a
+ * NULL value. */
+tci_status tci_fill(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, const void* value,
+                    tci_tensor* out);
+
+/* Spec, construction: eye.  New owning n x n tensor (order 2) with ones on
+ * the main diagonal and zeros elsewhere.  Errors: TCI_ERR_INVALID_ARGUMENT
+ * (n < 0), TCI_ERR_DTYPE, TCI_ERR_OUT_OF_MEMORY. */
+tci_status tci_eye(tci_context ctx, tci_dtype dtype, int64_t n, tci_tensor* out);
+
 /* Deep copy into a new owning tensor. */
 tci_status tci_copy(tci_context ctx, tci_tensor in, tci_tensor* out);
 
@@ -174,6 +186,20 @@ tci_status tci_to_host(tci_context ctx, tci_tensor t, void* host, size_t bytes);
  * `dtype` (C128 <-> C64, F64 <-> F32, real -> complex). */
 tci_status tci_convert(tci_context ctx, tci_tensor in, tci_dtype dtype, tci_tensor* out);
 
+/* Spec, construction: save / load.  Back-end file format: 8 bytes
+ * "TCIMI355", int32 format version (1), int32 dtype, int32 order, int32 0,
+ * int64 shape[order], then the elements row-major in the host's
+ * little-endian byte order.  save copies the tensor to the host
+ * (synchronous); load returns a new owning tensor.  Errors:
+ * TCI_ERR_INVALID_ARGUMENT (file cannot be opened, written, or is not such
+ * a file, or is truncated). */
+tci_status tci_save(tci_context ctx, tci_tensor t, const char* path);
+tci_status tci_load(tci_context ctx, const char* path, tci_tensor* out);
+
+/* Spec, miscellaneous: show.  Print dtype, shape and every element with
+ * its coordinates to standard output (synchronous). */
+tci_status tci_show(tci_context ctx, tci_tensor t);
+
 /* ------------------------------------------------------------------ */
 /* Manipulation (Spec, manipulation: reshape, transpose, cplx_conj,      */
 /* scale; linear algebra: linear_combine)                               */
@@ -189,6 +215,20 @@ tci_status tci_reshape(tci_context ctx, tci_tensor in, int order, const int64_t*
  * is allowed (a temporary is used). */
 tci_status tci_transpose(tci_context ctx, tci_tensor in, const int32_t* perm, tci_tensor out);
 
+/* Spec, manipulation: diag.  A first-order input of length n gives the
+ * n x n matrix with it on the main diagonal and zeros elsewhere; a
+ * second-order input gives its main diagonal (length min(d0, d1)).  `out`
+ * may be `in`.  Errors: TCI_ERR_SHAPE (order not 1 or 2). */
+tci_status tci_diag(tci_context ctx, tci_tensor in, tci_tensor out);
+
+/* Spec, manipulation: to_cplx, real, imag.  `out` (an existing handle; may
+ * be `in`) receives, elementwise: to_cplx the complex embedding (F32 -> C64,
+ * F64 -> C128, a copy for complex types); real the real part (F32/F64; a
+ * copy for real types); imag the imaginary part (zeros for real types). */
+tci_status tci_to_cplx(tci_context ctx, tci_tensor in, tci_tensor out);
+tci_status tci_real(tci_context ctx, tci_tensor in, tci_tensor out);
+tci_status tci_imag(tci_context ctx, tci_tensor in, tci_tensor out);
+
 /* Elementwise complex conjugate (identity copy for real types). */
 tci_status tci_cplx_conj(tci_context ctx, tci_tensor in, tci_tensor out);
 
@@ -199,6 +239,64 @@ tci_status tci_scale(tci_context ctx, tci_tensor inout, const void* s);
  * all ones).  All inputs same shape and dtype; out may alias one input. */
 tci_status tci_linear_combine(tci_context ctx, int n, const tci_tensor* ins, const void* coefs,
                               tci_tensor out);
+
+/* Sub-tensors (Spec, manipulation: extract_sub, shrink, expand,
+ * replace_sub, concatenate, stack).  All are asynchronous on the context
+ * stream; `out` is an existing handle whose shape and dtype are set by the
+ * call (an owning handle is resized, a borrowed one must have room).
+ * Coordinates are element coordinates, bond 0 slowest (row-major). */
+
+/* out = in[first[0]:last[0], ..., first[r-1]:last[r-1]] (half-open ranges,
+ * one per bond, 0 <= first <= last <= dim).  out == in works in place.
+ * Errors: TCI_ERR_INVALID_ARGUMENT (range outside a bond, NULL). */
+tci_status tci_extract_sub(tci_context ctx, tci_tensor in, const int64_t* first, const int64_t* last,
+                           tci_tensor out);
+
+/* As tci_extract_sub for the n listed bonds bonds[i] (each at most once),
+ * cut to [first[i], last[i]); unlisted bonds keep their full range. */
+tci_status tci_shrink(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* first,
+                      const int64_t* last, tci_tensor out);
+
+/* Bond bonds[i] grows by increments[i] >= 0 (appended at the end); elements
+ * inside the old bounds keep their values, every other element is zero.
+ * out == in works in place (owning handles). */
+tci_status tci_expand(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* increments,
+                      tci_tensor out);
+
+/* out = in with the box of `sub` (same order and dtype) written so that its
+ * origin lands at coordinate begin[].  out == in works in place; out must
+ * not alias sub otherwise.  Errors: TCI_ERR_SHAPE (order/dtype),
+ * TCI_ERR_INVALID_ARGUMENT (sub does not fit at begin). */
+tci_status tci_replace_sub(tci_context ctx, tci_tensor in, tci_tensor sub, const int64_t* begin,
+                           tci_tensor out);
+
+/* The n >= 1 inputs (same order and dtype, equal dimensions on every bond
+ * but `bond`) follow one another along `bond`; the output dimension there is
+ * the sum of the input dimensions.  out must not alias an input. */
+tci_status tci_concatenate(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out);
+
+/* The n >= 1 inputs (identical shapes) along a new bond of dimension n
+ * inserted at position `bond` (0 <= bond <= order): out[.., k, ..] = ins[k].
+ * out must not alias an input.  Errors: TCI_ERR_UNSUPPORTED when the result
+ * order exceeds the maximum. */
+tci_status tci_stack(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out);
+
+/* Spec, linear algebra: trace.  Partial trace over npairs bond pairs
+ * (pairs[2p], pairs[2p+1]; equal dimensions, every bond in at most one
+ * pair): out[kept] = sum_t in[kept, t, t]; the kept bonds keep their order;
+ * all bonds paired gives order 0.  FP64 accumulation.  out == in works in
+ * place.  Errors: TCI_ERR_INVALID_ARGUMENT, TCI_ERR_SHAPE. */
+tci_status tci_trace(tci_context ctx, tci_tensor in, int npairs, const int32_t* pairs, tci_tensor out);
+
+/* Spec, linear algebra: exp.  Matricise with the first k_rows bonds as rows
+ * (rows must equal columns), take the matrix exponential, fold back to the
+ * input shape.  Scaling and squaring in FP64 for every dtype (F32/C64 are
+ * promoted and the result rounded back): A / 2^s with ||A / 2^s||_F <= 1/2,
+ * Taylor polynomial of degree 18 by Horner's rule, s squarings, the
+ * products as FP64 GEMMs on the matrix cores.  out == in works in place.
+ * Synchronous.  Errors:
+ * TCI_ERR_SHAPE (not square), TCI_ERR_NUMERIC (non-finite input). */
+tci_status tci_exp(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out);
 
 /* ------------------------------------------------------------------ */
 /* Reductions (Spec, linear algebra: norm, normalize)                   */
@@ -261,6 +359,22 @@ tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u
  * diagonal.  Cholesky-QR2 in FP64; a rank-deficient column gives a zero
  * column of q and a zero row of r.  Synchronous. */
 tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r);
+
+/* Spec, linear algebra: inverse.  Matricise with the first k_rows bonds as
+ * rows (rows must equal columns, at most 65536), invert, fold back to the
+ * input shape.  Gauss-Jordan elimination with partial pivoting on [A | I]
+ * in FP64 for every dtype (single types promoted, the result rounded back).
+ * out == in works in place.  Synchronous.  Errors: TCI_ERR_SHAPE (not
+ * square), TCI_ERR_NUMERIC (an exactly zero pivot column, i.e. singular, or
+ * non-finite entries), TCI_ERR_UNSUPPORTED (too large). */
+tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out);
+
+/* Spec, lq: thin LQ of the matricised tensor, l {d_0..d_{k-1}, rho},
+ * q {rho, d_k..}, rho = min(I, J); l lower triangular with a real
+ * non-negative diagonal, q with orthonormal rows.  Computed as the
+ * Cholesky-QR2 of the conjugate transpose.  Wide or square matrices only
+ * (I <= J; TCI_ERR_UNSUPPORTED otherwise).  Synchronous. */
+tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_tensor q);
 
 /* Spec, eigh: Hermitian matrix (order 2, square; only the values are read
  * as given, no symmetrisation) -> w (ascending, real FP64) and v (columns =

@@ -58,6 +58,20 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     return LIB
 
 
+def build_program(src: str, out: str) -> str:
+    """Compile a C++ program that includes tci/tci.h (HIP device code allowed)
+    and links this library, found at run time next to the package."""
+    root = os.path.dirname(HERE)
+    rpath = os.path.relpath(HERE, os.path.dirname(out))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-I", os.path.join(root, "include"), src,
+           "-o", out, "-L", HERE, "-ltci_mi355x", f"-Wl,-rpath,$ORIGIN/{rpath}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

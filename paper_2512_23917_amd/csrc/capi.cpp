@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -16,6 +17,7 @@
 #include "gemm.hpp"
 #include "linalg.hpp"
 #include "runtime.hpp"
+#include "subtensor.hpp"
 #include "tsvd.hpp"
 #include "vecops.hpp"
 
@@ -728,6 +730,487 @@ tci_status tci_contract_str(tci_context ctx, tci_tensor a, const char* la, tci_t
   for (int i = 0; i < nb; ++i) B[i] = (unsigned char)lb[i];
   for (int i = 0; i < nc; ++i) C[i] = (unsigned char)lc[i];
   return tci_contract(ctx, a, A, na, b, B, nb, c, C, nc);
+}
+
+
+// ---------------------------------------------------------------- sub-tensors
+}  // extern "C"
+
+namespace {
+
+void row_major_strides(int order, const int64_t* shape, long long* st) {
+  long long acc = 1;
+  for (int b = order - 1; b >= 0; --b) {
+    st[b] = acc;
+    acc *= shape[b];
+  }
+}
+
+// Source of an out-of-place operation: the input itself, or a copy of it in
+// the arena when the output handle is the input handle (its storage may be
+// reallocated by the output's shape change).
+tci_status stable_source(tci_context ctx, tci_tensor in, tci_tensor out, const void*& src) {
+  src = in->data;
+  if (out != in) return TCI_OK;
+  const size_t bytes = tbytes(in);
+  void* tmp = ctx->arena.get(std::max<size_t>(bytes, 16));
+  if (!tmp) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  if (bytes) TCI_CHECK_HIP(hipMemcpyAsync(tmp, in->data, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  src = tmp;
+  return TCI_OK;
+}
+
+// Copy the whole of src (shape sshape, order) into dst (shape dshape) at the
+// offsets off[] (same order).
+tci_status copy_box(tci_context ctx, int dt, const void* src, int order, const int64_t* sshape, void* dst,
+                    const int64_t* dshape, const int64_t* off) {
+  BoxCopy c{};
+  c.order = order;
+  long long ss[MAX_ORDER + 1], ds[MAX_ORDER + 1];
+  row_major_strides(order, sshape, ss);
+  row_major_strides(order, dshape, ds);
+  c.total = 1;
+  c.soff = 0;
+  c.doff = 0;
+  for (int b = 0; b < order; ++b) {
+    c.dims[b] = sshape[b];
+    c.sstride[b] = ss[b];
+    c.dstride[b] = ds[b];
+    c.doff += off[b] * ds[b];
+    c.total *= sshape[b];
+  }
+  if (order == 0) {   // scalar
+    c.order = 1;
+    c.dims[0] = 1;
+    c.sstride[0] = c.dstride[0] = 1;
+  }
+  TCI_CHECK_HIP(box_copy(elem_bytes(dt), src, dst, c, ctx->stream));
+  return TCI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tci_status tci_fill(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, const void* value,
+                    tci_tensor* out) {
+  if (!value) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null value");
+  TCI_TRY(make_tensor(ctx, dtype, order, shape, out, false));
+  double vr, vi;
+  host_scalar(dtype, value, vr, vi);
+  TCI_CHECK_HIP(fill_value(dtype, (*out)->data, tsize(*out), vr, vi, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_eye(tci_context ctx, tci_dtype dtype, int64_t n, tci_tensor* out) {
+  if (n < 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "negative dimension");
+  const int64_t shape[2] = {n, n};
+  TCI_TRY(make_tensor(ctx, dtype, 2, shape, out, true));
+  TCI_CHECK_HIP(add_diag(dtype, (*out)->data, n, (int)n, 1.0, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_extract_sub(tci_context ctx, tci_tensor in, const int64_t* first, const int64_t* last,
+                           tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out || (in->order > 0 && (!first || !last))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  const int order = in->order;
+  int64_t oshape[MAX_ORDER];
+  for (int b = 0; b < order; ++b) {
+    if (first[b] < 0 || last[b] < first[b] || last[b] > in->shape[b])
+      TCI_RET(TCI_ERR_INVALID_ARGUMENT, "range outside the bond");
+    oshape[b] = last[b] - first[b];
+  }
+  Trace tr(ctx, "extract_sub", shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype;
+  int64_t ishape[MAX_ORDER];
+  for (int b = 0; b < order; ++b) ishape[b] = in->shape[b];
+  TCI_TRY(ensure_shape(ctx, out, dt, order, oshape));
+  BoxCopy c{};
+  long long ss[MAX_ORDER + 1], ds[MAX_ORDER + 1];
+  row_major_strides(order, ishape, ss);
+  row_major_strides(order, oshape, ds);
+  c.order = std::max(order, 1);
+  c.dims[0] = 1;
+  c.sstride[0] = c.dstride[0] = 1;
+  c.total = 1;
+  c.soff = c.doff = 0;
+  for (int b = 0; b < order; ++b) {
+    c.dims[b] = oshape[b];
+    c.sstride[b] = ss[b];
+    c.dstride[b] = ds[b];
+    c.soff += first[b] * ss[b];
+    c.total *= oshape[b];
+  }
+  TCI_CHECK_HIP(box_copy(elem_bytes(dt), src, out->data, c, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_shrink(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* first,
+                      const int64_t* last, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (n < 0 || (n > 0 && (!bonds || !first || !last))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  int64_t f[MAX_ORDER], l[MAX_ORDER];
+  bool seen[MAX_ORDER] = {false};
+  for (int b = 0; b < in->order; ++b) {
+    f[b] = 0;
+    l[b] = in->shape[b];
+  }
+  for (int k = 0; k < n; ++k) {
+    const int b = bonds[k];
+    if (b < 0 || b >= in->order || seen[b]) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad bond index");
+    seen[b] = true;
+    f[b] = first[k];
+    l[b] = last[k];
+  }
+  return tci_extract_sub(ctx, in, f, l, out);
+}
+
+tci_status tci_expand(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* increments,
+                      tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out || n < 0 || (n > 0 && (!bonds || !increments))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  const int order = in->order;
+  int64_t ishape[MAX_ORDER], oshape[MAX_ORDER], zero[MAX_ORDER];
+  bool seen[MAX_ORDER] = {false};
+  for (int b = 0; b < order; ++b) {
+    ishape[b] = oshape[b] = in->shape[b];
+    zero[b] = 0;
+  }
+  for (int k = 0; k < n; ++k) {
+    const int b = bonds[k];
+    if (b < 0 || b >= order || seen[b] || increments[k] < 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad bond or increment");
+    seen[b] = true;
+    oshape[b] += increments[k];
+  }
+  Trace tr(ctx, "expand", shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype;
+  TCI_TRY(ensure_shape(ctx, out, dt, order, oshape));
+  if (tbytes(out)) TCI_CHECK_HIP(hipMemsetAsync(out->data, 0, tbytes(out), ctx->stream));
+  return copy_box(ctx, dt, src, order, ishape, out->data, oshape, zero);
+}
+
+tci_status tci_replace_sub(tci_context ctx, tci_tensor in, tci_tensor sub, const int64_t* begin, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  TCI_TRY(check_t(sub, "sub"));
+  if (!out || (in->order > 0 && !begin)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (sub->order != in->order || sub->dtype != in->dtype) TCI_RET(TCI_ERR_SHAPE, "sub must match order and dtype");
+  if (sub == out && out != in) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "out must not alias sub");
+  const int order = in->order;
+  int64_t ishape[MAX_ORDER], sshape[MAX_ORDER];
+  for (int b = 0; b < order; ++b) {
+    ishape[b] = in->shape[b];
+    sshape[b] = sub->shape[b];
+    if (begin[b] < 0 || begin[b] + sub->shape[b] > in->shape[b])
+      TCI_RET(TCI_ERR_INVALID_ARGUMENT, "sub does not fit at begin");
+  }
+  Trace tr(ctx, "replace_sub", shape_str(in));
+  if (out != in) {
+    TCI_TRY(ensure_shape(ctx, out, in->dtype, order, ishape));
+    if (tbytes(in)) TCI_CHECK_HIP(hipMemcpyAsync(out->data, in->data, tbytes(in), hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return copy_box(ctx, in->dtype, sub->data, order, sshape, out->data, ishape, begin);
+}
+
+tci_status tci_concatenate(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  if (n < 1 || !ins || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need at least one input and an output");
+  for (int k = 0; k < n; ++k) {
+    TCI_TRY(check_t(ins[k], "ins"));
+    if (ins[k] == out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "out must not alias an input");
+  }
+  const tci_tensor a = ins[0];
+  const int order = a->order, dt = a->dtype;
+  if (bond < 0 || bond >= order) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad bond index");
+  int64_t oshape[MAX_ORDER];
+  for (int b = 0; b < order; ++b) oshape[b] = a->shape[b];
+  oshape[bond] = 0;
+  for (int k = 0; k < n; ++k) {
+    if (ins[k]->order != order || ins[k]->dtype != dt) TCI_RET(TCI_ERR_SHAPE, "inputs differ in order or dtype");
+    for (int b = 0; b < order; ++b)
+      if (b != bond && ins[k]->shape[b] != a->shape[b]) TCI_RET(TCI_ERR_SHAPE, "inputs differ off the bond");
+    oshape[bond] += ins[k]->shape[bond];
+  }
+  Trace tr(ctx, "concatenate", shape_str(a));
+  TCI_TRY(ensure_shape(ctx, out, dt, order, oshape));
+  int64_t off[MAX_ORDER] = {0};
+  for (int k = 0; k < n; ++k) {
+    int64_t sshape[MAX_ORDER];
+    for (int b = 0; b < order; ++b) sshape[b] = ins[k]->shape[b];
+    TCI_TRY(copy_box(ctx, dt, ins[k]->data, order, sshape, out->data, oshape, off));
+    off[bond] += sshape[bond];
+  }
+  return TCI_OK;
+}
+
+tci_status tci_stack(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  if (n < 1 || !ins || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need at least one input and an output");
+  for (int k = 0; k < n; ++k) {
+    TCI_TRY(check_t(ins[k], "ins"));
+    if (ins[k] == out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "out must not alias an input");
+  }
+  const tci_tensor a = ins[0];
+  const int order = a->order, dt = a->dtype;
+  if (order + 1 > MAX_ORDER) TCI_RET(TCI_ERR_UNSUPPORTED, "result order above the maximum");
+  if (bond < 0 || bond > order) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad bond index");
+  for (int k = 0; k < n; ++k) {
+    if (ins[k]->order != order || ins[k]->dtype != dt) TCI_RET(TCI_ERR_SHAPE, "inputs differ in order or dtype");
+    for (int b = 0; b < order; ++b)
+      if (ins[k]->shape[b] != a->shape[b]) TCI_RET(TCI_ERR_SHAPE, "inputs differ in shape");
+  }
+  // each input is viewed with a bond of dimension 1 inserted at `bond`
+  int64_t oshape[MAX_ORDER], sshape[MAX_ORDER];
+  for (int b = 0, c = 0; b <= order; ++b) {
+    if (b == bond) {
+      oshape[b] = n;
+      sshape[b] = 1;
+    } else {
+      oshape[b] = a->shape[c];
+      sshape[b] = a->shape[c];
+      ++c;
+    }
+  }
+  Trace tr(ctx, "stack", shape_str(a));
+  TCI_TRY(ensure_shape(ctx, out, dt, order + 1, oshape));
+  int64_t off[MAX_ORDER] = {0};
+  for (int k = 0; k < n; ++k) {
+    off[bond] = k;
+    TCI_TRY(copy_box(ctx, dt, ins[k]->data, order + 1, sshape, out->data, oshape, off));
+  }
+  return TCI_OK;
+}
+
+tci_status tci_trace(tci_context ctx, tci_tensor in, int npairs, const int32_t* pairs, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out || npairs < 0 || (npairs > 0 && !pairs)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  const int order = in->order;
+  bool used[MAX_ORDER] = {false};
+  long long st[MAX_ORDER + 1];
+  int64_t ishape[MAX_ORDER];
+  for (int b = 0; b < order; ++b) ishape[b] = in->shape[b];
+  row_major_strides(order, ishape, st);
+  TraceArgs ta{};
+  for (int p = 0; p < npairs; ++p) {
+    const int x = pairs[2 * p], y = pairs[2 * p + 1];
+    if (x < 0 || y < 0 || x >= order || y >= order || x == y || used[x] || used[y])
+      TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad bond pair");
+    if (in->shape[x] != in->shape[y]) TCI_RET(TCI_ERR_SHAPE, "paired bonds differ in dimension");
+    used[x] = used[y] = true;
+    ta.pdims[p] = in->shape[x];
+    ta.pstride[p] = st[x] + st[y];
+  }
+  ta.npair = npairs;
+  ta.ntr = 1;
+  for (int p = 0; p < npairs; ++p) ta.ntr *= ta.pdims[p];
+  int64_t oshape[MAX_ORDER];
+  int nk = 0;
+  ta.nout = 1;
+  for (int b = 0; b < order; ++b) {
+    if (used[b]) continue;
+    oshape[nk] = in->shape[b];
+    ta.kdims[nk] = in->shape[b];
+    ta.kstride[nk] = st[b];
+    ta.nout *= in->shape[b];
+    ++nk;
+  }
+  ta.nkeep = nk;
+  Trace tr(ctx, "trace", shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype;
+  TCI_TRY(ensure_shape(ctx, out, dt, nk, oshape));
+  TCI_CHECK_HIP(partial_trace(dt, src, out->data, ta, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_diag(tci_context ctx, tci_tensor in, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (in->order != 1 && in->order != 2) TCI_RET(TCI_ERR_SHAPE, "diag needs a first- or second-order tensor");
+  Trace tr(ctx, "diag", shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype;
+  BoxCopy c{};
+  c.order = 1;
+  c.soff = c.doff = 0;
+  if (in->order == 1) {   // vector -> diagonal matrix
+    const int64_t n = in->shape[0];
+    const int64_t shape[2] = {n, n};
+    TCI_TRY(ensure_shape(ctx, out, dt, 2, shape));
+    TCI_CHECK_HIP(fill_value(dt, out->data, (long long)n * n, 0.0, 0.0, ctx->stream));
+    c.dims[0] = n;
+    c.sstride[0] = 1;
+    c.dstride[0] = n + 1;
+    c.total = n;
+  } else {                // matrix -> main diagonal, length min(d0, d1)
+    const int64_t d1 = in->shape[1], n = std::min(in->shape[0], d1);
+    TCI_TRY(ensure_shape(ctx, out, dt, 1, &n));
+    c.dims[0] = n;
+    c.sstride[0] = d1 + 1;
+    c.dstride[0] = 1;
+    c.total = n;
+  }
+  TCI_CHECK_HIP(box_copy(elem_bytes(dt), src, out->data, c, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_to_cplx(tci_context ctx, tci_tensor in, tci_tensor out) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  Trace tr(ctx, "to_cplx", shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype, cdt = dt == F32 ? C64 : dt == F64 ? C128 : dt;
+  int64_t shape[MAX_ORDER];
+  for (int b = 0; b < in->order; ++b) shape[b] = in->shape[b];
+  const long long n = tsize(in);
+  TCI_TRY(ensure_shape(ctx, out, cdt, in->order, shape));
+  TCI_CHECK_HIP(tci::convert(dt, src, cdt, out->data, n, ctx->stream));
+  return TCI_OK;
+}
+
+namespace {
+tci_status part_of(tci_context ctx, tci_tensor in, tci_tensor out, bool imag, const char* name) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(in, "in"));
+  if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  Trace tr(ctx, name, shape_str(in));
+  ctx->arena.reset();
+  const void* src;
+  TCI_TRY(stable_source(ctx, in, out, src));
+  const int dt = in->dtype, rdt = dt == C64 ? F32 : dt == C128 ? F64 : dt;
+  int64_t shape[MAX_ORDER];
+  for (int b = 0; b < in->order; ++b) shape[b] = in->shape[b];
+  const long long n = tsize(in);
+  TCI_TRY(ensure_shape(ctx, out, rdt, in->order, shape));
+  if (is_complex(dt))
+    TCI_CHECK_HIP(complex_part(dt, src, out->data, n, imag, ctx->stream));
+  else if (imag)
+    TCI_CHECK_HIP(fill_value(rdt, out->data, n, 0.0, 0.0, ctx->stream));
+  else if (out->data != src && n > 0)
+    TCI_CHECK_HIP(hipMemcpyAsync(out->data, src, (size_t)n * elem_bytes(dt), hipMemcpyDeviceToDevice, ctx->stream));
+  return TCI_OK;
+}
+}  // namespace
+
+tci_status tci_real(tci_context ctx, tci_tensor in, tci_tensor out) { return part_of(ctx, in, out, false, "real"); }
+tci_status tci_imag(tci_context ctx, tci_tensor in, tci_tensor out) { return part_of(ctx, in, out, true, "imag"); }
+
+// File layout: 8 bytes "TCIMI355", int32 format version (1), int32 dtype,
+// int32 order, int32 zero, int64 shape[order], then the elements row-major in
+// the host's (little-endian) byte order.
+namespace {
+constexpr char SAVE_MAGIC[8] = {'T', 'C', 'I', 'M', 'I', '3', '5', '5'};
+constexpr int32_t SAVE_VERSION = 1;
+}  // namespace
+
+tci_status tci_save(tci_context ctx, tci_tensor t, const char* path) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(t, "t"));
+  if (!path) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null path");
+  Trace tr(ctx, "save", shape_str(t));
+  std::vector<char> host(tbytes(t));
+  if (!host.empty()) {
+    TCI_CHECK_HIP(hipMemcpyAsync(host.data(), t->data, host.size(), hipMemcpyDeviceToHost, ctx->stream));
+    TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("cannot open ") + path);
+  const int32_t hdr[4] = {SAVE_VERSION, t->dtype, t->order, 0};
+  bool ok = std::fwrite(SAVE_MAGIC, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int32_t), 4, f) == 4;
+  if (ok && t->order > 0) ok = std::fwrite(t->shape, sizeof(int64_t), t->order, f) == (size_t)t->order;
+  if (ok && !host.empty()) ok = std::fwrite(host.data(), 1, host.size(), f) == host.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("short write to ") + path);
+  return TCI_OK;
+}
+
+tci_status tci_load(tci_context ctx, const char* path, tci_tensor* out) {
+  TCI_TRY(check_ctx(ctx));
+  if (!path || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t hdr[4];
+  int64_t shape[MAX_ORDER];
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, SAVE_MAGIC, 8) == 0 &&
+            std::fread(hdr, sizeof(int32_t), 4, f) == 4 && hdr[0] == SAVE_VERSION && valid_dtype(hdr[1]) &&
+            hdr[2] >= 0 && hdr[2] <= MAX_ORDER;
+  if (ok && hdr[2] > 0) ok = std::fread(shape, sizeof(int64_t), hdr[2], f) == (size_t)hdr[2];
+  for (int b = 0; ok && b < hdr[2]; ++b) ok = shape[b] >= 0;
+  if (!ok) {
+    std::fclose(f);
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("not a tensor file: ") + path);
+  }
+  long long n = 1;
+  for (int b = 0; b < hdr[2]; ++b) n *= shape[b];
+  std::vector<char> host((size_t)n * elem_bytes(hdr[1]));
+  ok = host.empty() || std::fread(host.data(), 1, host.size(), f) == host.size();
+  std::fclose(f);
+  if (!ok) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("truncated tensor file: ") + path);
+  TCI_TRY(make_tensor(ctx, (tci_dtype)hdr[1], hdr[2], shape, out, false));
+  Trace tr(ctx, "load", shape_str(*out));
+  if (!host.empty()) {
+    TCI_CHECK_HIP(hipMemcpyAsync((*out)->data, host.data(), host.size(), hipMemcpyHostToDevice, ctx->stream));
+    TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return TCI_OK;
+}
+
+tci_status tci_show(tci_context ctx, tci_tensor t) {
+  TCI_TRY(check_ctx(ctx));
+  TCI_TRY(check_t(t, "t"));
+  static const char* names[] = {"F32", "F64", "C64", "C128"};
+  std::vector<char> host(tbytes(t));
+  if (!host.empty()) {
+    TCI_CHECK_HIP(hipMemcpyAsync(host.data(), t->data, host.size(), hipMemcpyDeviceToHost, ctx->stream));
+    TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  std::printf("tensor %s shape %s\n", names[t->dtype], shape_str(t).c_str());
+  const long long n = tsize(t);
+  long long st[MAX_ORDER + 1];
+  int64_t shp[MAX_ORDER];
+  for (int b = 0; b < t->order; ++b) shp[b] = t->shape[b];
+  row_major_strides(t->order, shp, st);
+  for (long long e = 0; e < n; ++e) {
+    std::printf("  (");
+    for (int b = 0; b < t->order; ++b) std::printf(b ? ",%lld" : "%lld", (long long)((e / st[b]) % shp[b]));
+    std::printf(") ");
+    const char* p = host.data() + (size_t)e * elem_bytes(t->dtype);
+    switch (t->dtype) {
+      case F32: std::printf("%.9g\n", (double)*reinterpret_cast<const float*>(p)); break;
+      case F64: std::printf("%.17g\n", *reinterpret_cast<const double*>(p)); break;
+      case C64: {
+        const float* c = reinterpret_cast<const float*>(p);
+        std::printf("%.9g%+.9gj\n", (double)c[0], (double)c[1]);
+        break;
+      }
+      default: {
+        const double* c = reinterpret_cast<const double*>(p);
+        std::printf("%.17g%+.17gj\n", c[0], c[1]);
+      }
+    }
+  }
+  std::fflush(stdout);
+  return TCI_OK;
 }
 
 }  // extern "C"

@@ -19,10 +19,12 @@
 #include "../../include/tci_c.h"
 #include "common.hpp"
 #include "eig.hpp"
+#include "gaussjordan.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
 #include "prof.hpp"
 #include "runtime.hpp"
+#include "subtensor.hpp"
 #include "tsvd.hpp"
 #include "vecops.hpp"
 
@@ -486,21 +488,13 @@ tci_status tci_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_
   return tci_trunc_svd(ctx, a, k_rows, u, s, vdag, nullptr, kap, kap, 0.0, 0.0);
 }
 
-tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r) {
-  if (!ctx || !a || !q || !r) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
-  TCI_CHECK_HIP(hipSetDevice(ctx->device));
-  int64_t rows, cols;
-  TCI_TRY(matricize(a, k_rows, rows, cols));
-  if (rows < cols) TCI_RET(TCI_ERR_UNSUPPORTED, "qr of a wide matrix (rows < cols) is not supported");
-  Trace tr(ctx, "qr", std::to_string(rows) + "x" + std::to_string(cols));
-  ctx->arena.reset();
-  int wdt;
-  const void* w;
-  TCI_TRY(working_copy(ctx, a, wdt, w));
+// Thin QR of the m x k (m >= k) working-precision matrix at w: Y (m x k)
+// receives Q and R (k x k) the triangular factor.  Two Cholesky-QR passes,
+// R = R2 R1 with the diagonals of dropped columns zeroed.
+static tci_status qr_core(tci_context ctx, int wdt, int m, int k, const void* w, void*& Y, void*& R) {
   const size_t es = elem_bytes(wdt);
-  const int m = (int)rows, k = (int)cols;
   hipStream_t st = ctx->stream;
-  void* Y = ctx->arena.get(es * (size_t)m * k);
+  Y = ctx->arena.get(es * (size_t)m * k);
   void* Q1 = ctx->arena.get(es * (size_t)m * k);
   if (!Y || !Q1) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(hipMemcpyAsync(Y, w, es * (size_t)m * k, hipMemcpyDeviceToDevice, st));
@@ -514,13 +508,29 @@ tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_t
   }
   TCI_CHECK_HIP(cholqr(wdt, 0, Y, k, 0, m, k, Q1, k, 0, w1, CHOL_DROP_TAU, 1, st));
   TCI_CHECK_HIP(cholqr(wdt, 0, Q1, k, 0, m, k, Y, k, 0, w2, CHOL_DROP_TAU, 1, st));
-  // R = triu(R2) triu(R1) with dropped diagonals zeroed
   TCI_CHECK_HIP(triu_mask(wdt, w1.G, k, 0, k, w1.mask, 0, 1, st));
   TCI_CHECK_HIP(triu_mask(wdt, w2.G, k, 0, k, w2.mask, 0, 1, st));
-  void* R = ctx->arena.get(es * (size_t)k * k);
+  R = ctx->arena.get(es * (size_t)k * k);
   if (!R) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   GemmArgs g = gemm_args(k, k, k, OP_N, OP_N, w2.G, k, w1.G, k, R, k);
   TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, st));
+  return TCI_OK;
+}
+
+tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r) {
+  if (!ctx || !a || !q || !r) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  if (rows < cols) TCI_RET(TCI_ERR_UNSUPPORTED, "qr of a wide matrix (rows < cols) is not supported");
+  Trace tr(ctx, "qr", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, a, wdt, w));
+  const int m = (int)rows, k = (int)cols;
+  void *Y, *R;
+  TCI_TRY(qr_core(ctx, wdt, m, k, w, Y, R));
   int64_t qshape[MAX_ORDER + 1], rshape[MAX_ORDER + 1];
   for (int i = 0; i < k_rows; ++i) qshape[i] = a->shape[i];
   qshape[k_rows] = k;
@@ -531,6 +541,154 @@ tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_t
   TCI_TRY(ensure_shape(ctx, r, odt, ord - k_rows + 1, rshape));
   TCI_TRY(store_as(ctx, wdt, Y, q));
   TCI_TRY(store_as(ctx, wdt, R, r));
+  TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  return TCI_OK;
+}
+
+// Conjugate transpose of a rows x cols working-precision matrix.
+static tci_status conj_transpose(tci_context ctx, int wdt, const void* in, int rows, int cols, void* out) {
+  const long long shp[2] = {rows, cols};
+  const int perm[2] = {1, 0};
+  TCI_CHECK_HIP(permute(wdt, in, out, 2, shp, perm, ctx->stream));
+  if (is_complex(wdt)) TCI_CHECK_HIP(conjugate(wdt, out, out, (long long)rows * cols, ctx->stream));
+  return TCI_OK;
+}
+
+tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_tensor q) {
+  if (!ctx || !a || !l || !q) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  if (rows > cols) TCI_RET(TCI_ERR_UNSUPPORTED, "lq of a tall matrix (rows > cols) is not supported");
+  Trace tr(ctx, "lq", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, a, wdt, w));
+  const size_t es = elem_bytes(wdt);
+  const int m = (int)rows, n = (int)cols;
+  // A^H = Q1 R1 (n x m tall), so A = R1^H Q1^H: L = R1^H, Q = Q1^H
+  void* Ah = ctx->arena.get(es * (size_t)m * n);
+  if (!Ah) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_TRY(conj_transpose(ctx, wdt, w, m, n, Ah));
+  void *Y, *R;
+  TCI_TRY(qr_core(ctx, wdt, n, m, Ah, Y, R));
+  void* Lw = ctx->arena.get(es * (size_t)m * m);
+  void* Qw = ctx->arena.get(es * (size_t)m * n);
+  if (!Lw || !Qw) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_TRY(conj_transpose(ctx, wdt, R, m, m, Lw));
+  TCI_TRY(conj_transpose(ctx, wdt, Y, n, m, Qw));
+  int64_t lshape[MAX_ORDER + 1], qshape[MAX_ORDER + 1];
+  for (int i = 0; i < k_rows; ++i) lshape[i] = a->shape[i];
+  lshape[k_rows] = m;
+  qshape[0] = m;
+  for (int i = k_rows; i < a->order; ++i) qshape[1 + i - k_rows] = a->shape[i];
+  const int odt = a->dtype, ord = a->order;
+  TCI_TRY(ensure_shape(ctx, l, odt, k_rows + 1, lshape));
+  TCI_TRY(ensure_shape(ctx, q, odt, ord - k_rows + 1, qshape));
+  TCI_TRY(store_as(ctx, wdt, Lw, l));
+  TCI_TRY(store_as(ctx, wdt, Qw, q));
+  TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  return TCI_OK;
+}
+
+// Matrix exponential by scaling and squaring with a Taylor polynomial, in
+// FP64 for every dtype: B = A / 2^s with ||B||_F <= 1/2, exp(B) ~ sum_{j <= 18}
+// B^j / j! by Horner's rule (P <- I + B P / j for j = 18 .. 1; truncation
+// below 2^-19 / 19! ~ 1.6e-23 relative), then s squarings.
+tci_status tci_exp(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) {
+  if (!ctx || !in || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(in, k_rows, rows, cols));
+  if (rows != cols) TCI_RET(TCI_ERR_SHAPE, "exp needs equal row and column dimensions");
+  Trace tr(ctx, "exp", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, in, wdt, w));
+  const int n = (int)rows;
+  const size_t es = elem_bytes(wdt);
+  const size_t bytes = es * (size_t)n * n;
+  hipStream_t st = ctx->stream;
+  void* B = ctx->arena.get(bytes);
+  void* P = ctx->arena.get(bytes);
+  void* T = ctx->arena.get(bytes);
+  double* nrm = static_cast<double*>(ctx->arena.get(sizeof(double) * (SUMSQ_PARTIALS + 1)));
+  if (!B || !P || !T || !nrm) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(hipMemcpyAsync(B, w, bytes, hipMemcpyDeviceToDevice, st));
+  TCI_CHECK_HIP(sumsq_batched(wdt, B, (long long)n * n, 0, nrm + SUMSQ_PARTIALS, nrm, 1, st));
+  double fn2 = 0.0;
+  TCI_CHECK_HIP(hipMemcpyAsync(&fn2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, st));
+  TCI_CHECK_HIP(hipStreamSynchronize(st));
+  if (!std::isfinite(fn2)) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries");
+  const double fn = std::sqrt(fn2);
+  int sq = 0;
+  while (fn > 0.5 * std::ldexp(1.0, sq) && sq < 1100) ++sq;
+  TCI_CHECK_HIP(scale_inplace(wdt, B, (long long)n * n, std::ldexp(1.0, -sq), 0.0, st));
+  constexpr int TAYLOR_DEGREE = 18;
+  TCI_CHECK_HIP(fill_value(wdt, P, (long long)n * n, 0.0, 0.0, st));
+  TCI_CHECK_HIP(add_diag(wdt, P, n, n, 1.0, st));
+  for (int j = TAYLOR_DEGREE; j >= 1; --j) {
+    // T = B P / j, then P = I + T
+    GemmArgs g = gemm_args(n, n, n, OP_N, OP_N, B, n, P, n, T, n);
+    g.alpha_re = 1.0 / j;
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, st));
+    TCI_CHECK_HIP(add_diag(wdt, T, n, n, 1.0, st));
+    std::swap(P, T);
+  }
+  for (int k = 0; k < sq; ++k) {
+    GemmArgs g = gemm_args(n, n, n, OP_N, OP_N, P, n, P, n, T, n);
+    TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, st));
+    std::swap(P, T);
+  }
+  int64_t shape[MAX_ORDER];
+  for (int i = 0; i < in->order; ++i) shape[i] = in->shape[i];
+  const int odt = in->dtype, ord = in->order;
+  TCI_TRY(ensure_shape(ctx, out, odt, ord, shape));
+  TCI_TRY(store_as(ctx, wdt, P, out));
+  TCI_CHECK_HIP(hipStreamSynchronize(st));
+  return TCI_OK;
+}
+
+tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) {
+  if (!ctx || !in || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(in, k_rows, rows, cols));
+  if (rows != cols) TCI_RET(TCI_ERR_SHAPE, "inverse needs equal row and column dimensions");
+  if (rows > 65536) TCI_RET(TCI_ERR_UNSUPPORTED, "inverse of a matrix above 65536 x 65536");
+  Trace tr(ctx, "inverse", std::to_string(rows) + "x" + std::to_string(cols));
+  ctx->arena.reset();
+  int wdt;
+  const void* w;
+  TCI_TRY(working_copy(ctx, in, wdt, w));
+  const int n = (int)rows;
+  const size_t es = elem_bytes(wdt);
+  hipStream_t st = ctx->stream;
+  void* work = ctx->arena.get(gauss_jordan_work_bytes(wdt, n));
+  void* res = ctx->arena.get(es * (size_t)n * n);
+  int* status = static_cast<int*>(ctx->arena.get(sizeof(int)));
+  double* nrm = static_cast<double*>(ctx->arena.get(sizeof(double) * (SUMSQ_PARTIALS + 1)));
+  if (!work || !res || !status || !nrm) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  TCI_CHECK_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
+  TCI_CHECK_HIP(gauss_jordan_inverse(wdt, w, n, work, status, st));
+  // the inverse is the right half of the n x 2n augmented matrix
+  TCI_CHECK_HIP(hipMemcpy2DAsync(res, es * n, static_cast<char*>(work) + es * n, es * 2 * n, es * n, n,
+                                 hipMemcpyDeviceToDevice, st));
+  TCI_CHECK_HIP(sumsq_batched(wdt, res, (long long)n * n, 0, nrm + SUMSQ_PARTIALS, nrm, 1, st));
+  int singular = 0;
+  double fn2 = 0.0;
+  TCI_CHECK_HIP(hipMemcpyAsync(&singular, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  TCI_CHECK_HIP(hipMemcpyAsync(&fn2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, st));
+  TCI_CHECK_HIP(hipStreamSynchronize(st));
+  if (singular) TCI_RET(TCI_ERR_NUMERIC, "singular matrix: no pivot in column " + std::to_string(singular - 1));
+  if (!std::isfinite(fn2)) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries");
+  int64_t shape[MAX_ORDER];
+  for (int i = 0; i < in->order; ++i) shape[i] = in->shape[i];
+  const int odt = in->dtype, ord = in->order;
+  TCI_TRY(ensure_shape(ctx, out, odt, ord, shape));
+  TCI_TRY(store_as(ctx, wdt, res, out));
   TCI_CHECK_HIP(hipStreamSynchronize(st));
   return TCI_OK;
 }

@@ -28,6 +28,7 @@ STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "SHAPE", 3: "LABEL", 4: "DTYPE", 5:
 
 TORCH_OF = {F32: torch.float32, F64: torch.float64, C64: torch.complex64, C128: torch.complex128}
 DTYPE_OF = {v: k for k, v in TORCH_OF.items()}
+NUMPY_OF = {F32: np.float32, F64: np.float64, C64: np.complex64, C128: np.complex128}
 ELEM_BYTES = {F32: 4, F64: 8, C64: 8, C128: 16}
 
 
@@ -107,6 +108,25 @@ def lib():
         "tci_qr": (i32, [p, p, ctypes.c_int, p, p]),
         "tci_eigh": (i32, [p, p, p, p]),
         "tci_close": (i32, [p, p, p, f64, P(ctypes.c_int)]),
+        "tci_fill": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), p, P(p)]),
+        "tci_eye": (i32, [p, ctypes.c_int, i64, P(p)]),
+        "tci_extract_sub": (i32, [p, p, P(i64), P(i64), p]),
+        "tci_shrink": (i32, [p, p, ctypes.c_int, P(i32), P(i64), P(i64), p]),
+        "tci_expand": (i32, [p, p, ctypes.c_int, P(i32), P(i64), p]),
+        "tci_replace_sub": (i32, [p, p, p, P(i64), p]),
+        "tci_concatenate": (i32, [p, ctypes.c_int, P(p), ctypes.c_int, p]),
+        "tci_stack": (i32, [p, ctypes.c_int, P(p), ctypes.c_int, p]),
+        "tci_trace": (i32, [p, p, ctypes.c_int, P(i32), p]),
+        "tci_exp": (i32, [p, p, ctypes.c_int, p]),
+        "tci_lq": (i32, [p, p, ctypes.c_int, p, p]),
+        "tci_inverse": (i32, [p, p, ctypes.c_int, p]),
+        "tci_to_cplx": (i32, [p, p, p]),
+        "tci_diag": (i32, [p, p, p]),
+        "tci_real": (i32, [p, p, p]),
+        "tci_imag": (i32, [p, p, p]),
+        "tci_save": (i32, [p, p, ctypes.c_char_p]),
+        "tci_load": (i32, [p, ctypes.c_char_p, P(p)]),
+        "tci_show": (i32, [p, p]),
         "tci_update_params_default": (None, [P(UpdateParams)]),
         "tci_two_site_update_batched": (i32, [p, ctypes.c_int, P(p), P(p), P(p), P(UpdateParams),
                                               P(p), P(p), P(p), P(UpdateInfo)]),
@@ -357,6 +377,123 @@ def close(ctx: Context, a: Tensor, b: Tensor, eps: float) -> bool:
     r = ctypes.c_int()
     _check(lib().tci_close(ctx.h, a.h, b.h, eps, ctypes.byref(r)), "tci_close")
     return bool(r.value)
+
+
+def lq(ctx: Context, a: Tensor, k_rows: int):
+    shp = a.shape()
+    rows = int(np.prod(shp[:k_rows]))
+    cols = int(np.prod(shp[k_rows:]))
+    rho = min(rows, cols)
+    l = Tensor.empty(ctx, a.dtype, rows * rho)
+    q = Tensor.empty(ctx, a.dtype, rho * cols)
+    _check(lib().tci_lq(ctx.h, a.h, k_rows, l.h, q.h), "tci_lq")
+    return l, q
+
+
+def exp(ctx: Context, a: Tensor, k_rows: int, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(a.shape())))
+    _check(lib().tci_exp(ctx.h, a.h, k_rows, out.h), "tci_exp")
+    return out
+
+
+def _scalar_bytes(dtype: int, value) -> ctypes.Array:
+    v = np.array([value], dtype=NUMPY_OF[dtype])
+    return (ctypes.c_char * v.nbytes).from_buffer_copy(v.tobytes())
+
+
+def _adopt(ctx: Context, h: ctypes.c_void_p, dtype: int, shape) -> Tensor:
+    """Copy an owning library tensor into a torch-backed Tensor and free it."""
+    n = max(1, int(np.prod(shape)))
+    out = Tensor(ctx, torch.empty(n, dtype=TORCH_OF[dtype], device=ctx.torch_device), shape=[n])
+    try:
+        _check(lib().tci_reshape(ctx.h, h, len(shape), _i64(shape), out.h), "tci_reshape")
+    finally:
+        lib().tci_destroy(ctx.h, h)
+    return out
+
+
+def fill(ctx: Context, dtype: int, shape, value) -> Tensor:
+    h = ctypes.c_void_p()
+    _check(lib().tci_fill(ctx.h, dtype, len(shape), _i64(shape), _scalar_bytes(dtype, value), ctypes.byref(h)),
+           "tci_fill")
+    return _adopt(ctx, h, dtype, list(shape))
+
+
+def eye(ctx: Context, dtype: int, n: int) -> Tensor:
+    h = ctypes.c_void_p()
+    _check(lib().tci_eye(ctx.h, dtype, n, ctypes.byref(h)), "tci_eye")
+    return _adopt(ctx, h, dtype, [n, n])
+
+
+def extract_sub(ctx: Context, a: Tensor, ranges, out: Tensor | None = None) -> Tensor:
+    first = [int(f) for f, _ in ranges]
+    last = [int(l) for _, l in ranges]
+    if out is None:
+        out = Tensor.empty(ctx, a.dtype, int(np.prod([max(0, l - f) for f, l in zip(first, last)])))
+    _check(lib().tci_extract_sub(ctx.h, a.h, _i64(first), _i64(last), out.h), "tci_extract_sub")
+    return out
+
+
+def shrink(ctx: Context, a: Tensor, ranges: dict, out: Tensor | None = None) -> Tensor:
+    bonds = list(ranges)
+    if out is None:
+        shp = list(a.shape())
+        for b, (f, l) in ranges.items():
+            if 0 <= b < len(shp):   # bad bonds are reported by the library
+                shp[b] = max(0, l - f)
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(shp)))
+    _check(lib().tci_shrink(ctx.h, a.h, len(bonds), _i32(bonds), _i64([ranges[b][0] for b in bonds]),
+                            _i64([ranges[b][1] for b in bonds]), out.h), "tci_shrink")
+    return out
+
+
+def expand(ctx: Context, a: Tensor, increments: dict, out: Tensor | None = None) -> Tensor:
+    bonds = list(increments)
+    if out is None:
+        shp = list(a.shape())
+        for b, inc in increments.items():
+            if 0 <= b < len(shp):   # bad bonds are reported by the library
+                shp[b] += max(0, inc)
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(shp)))
+    _check(lib().tci_expand(ctx.h, a.h, len(bonds), _i32(bonds), _i64([increments[b] for b in bonds]), out.h),
+           "tci_expand")
+    return out
+
+
+def replace_sub(ctx: Context, a: Tensor, sub: Tensor, begin, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(a.shape())))
+    _check(lib().tci_replace_sub(ctx.h, a.h, sub.h, _i64(begin), out.h), "tci_replace_sub")
+    return out
+
+
+def _handles(ins):
+    return (ctypes.c_void_p * len(ins))(*[t.h.value for t in ins])
+
+
+def concatenate(ctx: Context, ins: list, bond: int, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, ins[0].dtype, sum(int(np.prod(t.shape())) for t in ins))
+    _check(lib().tci_concatenate(ctx.h, len(ins), _handles(ins), bond, out.h), "tci_concatenate")
+    return out
+
+
+def stack(ctx: Context, ins: list, bond: int, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, ins[0].dtype, sum(int(np.prod(t.shape())) for t in ins))
+    _check(lib().tci_stack(ctx.h, len(ins), _handles(ins), bond, out.h), "tci_stack")
+    return out
+
+
+def trace(ctx: Context, a: Tensor, pairs, out: Tensor | None = None) -> Tensor:
+    flat = [int(x) for p in pairs for x in p]
+    if out is None:
+        shp = a.shape()
+        used = set(flat)
+        out = Tensor.empty(ctx, a.dtype, int(np.prod([d for b, d in enumerate(shp) if b not in used])))
+    _check(lib().tci_trace(ctx.h, a.h, len(pairs), _i32(flat), out.h), "tci_trace")
+    return out
 
 
 def _attach_prev(params: UpdateParams, prev):
@@ -638,3 +775,61 @@ def bs_two_site_update_batched(ctx: Context, A: list, B: list, gates: list | Non
                                                 P(*[x.h.value for x in s_out]), P(*[x.h.value for x in B_out]),
                                                 infos), "tci_bs_two_site_update_batched")
     return A_out, s_out, B_out, list(infos)
+
+
+def inverse(ctx: Context, a: Tensor, k_rows: int, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(a.shape())))
+    _check(lib().tci_inverse(ctx.h, a.h, k_rows, out.h), "tci_inverse")
+    return out
+
+
+COMPLEX_OF = {F32: C64, F64: C128, C64: C64, C128: C128}
+REAL_OF = {F32: F32, F64: F64, C64: F32, C128: F64}
+
+
+def to_cplx(ctx: Context, a: Tensor) -> Tensor:
+    out = Tensor.empty(ctx, COMPLEX_OF[a.dtype], int(np.prod(a.shape())))
+    _check(lib().tci_to_cplx(ctx.h, a.h, out.h), "tci_to_cplx")
+    return out
+
+
+def real(ctx: Context, a: Tensor) -> Tensor:
+    out = Tensor.empty(ctx, REAL_OF[a.dtype], int(np.prod(a.shape())))
+    _check(lib().tci_real(ctx.h, a.h, out.h), "tci_real")
+    return out
+
+
+def imag(ctx: Context, a: Tensor) -> Tensor:
+    out = Tensor.empty(ctx, REAL_OF[a.dtype], int(np.prod(a.shape())))
+    _check(lib().tci_imag(ctx.h, a.h, out.h), "tci_imag")
+    return out
+
+
+def save(ctx: Context, a: Tensor, path: str):
+    _check(lib().tci_save(ctx.h, a.h, os.fsencode(path)), "tci_save")
+
+
+def load(ctx: Context, path: str) -> Tensor:
+    h = ctypes.c_void_p()
+    _check(lib().tci_load(ctx.h, os.fsencode(path), ctypes.byref(h)), "tci_load")
+    order = ctypes.c_int()
+    dt = ctypes.c_int()
+    _check(lib().tci_order(ctx.h, h, ctypes.byref(order)), "tci_order")
+    shp = (ctypes.c_int64 * max(1, order.value))()
+    _check(lib().tci_shape(ctx.h, h, shp, order.value), "tci_shape")
+    _check(lib().tci_dtype_of(ctx.h, h, ctypes.byref(dt)), "tci_dtype_of")
+    return _adopt(ctx, h, dt.value, [shp[i] for i in range(order.value)])
+
+
+def show(ctx: Context, a: Tensor):
+    _check(lib().tci_show(ctx.h, a.h), "tci_show")
+
+
+def diag(ctx: Context, a: Tensor, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        shp = a.shape()
+        cap = shp[0] * shp[0] if len(shp) == 1 else (min(shp) if len(shp) == 2 else 1)
+        out = Tensor.empty(ctx, a.dtype, cap)
+    _check(lib().tci_diag(ctx.h, a.h, out.h), "tci_diag")
+    return out
