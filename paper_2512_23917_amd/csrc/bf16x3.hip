@@ -191,7 +191,6 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
-    if (more) fetch((kt + 1) * XBK);
     bf8v fa[NP][IM], fb[NP][JN];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -202,6 +201,9 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
       for (int j = 0; j < JN; ++j)
         fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[cur][p][wn * XWN + j * 16 + lr][rd]);
     }
+    // the next tile's global loads go out after this step's fragment reads,
+    // so that the first matrix instructions do not wait behind them
+    if (more) fetch((kt + 1) * XBK);
 #pragma unroll
     for (int i = 0; i < IM; ++i) {
 #pragma unroll
