@@ -26,7 +26,8 @@ Conventions (shared by the GPU driver only through this description):
         V_j <- V_j . Y^{-T} conj(V_chi) S_chi^{1/2},
     so that (X^{-T} U S^{1/2})(Y^{-T} conj(V) S^{1/2})^T = X^{-T} R Y^{-1} = I
     when nothing is cut; inverse square roots drop eigenvalues below
-    1e-12 of the largest;
+    1e-10 of the largest, and singular values below 1e-6 of the largest
+    are no bond directions (rounding lifted by the inverse square roots);
   * a two-site gate G[s_i, s_j, s_i', s_j'] on edge (i, j) enters as a
     tensor-network operator: G reshaped (s_i s_i') x (s_j s_j') is split by
     an SVD into O_i[s_i, s_i', k] (U sqrt(S)) and O_j[s_j, s_j', k]
@@ -37,7 +38,8 @@ from __future__ import annotations
 
 import numpy as np
 
-INV_SQRT_CUT = 1e-12
+INV_SQRT_CUT = 1e-10   # message eigenvalues kept by the inverse square root (relative)
+SV_CUT = 1e-6          # singular values of R kept as bond directions (relative)
 
 
 # ------------------------------------------------------------------ graphs
@@ -178,7 +180,7 @@ def truncate_edge(i, j, V, M, nb, chi):
     Y, Yi = _sqrt_and_inv(M[(j, i)])
     R = X.T @ Y
     u, s, vh = np.linalg.svd(R)
-    k = min(chi, int(np.sum(s > INV_SQRT_CUT * s[0])) if s[0] > 0 else 1)
+    k = min(chi, int(np.sum(s > SV_CUT * s[0])) if s[0] > 0 else 1)
     k = max(k, 1)
     u, s, vh = u[:, :k], s[:k], vh[:k]
     rs = np.sqrt(s)
