@@ -833,3 +833,16 @@ def diag(ctx: Context, a: Tensor, out: Tensor | None = None) -> Tensor:
         out = Tensor.empty(ctx, a.dtype, cap)
     _check(lib().tci_diag(ctx.h, a.h, out.h), "tci_diag")
     return out
+
+
+def cplx_conj(ctx: Context, a: Tensor, out: Tensor | None = None) -> Tensor:
+    if out is None:
+        out = Tensor.empty(ctx, a.dtype, int(np.prod(a.shape())))
+    _check(lib().tci_cplx_conj(ctx.h, a.h, out.h), "tci_cplx_conj")
+    return out
+
+
+def scale(ctx: Context, a: Tensor, s) -> Tensor:
+    """In place: a *= s (one scalar of a's dtype)."""
+    _check(lib().tci_scale(ctx.h, a.h, _scalar_bytes(a.dtype, s)), "tci_scale")
+    return a
