@@ -169,6 +169,19 @@ __device__ inline cd ldv(const cf* p) {
   const cf v = *p;
   return cd{(double)v.x, (double)v.y};
 }
+// Two consecutive elements (p 16-byte aligned): one 16-byte load for complex64.
+__device__ inline void ldv2(const cd* p, cd& a, cd& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ inline void ldv2(const cf* p, cd& a, cd& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = cd{(double)v.x, (double)v.y};
+  b = cd{(double)v.z, (double)v.w};
+}
+// The sweeps below take element pairs (2i, 2i+1) when n is even, so that a
+// complex64 basis vector is read with 16-byte loads; an odd n runs the
+// single-element loop over all of it.
 
 // NV is a compile-time bound on nv so that the accumulators stay in registers.
 template <int NV, typename VT>
@@ -178,7 +191,20 @@ __global__ __launch_bounds__(256) void multidot_partial_kernel(const VT* V, int 
   double accr[NV], acci[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+  const long long np2 = (n & 1) ? 0 : n / 2, stride = (long long)gridDim.x * 256;
+  for (long long i2 = blockIdx.x * 256LL + threadIdx.x; i2 < np2; i2 += stride) {
+    const cd x0 = w[2 * i2], x1 = w[2 * i2 + 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        cd v0, v1;
+        ldv2(V + (long long)q * n + 2 * i2, v0, v1);
+        accr[q] += (v0.x * x0.x + v0.y * x0.y) + (v1.x * x1.x + v1.y * x1.y);
+        acci[q] += (v0.x * x0.y - v0.y * x0.x) + (v1.x * x1.y - v1.y * x1.x);
+      }
+    }
+  }
+  for (long long i = 2 * np2 + blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
     const cd x = w[i];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -319,7 +345,25 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(const VT* V, int nv, con
     ci[q] = q < nv ? sign * c[2 * q + 1] : 0.0;
   }
   double ss = 0.0;
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+  const long long np2 = (n & 1) ? 0 : n / 2, stride = (long long)gridDim.x * 256;
+  for (long long i2 = blockIdx.x * 256LL + threadIdx.x; i2 < np2; i2 += stride) {
+    cd a0 = w[2 * i2], a1 = w[2 * i2 + 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if (q < nv) {
+        cd v0, v1;
+        ldv2(V + (long long)q * n + 2 * i2, v0, v1);
+        a0.x += cr[q] * v0.x - ci[q] * v0.y;
+        a0.y += cr[q] * v0.y + ci[q] * v0.x;
+        a1.x += cr[q] * v1.x - ci[q] * v1.y;
+        a1.y += cr[q] * v1.y + ci[q] * v1.x;
+      }
+    }
+    w[2 * i2] = a0;
+    w[2 * i2 + 1] = a1;
+    ss += (a0.x * a0.x + a0.y * a0.y) + (a1.x * a1.x + a1.y * a1.y);
+  }
+  for (long long i = 2 * np2 + blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
     cd acc = w[i];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -401,7 +445,42 @@ __global__ __launch_bounds__(256) void three_term_dot_kernel(const VT* V, const 
   double accr[NV], acci[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+  const long long np2 = (n & 1) ? 0 : n / 2, stride = (long long)gridDim.x * 256;
+  for (long long i2 = blockIdx.x * 256LL + threadIdx.x; i2 < np2; i2 += stride) {
+    const long long i = 2 * i2;
+    cd y0 = w[i], y1 = w[i + 1];
+    cd vj0, vj1, vp0{0.0, 0.0}, vp1{0.0, 0.0};
+    ldv2(V + (long long)(NV - 1) * n + i, vj0, vj1);
+    y0.x -= alpha * vj0.x;
+    y0.y -= alpha * vj0.y;
+    y1.x -= alpha * vj1.x;
+    y1.y -= alpha * vj1.y;
+    if constexpr (NV >= 2) {
+      ldv2(V + (long long)(NV - 2) * n + i, vp0, vp1);
+      y0.x -= beta * vp0.x;
+      y0.y -= beta * vp0.y;
+      y1.x -= beta * vp1.x;
+      y1.y -= beta * vp1.y;
+    }
+    w[i] = y0;
+    w[i + 1] = y1;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      cd v0, v1;
+      if (q == NV - 1) {
+        v0 = vj0;
+        v1 = vj1;
+      } else if (q == NV - 2) {
+        v0 = vp0;
+        v1 = vp1;
+      } else {
+        ldv2(V + (long long)q * n + i, v0, v1);
+      }
+      accr[q] += (v0.x * y0.x + v0.y * y0.y) + (v1.x * y1.x + v1.y * y1.y);
+      acci[q] += (v0.x * y0.y - v0.y * y0.x) + (v1.x * y1.y - v1.y * y1.x);
+    }
+  }
+  for (long long i = 2 * np2 + blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
     cd y = w[i];
     const cd vj = ldv(V + (long long)(NV - 1) * n + i);
     y.x -= alpha * vj.x;
