@@ -15,8 +15,8 @@ Gram / orthogonalisation / eigensolve); the learned sketch
 predicts the sketch rank of the randomized SVD and falls back to the plain
 SVD when the discarded weight misses eps (always here: the cap binds).
 
-Prints one JSON line (rank 0).  --gpus N with N > 1 exits: this build runs on
-one GPU.
+Prints one JSON line (rank 0).  --gpus N with N > 1 exits: the benchmark
+measures one GPU (the library has no multi-GPU path).
 """
 from __future__ import annotations
 
@@ -262,7 +262,7 @@ def main():
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
