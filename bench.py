@@ -48,6 +48,10 @@ PEAKS = {  # MI355X published dense peaks
     "c64_bf16x3_planes": (2.5e15, "TFLOP/s", "mfma"),
     "f32_bf16x3_planes": (2.5e15, "TFLOP/s", "mfma"),
     "hemv": (8.0e12, "GB/s", "hbm"),
+    "sweep_dot": (8.0e12, "GB/s", "hbm"),
+    "sweep_axpy": (8.0e12, "GB/s", "hbm"),
+    "reorth2_dot": (8.0e12, "GB/s", "hbm"),
+    "reorth2_axpy": (8.0e12, "GB/s", "hbm"),
 }
 
 
@@ -312,6 +316,7 @@ def main():
 
     # dominant kernel class of the measured (mixed) path, summed over call sites
     roof = None
+    classes = {}
     if prof:
         by_cls = {}
         for tag, (cnt, ms, work) in prof.items():
@@ -336,6 +341,17 @@ def main():
         share = {k: round(v[1] / (t_mixed * 1e3), 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:8]}
         if roof:
             roof["time_share_top"] = share
+        # every class of the mixed path: share of the timed region, achieved
+        # rate and fraction of the matching peak (classes with a peak only)
+        for k, (c_cnt, c_ms, c_work, _) in sorted(by_cls.items(), key=lambda kv: -kv[1][1]):
+            c_peak, c_unit, c_bound = PEAKS.get(k, (None, None, None))
+            entry = {"share": round(c_ms / (t_mixed * 1e3), 4), "launches": c_cnt}
+            if c_peak:
+                c_scale = 1e12 if c_unit == "TFLOP/s" else 1e9
+                c_rate = c_work / (c_ms * 1e-3)
+                entry.update({"rate": round(c_rate / c_scale, 2), "unit": c_unit, "bound": c_bound,
+                              "frac": round(c_rate / c_peak, 4)})
+            classes[k] = entry
 
     bs = None
     if not args.skip_blocksparse:
@@ -377,6 +393,7 @@ def main():
         "energy_parity_mixed_vs_plain": None if en_p is None else
             float(max(abs(a - b) / abs(b) for a, b in zip(en_m, en_p))),
         "roofline": roof,
+        "kernel_classes": classes,
         "cpu_baseline": cpu,
         "blocksparse": bs,
     }
