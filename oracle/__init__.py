@@ -18,8 +18,11 @@ into it and exposes the tensor-level operations of the paper's API
     eigh                  Spec, eigh
     norm / normalize      Spec, norm (Frobenius-norm equation) and normalize
 
-Algorithm-level oracles live in the sibling modules (``mps``, ``dmrg``,
-``rsvd``, ``mlp``, ``bf16``, ``blocksparse``).
+Algorithm-level oracles live in the sibling modules: ``mps`` (two-site
+update, open-chain sweep), ``dmrg`` (effective Hamiltonian, Lanczos),
+``rsvd`` (randomized truncated SVD), ``mlp`` (sketch-rank network), ``bf16``
+(split-BF16x3 emulation), ``u1`` (U(1) block-sparse update), ``itebd``,
+``subtensor`` and ``bp``.
 """
 from __future__ import annotations
 

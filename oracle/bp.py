@@ -25,9 +25,23 @@ Conventions (shared by the GPU driver only through this description):
         V_i <- V_i . X^{-T} U_chi S_chi^{1/2},
         V_j <- V_j . Y^{-T} conj(V_chi) S_chi^{1/2},
     so that (X^{-T} U S^{1/2})(Y^{-T} conj(V) S^{1/2})^T = X^{-T} R Y^{-1} = I
-    when nothing is cut; inverse square roots drop eigenvalues below
-    1e-10 of the largest, and singular values below 1e-6 of the largest
-    are no bond directions (rounding lifted by the inverse square roots);
+    when nothing is cut.  Two thresholds follow from the FP64 arithmetic
+    of these steps (the paper fixes neither):
+      - the messages come out of sums of products, so their entries carry
+        relative rounding of about 10 u (u = 2^-53) and, by Weyl's bound,
+        their eigenvalues an absolute error delta ~ 10 u w_max; the inverse
+        square root turns it into a relative error delta / (2 w), so only
+        the eigen-directions with w > INV_SQRT_CUT * w_max = 1e-10 w_max
+        are inverted, where that error stays below about 5e-6;
+      - R = X^T Y carries an absolute rounding of about u ||X|| ||Y||,
+        and the regauged bond X^{-T} R Y^{-1} multiplies it by
+        ||X^{-1}|| ||Y^{-1}||, up to INV_SQRT_CUT^-1 = 1e10 relative to the
+        largest scale: rounding can reach 1e10 u ~ 1e-6 of s_0 there.  A
+        singular value of R below SV_CUT * s_0 = 1e-6 s_0 is therefore not a
+        bond direction that FP64 resolves after the regauging, and is cut
+        (the relative form of trunc_svd's rule (a), s_i < s_min, with
+        s_min = SV_CUT * s_0).  sv_cut is an argument, so a caller can ask
+        for a smaller floor;
   * a two-site gate G[s_i, s_j, s_i', s_j'] on edge (i, j) enters as a
     tensor-network operator: G reshaped (s_i s_i') x (s_j s_j') is split by
     an SVD into O_i[s_i, s_i', k] (U sqrt(S)) and O_j[s_j, s_j', k]
@@ -39,7 +53,7 @@ from __future__ import annotations
 import numpy as np
 
 INV_SQRT_CUT = 1e-10   # message eigenvalues kept by the inverse square root (relative)
-SV_CUT = 1e-6          # singular values of R kept as bond directions (relative)
+SV_CUT = 1e-6          # default floor of the singular values of R kept as bond directions (relative)
 
 
 # ------------------------------------------------------------------ graphs
@@ -173,14 +187,15 @@ def _apply_on_bond(v, pos, mat):
     return np.moveaxis(out, -1, axis)
 
 
-def truncate_edge(i, j, V, M, nb, chi):
-    """App. B message-SVD truncation of bond (i, j); returns the kept
-    singular values (descending) and updates V_i, V_j in place."""
+def truncate_edge(i, j, V, M, nb, chi, sv_cut=SV_CUT):
+    """App. B message-SVD truncation of bond (i, j): at most chi values,
+    none below sv_cut * s_0; returns the kept singular values (descending)
+    and updates V_i, V_j in place."""
     X, Xi = _sqrt_and_inv(M[(i, j)])
     Y, Yi = _sqrt_and_inv(M[(j, i)])
     R = X.T @ Y
     u, s, vh = np.linalg.svd(R)
-    k = min(chi, int(np.sum(s > SV_CUT * s[0])) if s[0] > 0 else 1)
+    k = min(chi, int(np.sum(s > sv_cut * s[0])) if s[0] > 0 else 1)
     k = max(k, 1)
     u, s, vh = u[:, :k], s[:k], vh[:k]
     rs = np.sqrt(s)
@@ -217,7 +232,7 @@ def apply_gate_operator(i, j, gate, V, nb):
         V[site] = w.reshape(shp)
 
 
-def apply_layer(n, edges, V, gates, chi, bp_iters):
+def apply_layer(n, edges, V, gates, chi, bp_iters, sv_cut=SV_CUT):
     """One TNO layer (App. B): attach the gates of `gates` ({edge: 4x4x...}),
     converge BP with a fixed number of sweeps, then truncate every gated
     bond to chi.  Returns the BP messages used and the kept spectra."""
@@ -227,7 +242,7 @@ def apply_layer(n, edges, V, gates, chi, bp_iters):
     M, _ = bp_run(n, edges, V, iters=bp_iters)
     spectra = {}
     for (i, j) in gates:
-        spectra[(i, j)] = truncate_edge(i, j, V, M, nb, chi)
+        spectra[(i, j)] = truncate_edge(i, j, V, M, nb, chi, sv_cut)
     return M, spectra
 
 

@@ -449,3 +449,57 @@ def test_heisenberg_chain_exact_energy_and_mpo():
         op = np.einsum("vST,vust->uSsTt", op, w).reshape(5, op.shape[1] * 2, op.shape[2] * 2)
     dense = op[0]
     np.testing.assert_allclose(dense, od.heisenberg_chain_dense(n), atol=1e-14)
+
+
+def test_philox_normal_box_muller_pairs_from_known_answer_block():
+    """Key (0, 0), counter (0, 0, 0, 0) is the first published known-answer
+    block (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8).  Each normal pair
+    (z0, z1) of the block is a point in the plane with squared radius
+    -2 ln u1 and angle 2 pi u2, where u = (x + 1/2) 2^-32 maps the words
+    (x0, x1) and (x2, x3) into (0, 1)."""
+    import math
+    words = [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    z = oracle.philox_normal(0, 0, 4)
+    for p in range(2):
+        u1 = (words[2 * p] + 0.5) / 2.0 ** 32
+        u2 = (words[2 * p + 1] + 0.5) / 2.0 ** 32
+        z0, z1 = z[2 * p], z[2 * p + 1]
+        assert z0 * z0 + z1 * z1 == pytest.approx(-2.0 * math.log(u1), rel=1e-14)
+        ang = math.atan2(z1, z0) % (2.0 * math.pi)
+        assert ang == pytest.approx(2.0 * math.pi * u2, rel=1e-13)
+
+
+def test_philox_normal_distribution():
+    """Kolmogorov-Smirnov tests: the normals against N(0, 1), the halved
+    squared radii of the pairs against Exp(1), the pair angles against
+    U(0, 2 pi)."""
+    from scipy import stats
+    z = oracle.philox_normal(251223917, 3, 200000)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    pairs = z.reshape(-1, 2)
+    assert stats.kstest(0.5 * (pairs ** 2).sum(1), "expon").pvalue > 1e-3
+    ang = np.arctan2(pairs[:, 1], pairs[:, 0]) % (2 * np.pi)
+    assert stats.kstest(ang, "uniform", args=(0.0, 2 * np.pi)).pvalue > 1e-3
+
+
+def test_vidal_write_back_reconstructs_theta():
+    """Vidal form (App. A): with Gamma_A = Lambda_l^-1 U, Gamma_B = V^dagger
+    Lambda_r^-1 and Lambda = s / ||s||, the chain Lambda_l Gamma_A Lambda
+    Gamma_B Lambda_r reproduces theta' / ||theta'||_F when nothing is cut,
+    and Lambda_l Gamma_A has orthonormal columns (Lambda_l^2-weighted
+    left-canonical condition)."""
+    g = np.random.default_rng(31)
+    chi = 5
+    a = synth.complex_gaussian(g, (chi, 2, chi))
+    b = synth.complex_gaussian(g, (chi, 2, chi))
+    gate = synth.haar_gate(g)
+    lam_l = np.sort(g.uniform(0.1, 1.0, chi))[::-1]
+    lam_r = np.sort(g.uniform(0.1, 1.0, chi))[::-1]
+    r = mps.two_site_update(a, b, gate, 1, 2 * chi, 0.0, 0.0, mps.VIDAL, lam_left=lam_l, lam_right=lam_r)
+    rec = np.einsum("a,asm,m,mtb,b->astb", lam_l, r["a_out"], r["s"], r["b_out"], lam_r)
+    th = r["theta"]
+    np.testing.assert_allclose(rec, th / np.linalg.norm(th), atol=1e-13)
+    left = (lam_l[:, None, None] * r["a_out"]).reshape(2 * chi, -1)
+    np.testing.assert_allclose(left.conj().T @ left, np.eye(left.shape[1]), atol=1e-13)
+    right = (r["b_out"] * lam_r[None, None, :]).reshape(left.shape[1], -1)
+    np.testing.assert_allclose(right @ right.conj().T, np.eye(left.shape[1]), atol=1e-13)

@@ -105,3 +105,41 @@ def test_gate_split_reproduces_the_gate():
     back = np.einsum("aik,bjk->abij", oi, oj)
     assert np.abs(back - g).max() < 1e-14
     assert oi.shape[2] <= 4
+
+
+def _graded_tree(seed=4):
+    """Tree patch whose bond (4, 5) has dimension 4 with weights
+    (1, 1e-1, 1e-2, 1e-4) on both of its site tensors: the singular values of
+    R on that bond reach ~1e-9 of the largest, the message eigenvalues stay
+    above the inverse-square-root cut."""
+    n, edges = bp.heavy_hex_patch()
+    tree = tree_of(n, edges)
+    nb = bp.neighbours(n, tree)
+    g = np.random.default_rng(seed)
+    dims = {e: 2 for e in tree}
+    dims[(4, 5)] = 4
+    V = [synth.complex_gaussian(g, (2,) + tuple(dims[tuple(sorted((i, k)))] for k in nb[i])) for i in range(n)]
+    lam = np.array([1.0, 1e-1, 1e-2, 1e-4])
+    for site, other in ((4, 5), (5, 4)):
+        p = nb[site].index(other)
+        V[site] = np.moveaxis(np.moveaxis(V[site], 1 + p, -1) * lam, -1, 1 + p)
+    return n, tree, nb, V
+
+
+def test_regauge_exact_with_graded_bond_when_nothing_is_cut():
+    """With a singular-value floor below the bond's smallest value the
+    regauging keeps the state exactly; the default floor cuts the ~1e-9
+    direction and changes the state by about that much."""
+    n, tree, nb, V = _graded_tree()
+    psi = bp.state_vector(n, tree, V)
+    M, _ = bp.bp_run(n, tree, V, tol=1e-15)
+    Vk = [v.copy() for v in V]
+    s = bp.truncate_edge(4, 5, Vk, M, nb, 16, sv_cut=1e-12)
+    assert len(s) == 4 and 1e-10 < s[-1] / s[0] < 1e-8
+    out = bp.state_vector(n, tree, Vk)
+    assert np.linalg.norm(out - psi) / np.linalg.norm(psi) < 1e-12
+    Vc = [v.copy() for v in V]
+    s6 = bp.truncate_edge(4, 5, Vc, M, nb, 16)
+    assert len(s6) == 3
+    out6 = bp.state_vector(n, tree, Vc)
+    assert 1e-10 < np.linalg.norm(out6 - psi) / np.linalg.norm(psi) < 1e-7
