@@ -15,7 +15,11 @@ Conventions:
     R = X^T Y = U S V^H, and the bond matrices X^{-T} U S^{1/2} (on V_i) and
     Y^{-T} conj(V) S^{1/2} (on V_j), kept to the chi largest singular
     values; inverse square roots drop eigenvalues below 1e-10 of the
-    largest, and singular values below 1e-6 of the largest are dropped;
+    largest (their relative error from FP64 rounding would exceed ~5e-6),
+    and singular values below sv_cut (default 1e-6) of the largest are not
+    bond directions (FP64 rounding of R, amplified up to 1e10 by the two
+    inverse square roots, reaches that level); the SVD of R runs on the
+    library's one-sided Jacobi path, which resolves its small values;
   * a gate G[s_i, s_j, s_i', s_j'] is split by an SVD of its
     (s_i s_i') x (s_j s_j') matrix into O_i U S^{1/2} and O_j (S^{1/2} V^H)^T,
     whose shared index becomes the faster half of the bond (i, j).
@@ -32,7 +36,7 @@ import numpy as np
 from . import tci
 
 INV_SQRT_CUT = 1e-10   # message eigenvalues kept by the inverse square root (relative)
-SV_CUT = 1e-6          # singular values of R kept as bond directions (relative)
+SV_CUT = 1e-6          # default floor of the singular values of R kept as bond directions (relative)
 S_LABEL, KET, BRA, NEW, GATE = 1, 100, 200, 300, 400
 
 
@@ -129,14 +133,14 @@ class BPState:
         out = [NEW if x == KET + pos else x for x in lab]
         return tci.contract(self.ctx, self.V[i], lab, mat, [KET + pos, NEW], out)
 
-    def truncate_edge(self, i, j, chi: int) -> np.ndarray:
+    def truncate_edge(self, i, j, chi: int, sv_cut: float = SV_CUT) -> np.ndarray:
         c = self.ctx
         X, Xi = self._sqrt_and_inv(self.M[(i, j)])
         Y, Yi = self._sqrt_and_inv(self.M[(j, i)])
         R = tci.contract(c, X, "ab", Y, "ac", "bc")
         u, s, vh = tci.svd(c, R, 1)
         sv = s.numpy().copy()
-        k = max(1, min(chi, int(np.sum(sv > SV_CUT * sv[0])) if sv[0] > 0 else 1))
+        k = max(1, min(chi, int(np.sum(sv > sv_cut * sv[0])) if sv[0] > 0 else 1))
         d = sv.shape[0]
         u = tci.extract_sub(c, u, [(0, d), (0, k)])
         vh = tci.extract_sub(c, vh, [(0, k), (0, d)])
@@ -177,11 +181,11 @@ class BPState:
             del shp[2 + pos]
             self.V[site] = tci.reshape(c, w, shp)
 
-    def apply_layer(self, gates: dict, chi: int, bp_iters: int) -> dict:
+    def apply_layer(self, gates: dict, chi: int, bp_iters: int, sv_cut: float = SV_CUT) -> dict:
         """Attach the gates ({(i, j): 4x4 matrix}), run bp_iters BP sweeps
         from identity messages, truncate every gated bond to chi; returns the
         kept singular values per bond."""
         for (i, j), g in gates.items():
             self.apply_gate(i, j, g)
         self.run_bp(bp_iters)
-        return {e: self.truncate_edge(e[0], e[1], chi) for e in gates}
+        return {e: self.truncate_edge(e[0], e[1], chi, sv_cut) for e in gates}

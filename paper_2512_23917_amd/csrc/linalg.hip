@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, lo
                                                            const double* total, TruncParams p, int* chi_out,
                                                            double* err_out, double* disc_out, double* s_out,
                                                            double* sinv_out, double* sn_out, long long ss,
-                                                           int batch) {
+                                                           int batch, int sv_input) {
   __shared__ double s_scan[256];
   __shared__ int s_red[256];
   __shared__ double s_kept;
@@ -132,7 +132,10 @@ __global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, lo
   if (b >= batch) return;
   const double* l = lam + b * slam;
   const double W = total[b];
-  auto wt = [&](int j) { return fmax(l[j], 0.0); };
+  // lam holds eigenvalues of the Gram matrix (s_j^2), or the singular
+  // values themselves when sv_input is set
+  auto wt = [&](int j) { return sv_input ? l[j] * l[j] : fmax(l[j], 0.0); };
+  auto sval = [&](int j) { return sv_input ? l[j] : sqrt(fmax(l[j], 0.0)); };
   auto eps_of = [&](double kept_w) { return W > 0.0 ? fmax(W - kept_w, 0.0) / W : 0.0; };
   auto block_min = [&](int v) {
     __syncthreads();
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, lo
   // n_a: number of leading values with s_j >= s_min
   int bad = kmax;
   for (int j = tid; j < kmax; j += 256)
-    if (sqrt(wt(j)) < p.s_min) bad = min(bad, j);
+    if (sval(j) < p.s_min) bad = min(bad, j);
   const int n_a = block_min(bad);
   // exclusive scan of the chunk sums
   const int chunk = (kmax + 255) / 256;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, lo
     disc_out[b] = eps * W;
   }
   for (int j = tid; j < kmax; j += 256) {
-    const double sj = j < chi ? sqrt(wt(j)) : 0.0;
+    const double sj = j < chi ? sval(j) : 0.0;
     s_out[b * ss + j] = sj;
     sinv_out[b * ss + j] = sj > 0.0 ? 1.0 / sj : 0.0;
     sn_out[b * ss + j] = nrm > 0.0 ? sj / nrm : 0.0;
@@ -208,10 +211,10 @@ __global__ __launch_bounds__(256) void trunc_select_kernel(const double* lam, lo
 
 hipError_t trunc_select(const double* lam, long long slam, int kmax, const double* total,
                         const TruncParams& p, int* chi, double* err, double* disc, double* s,
-                        double* sinv, double* sn, long long ss, int batch, hipStream_t st) {
+                        double* sinv, double* sn, long long ss, int batch, hipStream_t st, bool sv_input) {
   if (batch <= 0 || kmax <= 0) return hipSuccess;
   hipLaunchKernelGGL(trunc_select_kernel, dim3(batch), dim3(256), 0, st, lam, slam, kmax, total, p, chi, err, disc,
-                     s, sinv, sn, ss, batch);
+                     s, sinv, sn, ss, batch, sv_input ? 1 : 0);
   return hipGetLastError();
 }
 

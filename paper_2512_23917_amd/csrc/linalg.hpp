@@ -30,7 +30,8 @@ hipError_t gate_apply(int dtype, void* theta, long long stheta, const void* gate
 
 hipError_t trunc_select(const double* lam, long long slam, int kmax, const double* total,
                         const TruncParams& p, int* chi, double* err, double* disc, double* s,
-                        double* sinv, double* sn, long long ss, int batch, hipStream_t st);
+                        double* sinv, double* sn, long long ss, int batch, hipStream_t st,
+                        bool sv_input = false);
 
 hipError_t gauge_columns(int dtype, void* U, long long ldu, long long sU, int m, int ncol,
                          const int* chi, int batch, hipStream_t s);

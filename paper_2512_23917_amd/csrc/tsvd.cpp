@@ -21,6 +21,7 @@
 #include "eig.hpp"
 #include "gaussjordan.hpp"
 #include "gemm.hpp"
+#include "jacobi.hpp"
 #include "linalg.hpp"
 #include "prof.hpp"
 #include "runtime.hpp"
@@ -248,6 +249,48 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   return tsvd_vectors(ctx, st, chi, kz, sinv, out);
 }
 
+// trunc_svd of one small matrix (min(m, n) <= JACOBI_MAX_K) by one-sided
+// Jacobi rotations on the matrix itself, so that singular values far below
+// the largest are resolved (the Gram route squares the condition number).
+// Fills the fields of `out` that tci_trunc_svd reads: U (m x k, ld k), Vh
+// (k x n), s, chi and the host copies.
+static tci_status tsvd_small(tci_context ctx, int wdt, int m, int n, const void* theta, const TruncParams& tp,
+                             TsvdOut& out) {
+  hipStream_t s = ctx->stream;
+  const size_t es = elem_bytes(wdt);
+  const int k = std::min(m, n);
+  ARENA(work, char, es * jacobi_work_elems(std::max(m, n), k));
+  ARENA(U, char, es * (size_t)m * k);
+  ARENA(Vh, char, es * (size_t)k * n);
+  ARENA(sraw, double, k);
+  ARENA(sweeps, int, 1);
+  ARENA(total, double, 1);
+  ARENA(partial, double, SUMSQ_PARTIALS);
+  TCI_CHECK_HIP(sumsq_batched(wdt, theta, (long long)m * n, 0, total, partial, 1, s));
+  TCI_CHECK_HIP(jacobi_svd(wdt, theta, n, 0, m, n, work, U, 0, Vh, 0, sraw, 0, sweeps, 1, s));
+  ARENA(chi, int, 1);
+  ARENA(err, double, 1);
+  ARENA(disc, double, 1);
+  ARENA(sv, double, k);
+  ARENA(sinv, double, k);
+  ARENA(sn, double, k);
+  TCI_CHECK_HIP(trunc_select(sraw, k, k, total, tp, chi, err, disc, sv, sinv, sn, k, 1, s, true));
+  int sw = 0;
+  out.chi_h.resize(1); out.err_h.resize(1); out.disc_h.resize(1); out.total_h.resize(1);
+  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), total, sizeof(double), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(out.total_h[0])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in the matrix");
+  if (sw < 0) TCI_RET(TCI_ERR_NOT_CONVERGED, "Jacobi SVD did not converge in 80 sweeps");
+  out.kmax = k; out.kz = k;
+  out.U = U; out.Vh = Vh;
+  out.chi = chi; out.s = sv; out.sn = sn; out.total = total;
+  return TCI_OK;
+}
+
 static tci_status matricize(tci_tensor a, int k_rows, int64_t& rows, int64_t& cols) {
   if (k_rows < 1 || k_rows >= a->order) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= k_rows < order");
   rows = 1;
@@ -451,7 +494,8 @@ tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u
   TruncParams tp{(int)std::min<int64_t>(chi_min, kap), (int)std::min<int64_t>(chi_max, kap), target_trunc_err, s_min};
   if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
   TsvdOut o;
-  TCI_TRY(tsvd_run(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
+  if (kap <= JACOBI_MAX_K) TCI_TRY(tsvd_small(ctx, wdt, (int)rows, (int)cols, w, tp, o));
+  else TCI_TRY(tsvd_run(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
   const int chi = o.chi_h[0];
   // outputs
   int64_t ushape[MAX_ORDER + 1];

@@ -91,3 +91,38 @@ def test_gate_layers_match_oracle(ctx, chi):
         fid = abs(np.vdot(psi, out)) / (np.linalg.norm(psi) * np.linalg.norm(out))
         assert 0.5 < fid < 1.0
     print(f"BP layer (5 gates, 10 sweeps, chi={chi}): {dt * 1e3:.1f} ms")
+
+
+def test_graded_bond_resolved_by_the_library_svd(ctx):
+    """A tree bond whose R has singular values down to ~1e-9 of the largest:
+    the library's SVD of R (one-sided Jacobi) resolves them, so the kept
+    spectrum matches the oracle to 1e-12 of s_0 and, with a floor below the
+    smallest value, the regauged state is the exact one."""
+    from paper_2512_23917_amd import bp
+    n, edges = obp.heavy_hex_patch()
+    tree = [e for e in edges if e != (0, 11)]
+    nb = obp.neighbours(n, tree)
+    g = np.random.default_rng(4)
+    dims = {e: 2 for e in tree}
+    dims[(4, 5)] = 4
+    V = [synth.complex_gaussian(g, (2,) + tuple(dims[tuple(sorted((i, k)))] for k in nb[i])) for i in range(n)]
+    lam = np.array([1.0, 1e-1, 1e-2, 1e-4])
+    for site, other in ((4, 5), (5, 4)):
+        p = nb[site].index(other)
+        V[site] = np.moveaxis(np.moveaxis(V[site], 1 + p, -1) * lam, -1, 1 + p)
+    psi = obp.state_vector(n, tree, V)
+    for cut in (1e-12, 1e-6):
+        st = bp.BPState(ctx, n, tree, V)
+        st.run_bp(30)
+        s = st.truncate_edge(4, 5, 16, sv_cut=cut)
+        Vo = [v.copy() for v in V]
+        M, _ = obp.bp_run(n, tree, Vo, iters=30)
+        so = obp.truncate_edge(4, 5, Vo, M, nb, 16, cut)
+        assert s.shape == so.shape
+        assert np.abs(s - so).max() < 1e-12 * so[0], (cut, s, so)
+        out = obp.state_vector(n, tree, st.host_tensors())
+        ref = obp.state_vector(n, tree, Vo)
+        assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-9
+        if cut == 1e-12:
+            assert len(s) == 4
+            assert np.linalg.norm(out - psi) / np.linalg.norm(psi) < 1e-9

@@ -147,6 +147,57 @@ def test_svd_full_matches_oracle(T, ctx, m, n, complex_):
     _svd_parity(u.numpy(), s.numpy(), vh.numpy(), a, min(m, n))
 
 
+@pytest.mark.parametrize("m,n", [(48, 40), (40, 48), (64, 64)])
+def test_svd_small_graded_spectrum(T, ctx, m, n):
+    """Matrices with k = min(m, n) <= 64 take the one-sided Jacobi path: a
+    spectrum graded from 1 down to 1e-13 is resolved to an absolute error of
+    a few ulps of s_0 (the Gram route would lose everything below ~1e-8)."""
+    g = np.random.default_rng(m + 3 * n)
+    k = min(m, n)
+    sv = np.logspace(0, -13, k)
+    u0 = synth.haar(g, m, k)
+    v0 = synth.haar(g, n, k)
+    a = (u0 * sv) @ v0.conj().T
+    u, s, vh = T.svd(ctx, up(T, ctx, a, T.C128), 1)
+    s = s.numpy()
+    assert np.abs(s - sv).max() < 1e-13
+    assert np.all(np.abs(s - sv)[sv >= 1e-9] <= 1e-4 * sv[sv >= 1e-9])
+    _, so, _ = oracle.svd_matrix(a)
+    assert np.abs(s - so).max() < 1e-13
+    um, vm = u.numpy().reshape(m, k), vh.numpy().reshape(k, n)
+    assert isometry_err(um) < 1e-12 and isometry_err(vm, axis_cols=False) < 1e-12
+    assert rel_fro(um @ np.diag(s) @ vm, a) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,exact_zero", [(30, 20, False), (20, 30, False), (30, 20, True), (20, 30, True)])
+def test_svd_small_rank_deficient(T, ctx, m, n, exact_zero):
+    """Rank 7: rounding-level singular values keep orthonormal vectors; and
+    with exactly zero columns (tall) or rows (wide) the zero singular values
+    get an orthonormal completion of their singular vectors (on u for tall
+    matrices, on the rows of v^dagger for wide ones)."""
+    g = np.random.default_rng(m * n + exact_zero)
+    if exact_zero:
+        a = cg(g, (m, n))
+        if m >= n:
+            a[:, [2, 5, 11, 12, 19]] = 0.0
+        else:
+            a[[2, 5, 11, 12, 19], :] = 0.0
+    else:
+        a = cg(g, (m, 7)) @ cg(g, (7, n))
+    rank = 15 if exact_zero else 7
+    u, s, vh = T.svd(ctx, up(T, ctx, a, T.C128), 1)
+    k = min(m, n)
+    s = s.numpy()
+    _, so, _ = oracle.svd_matrix(a)
+    assert np.abs(s - so).max() < 1e-12 * so[0]
+    assert np.all(s[rank:] < 1e-13 * s[0])
+    if exact_zero:
+        assert np.all(s[rank:] == 0.0)
+    um, vm = u.numpy().reshape(m, k), vh.numpy().reshape(k, n)
+    assert isometry_err(um) < 1e-12 and isometry_err(vm, axis_cols=False) < 1e-12
+    assert rel_fro(um @ np.diag(s) @ vm, a) < 1e-13
+
+
 @pytest.mark.parametrize("chi_min,chi_max,target,s_min", [(1, 40, 0.0, 0.0), (1, 200, 1e-3, 0.0),
                                                          (5, 60, 0.5, 0.0), (1, 200, 0.0, 0.5)])
 def test_trunc_svd_rule_matches_oracle(T, ctx, chi_min, chi_max, target, s_min):
