@@ -83,8 +83,12 @@ struct cplx_of<std::complex<R>> { using type = std::complex<R>; };
 class Context {
  public:
   Context() = default;
-  explicit Context(int device, void* hip_stream = nullptr) : stream_(hip_stream) {
-    detail::check(tci_create_context(&h_, device, hip_stream), "tci_create_context");
+  // opts: the implementation-defined parameters of create_context
+  // (allocator, precision, svd mode, autotune cache, verbosity); nullptr =
+  // the defaults.
+  explicit Context(int device, void* hip_stream = nullptr, const tci_context_opts* opts = nullptr)
+      : stream_(hip_stream) {
+    detail::check(tci_create_context(&h_, device, hip_stream, opts), "tci_create_context");
   }
   Context(const Context&) = delete;
   Context& operator=(const Context&) = delete;
@@ -702,21 +706,13 @@ void lq(context_handle_t<TenT>& ctx, const TenT& a, const order_t<TenT> num_of_b
 template <typename TenT>
 void eigh(context_handle_t<TenT>& ctx, const TenT& a, const order_t<TenT> num_of_bds_as_row, real_ten_t<TenT>& w,
           TenT& v) {
-  const auto s = shape(ctx, a);
-  std::int64_t rows = 1, cols = 1;
-  for (int b = 0; b < (int)s.size(); ++b) (b < num_of_bds_as_row ? rows : cols) *= s[b];
-  const std::int64_t m[2] = {rows, cols};
-  TenT mat;
-  detail::check(tci_reshape(ctx.get(), a.handle(), 2, m, mat.out_handle(ctx.get())), "tci_reshape");
-  detail::check(tci_eigh(ctx.get(), mat.handle(), w.out_handle(ctx.get()), v.out_handle(ctx.get())), "tci_eigh");
-  shape_t<TenT> vs(s.begin(), s.begin() + num_of_bds_as_row);
-  vs.push_back(rows);
-  reshape(ctx, v, vs);
+  detail::check(tci_eigh(ctx.get(), a.handle(), num_of_bds_as_row, w.out_handle(ctx.get()), v.out_handle(ctx.get())),
+                "tci_eigh");
 }
+// Eigenvalues only, ascending.
 template <typename TenT>
 void eigvalsh(context_handle_t<TenT>& ctx, const TenT& a, const order_t<TenT> num_of_bds_as_row, real_ten_t<TenT>& w) {
-  TenT v;
-  eigh(ctx, a, num_of_bds_as_row, w, v);
+  detail::check(tci_eigvalsh(ctx.get(), a.handle(), num_of_bds_as_row, w.out_handle(ctx.get())), "tci_eigvalsh");
 }
 
 // ---------------------------------------------------------------- miscellaneous (Spec)

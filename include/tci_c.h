@@ -50,6 +50,7 @@ typedef int32_t tci_status;
 #define TCI_ERR_NOT_CONVERGED 7
 #define TCI_ERR_NUMERIC 8           /* NaN / Inf where a finite value is required */
 #define TCI_ERR_UNSUPPORTED 9
+#define TCI_ERR_INTERNAL 10         /* an unexpected C++ exception inside the library (never escapes) */
 
 typedef enum { TCI_F32 = 0, TCI_F64 = 1, TCI_C64 = 2, TCI_C128 = 3 } tci_dtype;
 
@@ -68,7 +69,9 @@ typedef enum {
 /* Write-back of the factors after the two-site update. */
 typedef enum {
   TCI_DIR_LEFT = 0,   /* A' = U,            B' = diag(s) V^dagger  (centre moves right) */
-  TCI_DIR_RIGHT = 1   /* A' = U diag(s),    B' = V^dagger          (centre moves left)  */
+  TCI_DIR_RIGHT = 1,  /* A' = U diag(s),    B' = V^dagger          (centre moves left)  */
+  TCI_DIR_VIDAL = 2   /* A' = diag(1/lambda_l) U,  B' = V^dagger diag(1/lambda_r): the Gamma
+                         tensors of the Vidal form (App. A); s is the new Lambda */
 } tci_direction;
 
 typedef struct tci_context_s* tci_context;
@@ -91,13 +94,49 @@ const char* tci_last_error(void);
 /* destroy_context)                                                     */
 /* ------------------------------------------------------------------ */
 
+/* Device-memory allocator of a context.  Every device buffer the library
+ * allocates for the context (tensor storage, block-sparse storage, sketch
+ * models, workspace chunks) comes from alloc and goes back through free with
+ * the same size; hip_stream is the context's stream at that moment.  alloc
+ * returns NULL on failure, and the call that needed the memory then fails
+ * with TCI_ERR_OUT_OF_MEMORY.  Workspace is requested in chunks of at least
+ * 256 MiB and kept until the context is destroyed.  alloc and free are both
+ * set or both NULL (NULL: hipMalloc / hipFree). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* hip_stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* hip_stream, void* user);
+  void* user;
+} tci_allocator;
+
+/* Implementation-defined parameters of create_context (Spec, miscellaneous
+ * routines: create_context names allocators and logging flags as examples). */
+typedef struct {
+  tci_allocator allocator;
+  int32_t precision;          /* tci_precision of F32 / C64 contractions; -1: TCI_PREC_FP32 */
+  int32_t svd_mode;           /* tci_svd_mode of tci_trunc_svd and of the update composites called
+                                 with params NULL: TCI_SVD_PLAIN, or TCI_SVD_RANDOMIZED (a sketch of
+                                 rank chi_max + 64 rounded up to 32, two power iterations, kept only
+                                 when the discarded weight meets a positive target and the residual
+                                 certificate holds; the plain SVD otherwise).  TCI_SVD_LEARNED needs
+                                 per-call spectra and a model, so it is set in tci_update_params */
+  const char* autotune_cache; /* file of tuned grouped-GEMM tile shapes: read when the context is
+                                 created (a missing file is not an error), rewritten when it is
+                                 destroyed; NULL: no file.  The string is copied. */
+  int32_t verbosity;          /* 0, 1, 2 as TCI_VERBOSE; -1: from the environment */
+} tci_context_opts;
+
+/* Defaults: no allocator, precision -1, TCI_SVD_PLAIN, no cache, verbosity -1. */
+void tci_context_opts_default(tci_context_opts* opts);
+
 /* Create a context on HIP device `device_id` whose work is ordered on
  * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The
- * stream is borrowed.  The environment variable TCI_VERBOSE (0, 1, 2;
- * Spec, environment variables) selects per-call logging to stderr; level 2
+ * stream is borrowed.  opts may be NULL (the defaults above).  The
+ * environment variable TCI_VERBOSE (0, 1, 2; Spec, environment variables)
+ * selects per-call logging to stderr unless opts->verbosity >= 0; level 2
  * adds wall time and synchronises after each call.
- * Errors: TCI_ERR_INVALID_ARGUMENT (out NULL), TCI_ERR_DEVICE. */
-tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream);
+ * Errors: TCI_ERR_INVALID_ARGUMENT (out NULL, only one of alloc / free set,
+ * bad precision, svd mode or verbosity), TCI_ERR_DEVICE. */
+tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream, const tci_context_opts* opts);
 
 /* Release the context, its workspace and every cached resource.  Tensors
  * must be destroyed before their context. */
@@ -376,10 +415,19 @@ tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor ou
  * (I <= J; TCI_ERR_UNSUPPORTED otherwise).  Synchronous. */
 tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_tensor q);
 
-/* Spec, eigh: Hermitian matrix (order 2, square; only the values are read
- * as given, no symmetrisation) -> w (ascending, real FP64) and v (columns =
- * eigenvectors, gauge as in tci_svd).  Double types only.  Synchronous. */
-tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v);
+/* Spec, eigh: the tensor matricised with its first k_rows bonds as rows
+ * (1 <= k_rows < order; I = prod d_0..d_{k-1} must equal J = prod d_k..) is
+ * read as a Hermitian matrix (as given, no symmetrisation)
+ * -> w (I eigenvalues ascending, real: F64 for F64/C128, F32 for F32/C64)
+ * and v {d_0, .., d_{k-1}, I} in a's dtype whose last bond indexes the
+ * eigenvectors (gauge as in tci_svd).  Single-precision inputs are solved in
+ * FP64 and rounded.  FP64 Householder tridiagonalisation, bisection, inverse
+ * iteration and back-transformation on the GPU.  Synchronous.
+ * Errors: TCI_ERR_INVALID_ARGUMENT (k_rows), TCI_ERR_SHAPE (I != J). */
+tci_status tci_eigh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v);
+
+/* Spec, eigvalsh: the eigenvalues of tci_eigh only (no vectors are formed). */
+tci_status tci_eigvalsh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w);
 
 /* Spec, close: *result = 1 iff max |a - b| <= eps elementwise (same shape
  * and dtype), else 0.  Synchronous. */
@@ -407,6 +455,9 @@ typedef struct {
   void* sketch_model;       /* tci_sketch_model for TCI_SVD_LEARNED */
   const tci_tensor* prev_spectra; /* TCI_SVD_LEARNED: per update, the bond's spectrum before the
                                      update (F64 vector, descending); indexed like A / theta */
+  const tci_tensor* lambda_left;  /* TCI_DIR_VIDAL: per update, the outer bond weights on the left
+                                     (F64 vector of chi_l entries, all > 0); indexed like A */
+  const tci_tensor* lambda_right; /* TCI_DIR_VIDAL: the same on the right (chi_r entries) */
 } tci_update_params;
 
 typedef struct {
@@ -420,7 +471,8 @@ typedef struct {
 } tci_update_info;
 
 /* Fill `p` with defaults: chi_min 1, chi_max INT64_MAX, target 0, s_min 0,
- * RIGHT, FP64, PLAIN, sketch 0, q 2, max_batch 0, seed 0, cert 1e-7. */
+ * RIGHT, FP64, PLAIN, sketch 0, q 2, max_batch 0, seed 0, cert 1e-7, no
+ * model, spectra or Vidal weights. */
 void tci_update_params_default(tci_update_params* p);
 
 /* n independent two-site updates.  A[i] has shape (chi_l, d, chi_m), B[i]
@@ -438,6 +490,15 @@ tci_status tci_two_site_update_batched(tci_context ctx, int n, const tci_tensor*
                                        const tci_update_params* params, tci_tensor* A_out,
                                        tci_tensor* s_out, tci_tensor* B_out,
                                        tci_update_info* infos);
+
+/* One two-site update (the Application A listing: theta = contract(A, B),
+ * gate, trunc_svd, normalize, then the write-back of params->direction):
+ * tci_two_site_update_batched with n = 1.  gate and info are nullable;
+ * params NULL means tci_update_params_default with the context's svd mode
+ * and precision (FP64 for F64/C128 tensors).  Synchronous. */
+tci_status tci_two_site_update(tci_context ctx, tci_tensor A, tci_tensor B, tci_tensor gate,
+                               const tci_update_params* params, tci_tensor A_out, tci_tensor s_out,
+                               tci_tensor B_out, tci_update_info* info);
 
 /* The second half of the update for given two-site tensors: theta[i] of
  * shape (chi_l, d, d, chi_r) (all i the same shape and dtype) is split by
@@ -544,8 +605,9 @@ tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_t
  *   [log2(chi_max)/11, d/4, -log10(eps)/16, 32 clamped log10 quantiles
  *    q_t = clamp(log10(s_j/s_0)/16, -1, 0), j = floor((t+1/2)/32 (len-1))]
  * of the bond's previous spectrum s.  The update uses the sketch rank
- * k = min(n, 32 ceil((2^y 1.1 + 16)/32)) and the plain truncated SVD when
- * y > log2(chi_max).  Parameters are FP32, flat: W1 (128x35), b1, W2
+ * k = 32 ceil((1.5 * 2^y + 32)/32) and the plain truncated SVD when
+ * y > log2(chi_max) or k > 0.6 min(m, n) (the sketch would then cost about
+ * as much as the plain SVD).  Parameters are FP32, flat: W1 (128x35), b1, W2
  * (128x128), b2, W3 (1x128), b3.  All data pointers below are device
  * pointers unless marked host. */
 

@@ -46,6 +46,7 @@ struct tci_bs_tensor_s {
   int64_t nelem = 0;
   void* data = nullptr;
   size_t cap = 0;
+  tci_allocator al{};  // allocator of data (the creating context's)
   uint32_t magic = 0xB5B5A11Cu;
 };
 
@@ -94,11 +95,16 @@ tci_status bs_define(tci_context ctx, tci_bs_tensor t, int dtype, const std::vec
   t->nelem = off;
   const size_t bytes = (size_t)std::max<int64_t>(off, 1) * elem_bytes(dtype);
   if (t->cap < bytes) {
-    if (t->data) TCI_CHECK_HIP(hipFree(t->data));
+    if (t->data) {
+      TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+      dev_free(t->al, t->data, t->cap, ctx->stream);
+    }
     t->data = nullptr;
     t->cap = 0;
     TCI_CHECK_HIP(hipSetDevice(ctx->device));
-    if (hipMalloc(&t->data, bytes) != hipSuccess) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "block-sparse storage");
+    t->data = dev_alloc(ctx->al, bytes, ctx->stream);
+    if (!t->data) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "block-sparse storage");
+    t->al = ctx->al;
     t->cap = bytes;
   }
   return TCI_OK;
@@ -186,7 +192,7 @@ using namespace tci;
 extern "C" {
 
 tci_status tci_bs_create(tci_context ctx, tci_dtype dtype, int n_left, const int32_t* q_left, const int64_t* d_left,
-                         int n_right, const int32_t* q_right, const int64_t* d_right, tci_bs_tensor* out) {
+                         int n_right, const int32_t* q_right, const int64_t* d_right, tci_bs_tensor* out) try {
   if (!ctx || !out || n_left < 0 || n_right < 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   if ((n_left > 0 && (!q_left || !d_left)) || (n_right > 0 && (!q_right || !d_right)))
     TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null bond arrays");
@@ -196,25 +202,27 @@ tci_status tci_bs_create(tci_context ctx, tci_dtype dtype, int n_left, const int
                             std::vector<int32_t>(q_right, q_right + n_right),
                             std::vector<int64_t>(d_right, d_right + n_right));
   if (st != TCI_OK) {
-    if (t->data) (void)hipFree(t->data);
+    if (t->data) dev_free(t->al, t->data, t->cap, ctx->stream);
     delete t;
     return st;
   }
   *out = t;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_bs_destroy(tci_context ctx, tci_bs_tensor t) {
-  (void)ctx;
+tci_status tci_bs_destroy(tci_context ctx, tci_bs_tensor t) try {
   if (!t) return TCI_OK;
   TCI_TRY(bs_check(t));
-  if (t->data) TCI_CHECK_HIP(hipFree(t->data));
+  if (t->data) {
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    dev_free(t->al, t->data, t->cap, ctx ? ctx->stream : nullptr);
+  }
   t->magic = 0;
   delete t;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_bs_dims(tci_context ctx, tci_bs_tensor t, int* n_left, int* n_right, int* n_blocks, int64_t* n_elems) {
+tci_status tci_bs_dims(tci_context ctx, tci_bs_tensor t, int* n_left, int* n_right, int* n_blocks, int64_t* n_elems) try {
   (void)ctx;
   TCI_TRY(bs_check(t));
   if (n_left) *n_left = (int)t->ql.size();
@@ -222,10 +230,10 @@ tci_status tci_bs_dims(tci_context ctx, tci_bs_tensor t, int* n_left, int* n_rig
   if (n_blocks) *n_blocks = (int)t->blocks.size();
   if (n_elems) *n_elems = t->nelem;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_bs_bonds(tci_context ctx, tci_bs_tensor t, int32_t* q_left, int64_t* d_left, int32_t* q_right,
-                        int64_t* d_right) {
+                        int64_t* d_right) try {
   (void)ctx;
   TCI_TRY(bs_check(t));
   for (size_t i = 0; i < t->ql.size(); ++i) {
@@ -237,9 +245,9 @@ tci_status tci_bs_bonds(tci_context ctx, tci_bs_tensor t, int32_t* q_left, int64
     if (d_right) d_right[i] = t->dr[i];
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_bs_block_info(tci_context ctx, tci_bs_tensor t, int i, int* a, int* s, int* b, int64_t* offset) {
+tci_status tci_bs_block_info(tci_context ctx, tci_bs_tensor t, int i, int* a, int* s, int* b, int64_t* offset) try {
   (void)ctx;
   TCI_TRY(bs_check(t));
   if (i < 0 || i >= (int)t->blocks.size()) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "block index");
@@ -249,9 +257,9 @@ tci_status tci_bs_block_info(tci_context ctx, tci_bs_tensor t, int i, int* a, in
   if (b) *b = k.b;
   if (offset) *offset = k.off;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_bs_from_host(tci_context ctx, tci_bs_tensor t, const void* host, size_t bytes) {
+tci_status tci_bs_from_host(tci_context ctx, tci_bs_tensor t, const void* host, size_t bytes) try {
   if (!ctx || !host) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_TRY(bs_check(t));
   if (bytes != (size_t)t->nelem * elem_bytes(t->dtype)) TCI_RET(TCI_ERR_SHAPE, "byte count");
@@ -259,9 +267,9 @@ tci_status tci_bs_from_host(tci_context ctx, tci_bs_tensor t, const void* host, 
   if (bytes) TCI_CHECK_HIP(hipMemcpyAsync(t->data, host, bytes, hipMemcpyHostToDevice, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_bs_to_host(tci_context ctx, tci_bs_tensor t, void* host, size_t bytes) {
+tci_status tci_bs_to_host(tci_context ctx, tci_bs_tensor t, void* host, size_t bytes) try {
   if (!ctx || !host) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_TRY(bs_check(t));
   if (bytes != (size_t)t->nelem * elem_bytes(t->dtype)) TCI_RET(TCI_ERR_SHAPE, "byte count");
@@ -269,12 +277,12 @@ tci_status tci_bs_to_host(tci_context ctx, tci_bs_tensor t, void* host, size_t b
   if (bytes) TCI_CHECK_HIP(hipMemcpyAsync(host, t->data, bytes, hipMemcpyDeviceToHost, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_tensor* A, const tci_bs_tensor* B,
                                           const tci_tensor* gates, const tci_update_params* params,
                                           const int64_t* chi_max_each, tci_bs_tensor* A_out, tci_tensor* s_out,
-                                          tci_bs_tensor* B_out, tci_update_info* infos) {
+                                          tci_bs_tensor* B_out, tci_update_info* infos) try {
   if (!ctx || n < 1 || !A || !B || !A_out || !s_out || !B_out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   tci_update_params p;
   if (params) p = *params;
@@ -696,6 +704,6 @@ tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_t
   }
   TCI_CHECK_HIP(hipStreamSynchronize(st));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 }  // extern "C"

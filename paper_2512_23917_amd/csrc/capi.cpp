@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "eig.hpp"
 #include "gemm.hpp"
+#include "grouped.hpp"
 #include "linalg.hpp"
 #include "runtime.hpp"
 #include "subtensor.hpp"
@@ -25,6 +26,48 @@ namespace tci {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+tci_status status_of_exception() noexcept {
+  tci_status code = TCI_ERR_INTERNAL;
+  const char* msg = "internal error: unknown exception";
+  std::string what;
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    code = TCI_ERR_OUT_OF_MEMORY;
+    msg = "host memory allocation failed";
+  } catch (const std::exception& e) {
+    try {
+      what = std::string("internal error: ") + e.what();
+      msg = what.c_str();
+    } catch (...) {
+      msg = "internal error";
+    }
+  } catch (...) {
+  }
+  try {
+    g_last_error = msg;
+  } catch (...) {
+    g_last_error.clear();
+  }
+  return code;
+}
+
+void* dev_alloc(const tci_allocator& al, size_t bytes, hipStream_t s) {
+  if (al.alloc) return al.alloc(bytes, static_cast<void*>(s), al.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(const tci_allocator& al, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (al.free) al.free(p, bytes, static_cast<void*>(s), al.user);
+  else (void)hipFree(p);
+}
 
 void* Arena::get(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
@@ -38,17 +81,15 @@ void* Arena::get(size_t bytes) {
   }
   Chunk c;
   c.cap = std::max(bytes, size_t(256) << 20);
-  if (hipMalloc(&c.ptr, c.cap) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
+  c.ptr = dev_alloc(al, c.cap, stream ? *stream : nullptr);
+  if (!c.ptr) return nullptr;
   c.used = bytes;
   chunks.push_back(c);
   return c.ptr;
 }
 
 void Arena::release() {
-  for (auto& c : chunks) (void)hipFree(c.ptr);
+  for (auto& c : chunks) dev_free(al, c.ptr, c.cap, stream ? *stream : nullptr);
   chunks.clear();
 }
 
@@ -76,7 +117,6 @@ static std::string shape_str(const tci_tensor_s* t) {
 static bool valid_dtype(int dt) { return dt >= TCI_F32 && dt <= TCI_C128; }
 
 static tci_status alloc_storage(tci_context ctx, tci_tensor_s* t, size_t bytes) {
-  (void)ctx;
   if (t->owns && t->data && t->cap >= bytes) return TCI_OK;
   if (!t->owns && t->data) {
     if (t->cap >= bytes) return TCI_OK;
@@ -84,19 +124,17 @@ static tci_status alloc_storage(tci_context ctx, tci_tensor_s* t, size_t bytes) 
   }
   if (t->owns && t->data) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(t->data);
+    dev_free(t->al, t->data, t->cap, ctx->stream);
     t->data = nullptr;
     t->cap = 0;
   }
-  void* p = nullptr;
   const size_t want = std::max<size_t>(bytes, 16);
-  if (hipMalloc(&p, want) != hipSuccess) {
-    (void)hipGetLastError();
-    TCI_RET(TCI_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want) + " bytes failed");
-  }
+  void* p = dev_alloc(ctx->al, want, ctx->stream);
+  if (!p) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(want) + " bytes failed");
   t->data = p;
   t->cap = want;
   t->owns = true;
+  t->al = ctx->al;
   return TCI_OK;
 }
 
@@ -153,8 +191,26 @@ void tci_update_params_default(tci_update_params* p) {
   p->cert_tol = 1e-7;
 }
 
-tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream) {
+void tci_context_opts_default(tci_context_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = -1;
+  o->svd_mode = TCI_SVD_PLAIN;
+  o->verbosity = -1;
+}
+
+tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream, const tci_context_opts* opts) try {
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "out is NULL");
+  tci_context_opts o;
+  tci_context_opts_default(&o);
+  if (opts) o = *opts;
+  if ((o.allocator.alloc == nullptr) != (o.allocator.free == nullptr))
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "allocator: set both alloc and free, or neither");
+  if (o.precision != -1 && o.precision != TCI_PREC_FP32 && o.precision != TCI_PREC_BF16X3)
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "opts.precision must be -1, TCI_PREC_FP32 or TCI_PREC_BF16X3");
+  if (o.svd_mode != TCI_SVD_PLAIN && o.svd_mode != TCI_SVD_RANDOMIZED)
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "opts.svd_mode must be TCI_SVD_PLAIN or TCI_SVD_RANDOMIZED");
+  if (o.verbosity < -1 || o.verbosity > 2) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "opts.verbosity must be in [-1, 2]");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
     (void)hipGetLastError();
@@ -166,36 +222,51 @@ tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream)
   c->device = device_id;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->arena.device = device_id;
-  if (const char* v = std::getenv("TCI_VERBOSE")) c->verbose = std::atoi(v);
+  c->al = o.allocator;
+  c->arena.al = o.allocator;
+  c->arena.stream = &c->stream;
+  if (o.precision != -1) c->precision = o.precision;
+  c->svd_mode = o.svd_mode;
+  if (o.verbosity >= 0) c->verbose = o.verbosity;
+  else if (const char* v = std::getenv("TCI_VERBOSE")) c->verbose = std::atoi(v);
+  if (o.autotune_cache) {
+    c->tune_path = o.autotune_cache;
+    grouped_tune_load(c->tune_path, device_id);
+  }
   *out = c;
   Trace tr(c, "create_context", "device=" + std::to_string(device_id));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_destroy_context(tci_context ctx) {
+tci_status tci_destroy_context(tci_context ctx) try {
   TCI_TRY(check_ctx(ctx));
   (void)hipStreamSynchronize(ctx->stream);
   ctx->bs_graphs.reset();
   ctx->arena.release();
+  tci_status st = TCI_OK;
+  if (!ctx->tune_path.empty() && !grouped_tune_save(ctx->tune_path)) {
+    set_error("could not write the autotune cache " + ctx->tune_path);
+    st = TCI_ERR_INVALID_ARGUMENT;
+  }
   ctx->magic = 0;
   delete ctx;
-  return TCI_OK;
-}
+  return st;
+} TCI_API_CATCH
 
-tci_status tci_set_stream(tci_context ctx, void* hip_stream) {
+tci_status tci_set_stream(tci_context ctx, void* hip_stream) try {
   TCI_TRY(check_ctx(ctx));
   (void)hipStreamSynchronize(ctx->stream);
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_set_precision(tci_context ctx, tci_precision prec) {
+tci_status tci_set_precision(tci_context ctx, tci_precision prec) try {
   TCI_TRY(check_ctx(ctx));
   if (prec != TCI_PREC_FP32 && prec != TCI_PREC_BF16X3 && prec != TCI_PREC_FP64)
     TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad precision");
   ctx->precision = prec == TCI_PREC_FP64 ? TCI_PREC_FP32 : prec;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // ----------------------------------------------------------------- tensors
 static tci_status make_tensor(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape,
@@ -216,7 +287,7 @@ static tci_status make_tensor(tci_context ctx, tci_dtype dtype, int order, const
   if (zero && tbytes(t) > 0) {
     hipError_t e = hipMemsetAsync(t->data, 0, tbytes(t), ctx->stream);
     if (e != hipSuccess) {
-      (void)hipFree(t->data);
+      dev_free(t->al, t->data, t->cap, ctx->stream);
       delete t;
       TCI_CHECK_HIP(e);
     }
@@ -225,16 +296,16 @@ static tci_status make_tensor(tci_context ctx, tci_dtype dtype, int order, const
   return TCI_OK;
 }
 
-tci_status tci_allocate(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, tci_tensor* out) {
+tci_status tci_allocate(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, tci_tensor* out) try {
   return make_tensor(ctx, dtype, order, shape, out, false);
-}
+} TCI_API_CATCH
 
-tci_status tci_zeros(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, tci_tensor* out) {
+tci_status tci_zeros(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, tci_tensor* out) try {
   return make_tensor(ctx, dtype, order, shape, out, true);
-}
+} TCI_API_CATCH
 
 tci_status tci_wrap(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, void* dev_ptr,
-                    tci_tensor* out) {
+                    tci_tensor* out) try {
   TCI_TRY(check_ctx(ctx));
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "out is NULL");
   if (!valid_dtype(dtype)) TCI_RET(TCI_ERR_DTYPE, "bad dtype");
@@ -259,9 +330,9 @@ tci_status tci_wrap(tci_context ctx, tci_dtype dtype, int order, const int64_t* 
   t->owns = false;
   *out = t;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_copy(tci_context ctx, tci_tensor in, tci_tensor* out) {
+tci_status tci_copy(tci_context ctx, tci_tensor in, tci_tensor* out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   TCI_TRY(make_tensor(ctx, (tci_dtype)in->dtype, in->order, in->shape, out, false));
@@ -270,9 +341,9 @@ tci_status tci_copy(tci_context ctx, tci_tensor in, tci_tensor* out) {
   std::memcpy((*out)->labels, in->labels, sizeof(in->labels));
   (*out)->nlabels = in->nlabels;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_move(tci_context ctx, tci_tensor* from, tci_tensor* out) {
+tci_status tci_move(tci_context ctx, tci_tensor* from, tci_tensor* out) try {
   TCI_TRY(check_ctx(ctx));
   if (!from || !*from || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   auto* t = new tci_tensor_s(**from);
@@ -285,60 +356,60 @@ tci_status tci_move(tci_context ctx, tci_tensor* from, tci_tensor* out) {
   f->empty = true;
   *out = t;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_destroy(tci_context ctx, tci_tensor t) {
+tci_status tci_destroy(tci_context ctx, tci_tensor t) try {
   if (!t) return TCI_OK;
   TCI_TRY(check_ctx(ctx));
   if (t->owns && t->data) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(t->data);
+    dev_free(t->al, t->data, t->cap, ctx->stream);
   }
   delete t;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_order(tci_context ctx, tci_tensor t, int* out) {
+tci_status tci_order(tci_context ctx, tci_tensor t, int* out) try {
   (void)ctx;
   if (!t || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   *out = t->order;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_shape(tci_context ctx, tci_tensor t, int64_t* shape_out, int cap) {
+tci_status tci_shape(tci_context ctx, tci_tensor t, int64_t* shape_out, int cap) try {
   (void)ctx;
   if (!t || (!shape_out && cap > 0)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   for (int i = 0; i < std::min(cap, t->order); ++i) shape_out[i] = t->shape[i];
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_size(tci_context ctx, tci_tensor t, int64_t* out) {
+tci_status tci_size(tci_context ctx, tci_tensor t, int64_t* out) try {
   (void)ctx;
   if (!t || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   *out = t->empty ? 0 : tsize(t);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_size_bytes(tci_context ctx, tci_tensor t, int64_t* out) {
+tci_status tci_size_bytes(tci_context ctx, tci_tensor t, int64_t* out) try {
   (void)ctx;
   if (!t || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   *out = t->empty ? 0 : (int64_t)tbytes(t);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_dtype_of(tci_context ctx, tci_tensor t, tci_dtype* out) {
+tci_status tci_dtype_of(tci_context ctx, tci_tensor t, tci_dtype* out) try {
   (void)ctx;
   if (!t || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   *out = (tci_dtype)t->dtype;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_data_ptr(tci_context ctx, tci_tensor t, void** out) {
+tci_status tci_data_ptr(tci_context ctx, tci_tensor t, void** out) try {
   (void)ctx;
   if (!t || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   *out = t->data;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 static tci_status elem_offset(tci_tensor t, const int64_t* coors, size_t* off) {
   int64_t lin = 0;
@@ -350,7 +421,7 @@ static tci_status elem_offset(tci_tensor t, const int64_t* coors, size_t* off) {
   return TCI_OK;
 }
 
-tci_status tci_get_elem(tci_context ctx, tci_tensor t, const int64_t* coors, void* out) {
+tci_status tci_get_elem(tci_context ctx, tci_tensor t, const int64_t* coors, void* out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (!out || (t->order > 0 && !coors)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -360,9 +431,9 @@ tci_status tci_get_elem(tci_context ctx, tci_tensor t, const int64_t* coors, voi
                                hipMemcpyDeviceToHost, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_set_elem(tci_context ctx, tci_tensor t, const int64_t* coors, const void* val) {
+tci_status tci_set_elem(tci_context ctx, tci_tensor t, const int64_t* coors, const void* val) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (!val || (t->order > 0 && !coors)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -372,25 +443,25 @@ tci_status tci_set_elem(tci_context ctx, tci_tensor t, const int64_t* coors, con
                                hipMemcpyHostToDevice, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_set_labels(tci_context ctx, tci_tensor t, const int32_t* labels, int n) {
+tci_status tci_set_labels(tci_context ctx, tci_tensor t, const int32_t* labels, int n) try {
   (void)ctx;
   if (!t || n < 0 || n > MAX_ORDER || (n > 0 && !labels)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad labels");
   if (n != t->order) TCI_RET(TCI_ERR_LABEL, "label count must equal the order");
   for (int i = 0; i < n; ++i) t->labels[i] = labels[i];
   t->nlabels = n;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_get_labels(tci_context ctx, tci_tensor t, int32_t* labels, int cap) {
+tci_status tci_get_labels(tci_context ctx, tci_tensor t, int32_t* labels, int cap) try {
   (void)ctx;
   if (!t || (cap > 0 && !labels)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   for (int i = 0; i < std::min(cap, t->nlabels); ++i) labels[i] = t->labels[i];
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_from_host(tci_context ctx, tci_tensor t, const void* host, size_t bytes) {
+tci_status tci_from_host(tci_context ctx, tci_tensor t, const void* host, size_t bytes) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (bytes != tbytes(t)) TCI_RET(TCI_ERR_SHAPE, "byte count differs from size_bytes");
@@ -399,9 +470,9 @@ tci_status tci_from_host(tci_context ctx, tci_tensor t, const void* host, size_t
   TCI_CHECK_HIP(hipMemcpyAsync(t->data, host, bytes, hipMemcpyHostToDevice, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_to_host(tci_context ctx, tci_tensor t, void* host, size_t bytes) {
+tci_status tci_to_host(tci_context ctx, tci_tensor t, void* host, size_t bytes) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (bytes != tbytes(t)) TCI_RET(TCI_ERR_SHAPE, "byte count differs from size_bytes");
@@ -410,9 +481,9 @@ tci_status tci_to_host(tci_context ctx, tci_tensor t, void* host, size_t bytes) 
   TCI_CHECK_HIP(hipMemcpyAsync(host, t->data, bytes, hipMemcpyDeviceToHost, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_convert(tci_context ctx, tci_tensor in, tci_dtype dtype, tci_tensor* out) {
+tci_status tci_convert(tci_context ctx, tci_tensor in, tci_dtype dtype, tci_tensor* out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!valid_dtype(dtype)) TCI_RET(TCI_ERR_DTYPE, "bad dtype");
@@ -422,10 +493,10 @@ tci_status tci_convert(tci_context ctx, tci_tensor in, tci_dtype dtype, tci_tens
   TCI_TRY(make_tensor(ctx, dtype, in->order, in->shape, out, false));
   TCI_CHECK_HIP(tci::convert(in->dtype, in->data, dtype, (*out)->data, tsize(in), ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // ----------------------------------------------------------------- manipulation
-tci_status tci_reshape(tci_context ctx, tci_tensor in, int order, const int64_t* shape, tci_tensor out) {
+tci_status tci_reshape(tci_context ctx, tci_tensor in, int order, const int64_t* shape, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out || order < 0 || order > MAX_ORDER || (order > 0 && !shape))
@@ -443,9 +514,9 @@ tci_status tci_reshape(tci_context ctx, tci_tensor in, int order, const int64_t*
   if (tbytes(in) > 0)
     TCI_CHECK_HIP(hipMemcpyAsync(out->data, in->data, tbytes(in), hipMemcpyDeviceToDevice, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_transpose(tci_context ctx, tci_tensor in, const int32_t* perm, tci_tensor out) {
+tci_status tci_transpose(tci_context ctx, tci_tensor in, const int32_t* perm, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out || (in->order > 0 && !perm)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -476,16 +547,16 @@ tci_status tci_transpose(tci_context ctx, tci_tensor in, const int32_t* perm, tc
   TCI_TRY(ensure_shape(ctx, out, dt, order, oshape));
   if (bytes) TCI_CHECK_HIP(tci::permute(dt, src, out->data, order, ishape, p32, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_cplx_conj(tci_context ctx, tci_tensor in, tci_tensor out) {
+tci_status tci_cplx_conj(tci_context ctx, tci_tensor in, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null output");
   if (out != in) TCI_TRY(ensure_shape(ctx, out, in->dtype, in->order, in->shape));
   TCI_CHECK_HIP(tci::conjugate(in->dtype, in->data, out->data, tsize(in), ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 static void host_scalar(int dt, const void* s, double& r, double& i) {
   switch (dt) {
@@ -496,7 +567,7 @@ static void host_scalar(int dt, const void* s, double& r, double& i) {
   }
 }
 
-tci_status tci_scale(tci_context ctx, tci_tensor inout, const void* s) {
+tci_status tci_scale(tci_context ctx, tci_tensor inout, const void* s) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(inout, "inout"));
   if (!s) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null scalar");
@@ -504,9 +575,9 @@ tci_status tci_scale(tci_context ctx, tci_tensor inout, const void* s) {
   host_scalar(inout->dtype, s, r, i);
   TCI_CHECK_HIP(tci::scale_inplace(inout->dtype, inout->data, tsize(inout), r, i, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_linear_combine(tci_context ctx, int n, const tci_tensor* ins, const void* coefs, tci_tensor out) {
+tci_status tci_linear_combine(tci_context ctx, int n, const tci_tensor* ins, const void* coefs, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   if (n < 1 || n > LINCOMB_MAX || !ins || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   for (int q = 0; q < n; ++q) {
@@ -531,7 +602,7 @@ tci_status tci_linear_combine(tci_context ctx, int n, const tci_tensor* ins, con
   // elementwise: out[i] depends on ins[*][i] only, so aliasing is safe
   TCI_CHECK_HIP(tci::linear_combine(dt, a, out->data, tsize(ins[0]), ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // ----------------------------------------------------------------- reductions
 static tci_status norm2_dev(tci_context ctx, tci_tensor t, double* host_out) {
@@ -543,7 +614,7 @@ static tci_status norm2_dev(tci_context ctx, tci_tensor t, double* host_out) {
   return TCI_OK;
 }
 
-tci_status tci_norm(tci_context ctx, tci_tensor t, double* out) {
+tci_status tci_norm(tci_context ctx, tci_tensor t, double* out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null output");
@@ -553,9 +624,9 @@ tci_status tci_norm(tci_context ctx, tci_tensor t, double* out) {
   TCI_TRY(norm2_dev(ctx, t, &s2));
   *out = std::sqrt(s2);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_normalize(tci_context ctx, tci_tensor inout, double* old_norm) {
+tci_status tci_normalize(tci_context ctx, tci_tensor inout, double* old_norm) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(inout, "inout"));
   Trace tr(ctx, "normalize", shape_str(inout));
@@ -566,9 +637,9 @@ tci_status tci_normalize(tci_context ctx, tci_tensor inout, double* old_norm) {
   if (old_norm) *old_norm = nrm;
   if (nrm > 0.0) TCI_CHECK_HIP(tci::scale_inplace(inout->dtype, inout->data, tsize(inout), 1.0 / nrm, 0.0, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_close(tci_context ctx, tci_tensor a, tci_tensor b, double eps, int* result) {
+tci_status tci_close(tci_context ctx, tci_tensor a, tci_tensor b, double eps, int* result) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(a, "a"));
   TCI_TRY(check_t(b, "b"));
@@ -592,7 +663,7 @@ tci_status tci_close(tci_context ctx, tci_tensor a, tci_tensor b, double eps, in
   for (double v : h) { if (v != v) nan = true; m = std::max(m, v); }
   *result = (!nan && m <= eps) ? 1 : 0;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // ----------------------------------------------------------------- contraction
 static int find_lab(const int32_t* l, int n, int32_t x) {
@@ -602,7 +673,7 @@ static int find_lab(const int32_t* l, int n, int32_t x) {
 }
 
 tci_status tci_contract(tci_context ctx, tci_tensor a, const int32_t* la, int na, tci_tensor b,
-                        const int32_t* lb, int nb, tci_tensor c, const int32_t* lc, int nc) {
+                        const int32_t* lb, int nb, tci_tensor c, const int32_t* lc, int nc) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(a, "a"));
   TCI_TRY(check_t(b, "b"));
@@ -718,10 +789,10 @@ tci_status tci_contract(tci_context ctx, tci_tensor a, const int32_t* la, int na
     else TCI_CHECK_HIP(hipMemcpyAsync(c->data, Cp, es, hipMemcpyDeviceToDevice, ctx->stream));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_contract_str(tci_context ctx, tci_tensor a, const char* la, tci_tensor b, const char* lb,
-                            tci_tensor c, const char* lc) {
+                            tci_tensor c, const char* lc) try {
   if (!la || !lb || !lc) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null label string");
   int32_t A[MAX_ORDER + 1], B[MAX_ORDER + 1], C[MAX_ORDER + 1];
   const int na = (int)std::strlen(la), nb = (int)std::strlen(lb), nc = (int)std::strlen(lc);
@@ -730,7 +801,7 @@ tci_status tci_contract_str(tci_context ctx, tci_tensor a, const char* la, tci_t
   for (int i = 0; i < nb; ++i) B[i] = (unsigned char)lb[i];
   for (int i = 0; i < nc; ++i) C[i] = (unsigned char)lc[i];
   return tci_contract(ctx, a, A, na, b, B, nb, c, C, nc);
-}
+} TCI_API_CATCH
 
 
 // ---------------------------------------------------------------- sub-tensors
@@ -793,25 +864,25 @@ tci_status copy_box(tci_context ctx, int dt, const void* src, int order, const i
 extern "C" {
 
 tci_status tci_fill(tci_context ctx, tci_dtype dtype, int order, const int64_t* shape, const void* value,
-                    tci_tensor* out) {
+                    tci_tensor* out) try {
   if (!value) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null value");
   TCI_TRY(make_tensor(ctx, dtype, order, shape, out, false));
   double vr, vi;
   host_scalar(dtype, value, vr, vi);
   TCI_CHECK_HIP(fill_value(dtype, (*out)->data, tsize(*out), vr, vi, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_eye(tci_context ctx, tci_dtype dtype, int64_t n, tci_tensor* out) {
+tci_status tci_eye(tci_context ctx, tci_dtype dtype, int64_t n, tci_tensor* out) try {
   if (n < 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "negative dimension");
   const int64_t shape[2] = {n, n};
   TCI_TRY(make_tensor(ctx, dtype, 2, shape, out, true));
   TCI_CHECK_HIP(add_diag(dtype, (*out)->data, n, (int)n, 1.0, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_extract_sub(tci_context ctx, tci_tensor in, const int64_t* first, const int64_t* last,
-                           tci_tensor out) {
+                           tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out || (in->order > 0 && (!first || !last))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -848,10 +919,10 @@ tci_status tci_extract_sub(tci_context ctx, tci_tensor in, const int64_t* first,
   }
   TCI_CHECK_HIP(box_copy(elem_bytes(dt), src, out->data, c, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_shrink(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* first,
-                      const int64_t* last, tci_tensor out) {
+                      const int64_t* last, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (n < 0 || (n > 0 && (!bonds || !first || !last))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -869,10 +940,10 @@ tci_status tci_shrink(tci_context ctx, tci_tensor in, int n, const int32_t* bond
     l[b] = last[k];
   }
   return tci_extract_sub(ctx, in, f, l, out);
-}
+} TCI_API_CATCH
 
 tci_status tci_expand(tci_context ctx, tci_tensor in, int n, const int32_t* bonds, const int64_t* increments,
-                      tci_tensor out) {
+                      tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out || n < 0 || (n > 0 && (!bonds || !increments))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -897,9 +968,9 @@ tci_status tci_expand(tci_context ctx, tci_tensor in, int n, const int32_t* bond
   TCI_TRY(ensure_shape(ctx, out, dt, order, oshape));
   if (tbytes(out)) TCI_CHECK_HIP(hipMemsetAsync(out->data, 0, tbytes(out), ctx->stream));
   return copy_box(ctx, dt, src, order, ishape, out->data, oshape, zero);
-}
+} TCI_API_CATCH
 
-tci_status tci_replace_sub(tci_context ctx, tci_tensor in, tci_tensor sub, const int64_t* begin, tci_tensor out) {
+tci_status tci_replace_sub(tci_context ctx, tci_tensor in, tci_tensor sub, const int64_t* begin, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   TCI_TRY(check_t(sub, "sub"));
@@ -920,9 +991,9 @@ tci_status tci_replace_sub(tci_context ctx, tci_tensor in, tci_tensor sub, const
     if (tbytes(in)) TCI_CHECK_HIP(hipMemcpyAsync(out->data, in->data, tbytes(in), hipMemcpyDeviceToDevice, ctx->stream));
   }
   return copy_box(ctx, in->dtype, sub->data, order, sshape, out->data, ishape, begin);
-}
+} TCI_API_CATCH
 
-tci_status tci_concatenate(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) {
+tci_status tci_concatenate(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   if (n < 1 || !ins || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need at least one input and an output");
   for (int k = 0; k < n; ++k) {
@@ -951,9 +1022,9 @@ tci_status tci_concatenate(tci_context ctx, int n, const tci_tensor* ins, int bo
     off[bond] += sshape[bond];
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_stack(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) {
+tci_status tci_stack(tci_context ctx, int n, const tci_tensor* ins, int bond, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   if (n < 1 || !ins || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need at least one input and an output");
   for (int k = 0; k < n; ++k) {
@@ -989,9 +1060,9 @@ tci_status tci_stack(tci_context ctx, int n, const tci_tensor* ins, int bond, tc
     TCI_TRY(copy_box(ctx, dt, ins[k]->data, order + 1, sshape, out->data, oshape, off));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_trace(tci_context ctx, tci_tensor in, int npairs, const int32_t* pairs, tci_tensor out) {
+tci_status tci_trace(tci_context ctx, tci_tensor in, int npairs, const int32_t* pairs, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out || npairs < 0 || (npairs > 0 && !pairs)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -1034,9 +1105,9 @@ tci_status tci_trace(tci_context ctx, tci_tensor in, int npairs, const int32_t* 
   TCI_TRY(ensure_shape(ctx, out, dt, nk, oshape));
   TCI_CHECK_HIP(partial_trace(dt, src, out->data, ta, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_diag(tci_context ctx, tci_tensor in, tci_tensor out) {
+tci_status tci_diag(tci_context ctx, tci_tensor in, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -1068,9 +1139,9 @@ tci_status tci_diag(tci_context ctx, tci_tensor in, tci_tensor out) {
   }
   TCI_CHECK_HIP(box_copy(elem_bytes(dt), src, out->data, c, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_to_cplx(tci_context ctx, tci_tensor in, tci_tensor out) {
+tci_status tci_to_cplx(tci_context ctx, tci_tensor in, tci_tensor out) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(in, "in"));
   if (!out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
@@ -1085,7 +1156,7 @@ tci_status tci_to_cplx(tci_context ctx, tci_tensor in, tci_tensor out) {
   TCI_TRY(ensure_shape(ctx, out, cdt, in->order, shape));
   TCI_CHECK_HIP(tci::convert(dt, src, cdt, out->data, n, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 namespace {
 tci_status part_of(tci_context ctx, tci_tensor in, tci_tensor out, bool imag, const char* name) {
@@ -1111,8 +1182,8 @@ tci_status part_of(tci_context ctx, tci_tensor in, tci_tensor out, bool imag, co
 }
 }  // namespace
 
-tci_status tci_real(tci_context ctx, tci_tensor in, tci_tensor out) { return part_of(ctx, in, out, false, "real"); }
-tci_status tci_imag(tci_context ctx, tci_tensor in, tci_tensor out) { return part_of(ctx, in, out, true, "imag"); }
+tci_status tci_real(tci_context ctx, tci_tensor in, tci_tensor out) try { return part_of(ctx, in, out, false, "real"); } TCI_API_CATCH
+tci_status tci_imag(tci_context ctx, tci_tensor in, tci_tensor out) try { return part_of(ctx, in, out, true, "imag"); } TCI_API_CATCH
 
 // File layout: 8 bytes "TCIMI355", int32 format version (1), int32 dtype,
 // int32 order, int32 zero, int64 shape[order], then the elements row-major in
@@ -1122,7 +1193,7 @@ constexpr char SAVE_MAGIC[8] = {'T', 'C', 'I', 'M', 'I', '3', '5', '5'};
 constexpr int32_t SAVE_VERSION = 1;
 }  // namespace
 
-tci_status tci_save(tci_context ctx, tci_tensor t, const char* path) {
+tci_status tci_save(tci_context ctx, tci_tensor t, const char* path) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   if (!path) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null path");
@@ -1141,9 +1212,9 @@ tci_status tci_save(tci_context ctx, tci_tensor t, const char* path) {
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("short write to ") + path);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_load(tci_context ctx, const char* path, tci_tensor* out) {
+tci_status tci_load(tci_context ctx, const char* path, tci_tensor* out) try {
   TCI_TRY(check_ctx(ctx));
   if (!path || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   FILE* f = std::fopen(path, "rb");
@@ -1173,9 +1244,9 @@ tci_status tci_load(tci_context ctx, const char* path, tci_tensor* out) {
     TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_show(tci_context ctx, tci_tensor t) {
+tci_status tci_show(tci_context ctx, tci_tensor t) try {
   TCI_TRY(check_ctx(ctx));
   TCI_TRY(check_t(t, "t"));
   static const char* names[] = {"F32", "F64", "C64", "C128"};
@@ -1211,6 +1282,6 @@ tci_status tci_show(tci_context ctx, tci_tensor t) {
   }
   std::fflush(stdout);
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 }  // extern "C"

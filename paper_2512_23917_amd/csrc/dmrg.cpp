@@ -148,7 +148,7 @@ using namespace tci;
 extern "C" {
 
 tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, tci_tensor x,
-                           tci_tensor y) {
+                           tci_tensor y) try {
   if (!ctx || !y) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   int chil, chir, wd, d;
@@ -162,10 +162,10 @@ tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_ten
   TCI_TRY(ensure_shape(ctx, y, L->dtype, 4, ysh));
   TCI_TRY(heff_apply(ctx, p, x->data, y->data));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R,
-                              tci_tensor theta, int n_matvec, double* energy) {
+                              tci_tensor theta, int n_matvec, double* energy) try {
   if (!ctx || !theta || !energy) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   if (n_matvec < 1 || n_matvec > 32) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "n_matvec must be in [1, 32]");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -332,6 +332,6 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   TCI_CHECK_HIP(hipStreamSynchronize(s));
   *energy = -hl;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 }  // extern "C"

@@ -9,6 +9,9 @@
 // times every candidate shape on a scratch output and remembers the fastest.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <string>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -145,6 +148,35 @@ std::mutex g_tune_mu;
 std::map<std::pair<int, std::vector<long long>>, int> g_tuned;   // (device, signature) -> shape index
 
 }  // namespace
+
+// Cache file: one line per tuned signature, "device shape h0 .. h36".
+void grouped_tune_load(const std::string& path, int device) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (;;) {
+    int dev = 0, shape = 0;
+    if (std::fscanf(f, "%d %d", &dev, &shape) != 2) break;
+    std::vector<long long> h(3 * 12 + 1, 0);
+    bool ok = true;
+    for (auto& v : h) ok = ok && std::fscanf(f, "%lld", &v) == 1;
+    if (!ok) break;
+    if (dev == device && shape >= 0 && shape < kNumShapes) g_tuned[{dev, h}] = shape;
+  }
+  std::fclose(f);
+}
+
+bool grouped_tune_save(const std::string& path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path.c_str(), "w");
+  if (!f) return false;
+  for (const auto& kv : g_tuned) {
+    std::fprintf(f, "%d %d", kv.first.first, kv.second);
+    for (long long v : kv.first.second) std::fprintf(f, " %lld", v);
+    std::fprintf(f, "\n");
+  }
+  return std::fclose(f) == 0;
+}
 
 int grouped_tuned_shape(int device, const std::vector<GroupProb>& probs) {
   std::lock_guard<std::mutex> lk(g_tune_mu);

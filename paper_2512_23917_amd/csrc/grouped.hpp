@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 namespace tci {
@@ -24,6 +25,10 @@ struct GroupProb {
 hipError_t grouped_gemm_f32(int device, const std::vector<GroupProb>& probs, GroupProb* P_dev, int* tile0_dev,
                             long long scratch_shift, hipStream_t s, int* shape_out);
 int grouped_tuned_shape(int device, const std::vector<GroupProb>& probs);
+// Tuned shapes of `device` from a cache file (missing file: nothing), and
+// every tuned shape of the process into one (false when it cannot be written).
+void grouped_tune_load(const std::string& path, int device);
+bool grouped_tune_save(const std::string& path);
 
 // The same in two halves: grouped_prepare uploads the tables, tunes the tile
 // shape if needed and synchronises; grouped_launch only enqueues the kernel

@@ -382,6 +382,39 @@ hipError_t scale_rows(int dtype, const void* in, long long sin_, void* out, long
   return hipGetLastError();
 }
 
+// x[i] /= lam[(i / div) % mod] for i < n: the inverse bond weights of the
+// Vidal form applied along one bond of a row-major tensor (quotient in FP64).
+template <typename T>
+__device__ inline T div_scalar(T v, double w);
+template <>
+__device__ inline double div_scalar<double>(double v, double w) { return v / w; }
+template <>
+__device__ inline float div_scalar<float>(float v, double w) { return (float)((double)v / w); }
+template <>
+__device__ inline cd div_scalar<cd>(cd v, double w) { return cd{v.x / w, v.y / w}; }
+template <>
+__device__ inline cf div_scalar<cf>(cf v, double w) { return cf{(float)((double)v.x / w), (float)((double)v.y / w)}; }
+
+template <typename T>
+__global__ void inv_scale_axis_kernel(T* x, long long n, long long div, long long mod, const double* lam) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    x[i] = div_scalar(x[i], lam[(i / div) % mod]);
+}
+
+hipError_t inv_scale_axis(int dtype, void* x, long long n, long long div, long long mod, const double* lam,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)std::min<long long>(2048, (n + 255) / 256));
+  switch (dtype) {
+    case C128: hipLaunchKernelGGL(inv_scale_axis_kernel<cd>, grid, dim3(256), 0, s, (cd*)x, n, div, mod, lam); break;
+    case F64: hipLaunchKernelGGL(inv_scale_axis_kernel<double>, grid, dim3(256), 0, s, (double*)x, n, div, mod, lam); break;
+    case C64: hipLaunchKernelGGL(inv_scale_axis_kernel<cf>, grid, dim3(256), 0, s, (cf*)x, n, div, mod, lam); break;
+    case F32: hipLaunchKernelGGL(inv_scale_axis_kernel<float>, grid, dim3(256), 0, s, (float*)x, n, div, mod, lam); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Transpose of an order-r tensor (r <= 8): out[c] = in[c'] with
 // c'[perm[b]] = c[b].  When the last bond stays last, consecutive threads

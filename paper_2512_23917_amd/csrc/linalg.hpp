@@ -45,6 +45,10 @@ hipError_t compact_columns(int dtype, const void* in, long long ldin, long long 
 hipError_t scale_rows(int dtype, const void* in, long long sin_, void* out, long long sout, long long ncols,
                       int maxchi, const int* chi, const double* rs, long long srs, int batch, hipStream_t s);
 
+// x[i] /= lam[(i / div) % mod], i < n (Vidal-form inverse bond weights).
+hipError_t inv_scale_axis(int dtype, void* x, long long n, long long div, long long mod, const double* lam,
+                          hipStream_t s);
+
 hipError_t permute(int dtype, const void* in, void* out, int order, const long long* shape,
                    const int* perm, hipStream_t s);
 

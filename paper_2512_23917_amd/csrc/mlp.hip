@@ -22,6 +22,7 @@ struct tci_sketch_model_s {
   float* m = nullptr;       // Adam first moment
   float* v = nullptr;       // Adam second moment
   int64_t step = 0;
+  tci_allocator al{};       // allocator of the three buffers (the creating context's)
   uint32_t magic = 0x5C37C4u;
 };
 
@@ -221,14 +222,19 @@ using namespace tci;
 
 extern "C" {
 
-tci_status tci_sketch_model_create(tci_context ctx, uint64_t seed, tci_sketch_model* out) {
+tci_status tci_sketch_model_create(tci_context ctx, uint64_t seed, tci_sketch_model* out) try {
   if (!ctx || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   auto* m = new tci_sketch_model_s();
   const size_t bytes = sizeof(float) * NPARAM;
-  if (hipMalloc(&m->params, bytes) != hipSuccess || hipMalloc(&m->m, bytes) != hipSuccess ||
-      hipMalloc(&m->v, bytes) != hipSuccess) {
-    (void)hipGetLastError();
+  m->al = ctx->al;
+  m->params = static_cast<float*>(dev_alloc(m->al, bytes, ctx->stream));
+  m->m = static_cast<float*>(dev_alloc(m->al, bytes, ctx->stream));
+  m->v = static_cast<float*>(dev_alloc(m->al, bytes, ctx->stream));
+  if (!m->params || !m->m || !m->v) {
+    dev_free(m->al, m->params, bytes, ctx->stream);
+    dev_free(m->al, m->m, bytes, ctx->stream);
+    dev_free(m->al, m->v, bytes, ctx->stream);
     delete m;
     TCI_RET(TCI_ERR_OUT_OF_MEMORY, "model allocation");
   }
@@ -241,40 +247,42 @@ tci_status tci_sketch_model_create(tci_context ctx, uint64_t seed, tci_sketch_mo
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   *out = m;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_sketch_model_destroy(tci_context ctx, tci_sketch_model m) {
+tci_status tci_sketch_model_destroy(tci_context ctx, tci_sketch_model m) try {
   if (!m) return TCI_OK;
   if (ctx) (void)hipStreamSynchronize(ctx->stream);
-  (void)hipFree(m->params);
-  (void)hipFree(m->m);
-  (void)hipFree(m->v);
+  const size_t bytes = sizeof(float) * NPARAM;
+  hipStream_t st = ctx ? ctx->stream : nullptr;
+  dev_free(m->al, m->params, bytes, st);
+  dev_free(m->al, m->m, bytes, st);
+  dev_free(m->al, m->v, bytes, st);
   m->magic = 0;
   delete m;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 int64_t tci_sketch_model_nparams(void) { return NPARAM; }
 
-tci_status tci_sketch_model_get_params(tci_context ctx, tci_sketch_model m, float* host, int64_t n) {
+tci_status tci_sketch_model_get_params(tci_context ctx, tci_sketch_model m, float* host, int64_t n) try {
   if (!ctx || !host) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_TRY(model_check(m));
   if (n != NPARAM) TCI_RET(TCI_ERR_SHAPE, "parameter count");
   TCI_CHECK_HIP(hipMemcpyAsync(host, m->params, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_sketch_model_set_params(tci_context ctx, tci_sketch_model m, const float* host, int64_t n) {
+tci_status tci_sketch_model_set_params(tci_context ctx, tci_sketch_model m, const float* host, int64_t n) try {
   if (!ctx || !host) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_TRY(model_check(m));
   if (n != NPARAM) TCI_RET(TCI_ERR_SHAPE, "parameter count");
   TCI_CHECK_HIP(hipMemcpyAsync(m->params, host, sizeof(float) * NPARAM, hipMemcpyHostToDevice, ctx->stream));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_sketch_model_save(tci_context ctx, tci_sketch_model m, const char* path) {
+tci_status tci_sketch_model_save(tci_context ctx, tci_sketch_model m, const char* path) try {
   if (!path) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null path");
   std::vector<float> h(NPARAM);
   TCI_TRY(tci_sketch_model_get_params(ctx, m, h.data(), NPARAM));
@@ -287,9 +295,9 @@ tci_status tci_sketch_model_save(tci_context ctx, tci_sketch_model m, const char
   std::fclose(f);
   if (!ok) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "short write");
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_sketch_model_load(tci_context ctx, const char* path, tci_sketch_model* out) {
+tci_status tci_sketch_model_load(tci_context ctx, const char* path, tci_sketch_model* out) try {
   if (!ctx || !path || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   FILE* f = std::fopen(path, "rb");
   if (!f) TCI_RET(TCI_ERR_INVALID_ARGUMENT, std::string("cannot open ") + path);
@@ -303,16 +311,16 @@ tci_status tci_sketch_model_load(tci_context ctx, const char* path, tci_sketch_m
   if (!ok) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "not a sketch-model file");
   TCI_TRY(tci_sketch_model_create(ctx, 0, out));
   return tci_sketch_model_set_params(ctx, *out, h.data(), NPARAM);
-}
+} TCI_API_CATCH
 
-tci_status tci_sketch_predict(tci_context ctx, tci_sketch_model m, const float* X, int n, float* y) {
+tci_status tci_sketch_predict(tci_context ctx, tci_sketch_model m, const float* X, int n, float* y) try {
   if (!ctx || (n > 0 && (!X || !y))) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   return sketch_predict_dev(ctx, m, X, n, y);
-}
+} TCI_API_CATCH
 
 tci_status tci_sketch_grads(tci_context ctx, tci_sketch_model m, const float* X, const float* T, int n, float* grad,
-                            float* loss) {
+                            float* loss) try {
   if (!ctx || !X || !T || !grad || n < 1) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   TCI_TRY(model_check(m));
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -325,10 +333,10 @@ tci_status tci_sketch_grads(tci_context ctx, tci_sketch_model m, const float* X,
     TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_sketch_train_step(tci_context ctx, tci_sketch_model m, const float* X, const float* T, int n, float lr,
-                                 float* loss) {
+                                 float* loss) try {
   if (!ctx || !X || !T || n < 1) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   TCI_TRY(model_check(m));
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -349,13 +357,13 @@ tci_status tci_sketch_train_step(tci_context ctx, tci_sketch_model m, const floa
     TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 tci_status tci_sketch_features(tci_context ctx, const double* s, int64_t ss, const int32_t* len, int n, int chi_max,
-                               int d, double eps, float* X) {
+                               int d, double eps, float* X) try {
   if (!ctx || !s || !len || !X || n < 1 || chi_max < 1 || !(eps > 0.0)) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   return sketch_features_dev(ctx, s, ss, len, chi_max, d, eps, X, n);
-}
+} TCI_API_CATCH
 
 }  // extern "C"

@@ -62,7 +62,7 @@ using namespace tci;
 
 extern "C" {
 
-tci_status tci_profile_enable(tci_context ctx, int enable) {
+tci_status tci_profile_enable(tci_context ctx, int enable) try {
   if (!ctx) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null context");
   (void)hipStreamSynchronize(ctx->stream);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -73,9 +73,9 @@ tci_status tci_profile_enable(tci_context ctx, int enable) {
   }
   g_recs.clear();
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_profile_query(tci_context ctx, const char* tag, int64_t* count, double* total_ms, double* work) {
+tci_status tci_profile_query(tci_context ctx, const char* tag, int64_t* count, double* total_ms, double* work) try {
   if (!ctx || !tag || !count || !total_ms || !work) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   (void)hipStreamSynchronize(ctx->stream);
   std::lock_guard<std::mutex> lk(g_mu);
@@ -94,10 +94,10 @@ tci_status tci_profile_query(tci_context ctx, const char* tag, int64_t* count, d
     *work += r.work;
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // Writes the distinct tags recorded so far, separated by '\n', into buf.
-tci_status tci_profile_tags(tci_context ctx, char* buf, int cap) {
+tci_status tci_profile_tags(tci_context ctx, char* buf, int cap) try {
   if (!ctx || !buf || cap <= 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   std::lock_guard<std::mutex> lk(g_mu);
   std::vector<std::string> seen;
@@ -111,6 +111,6 @@ tci_status tci_profile_tags(tci_context ctx, char* buf, int cap) {
   std::strncpy(buf, out.c_str(), cap - 1);
   buf[cap - 1] = 0;
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 }  // extern "C"

@@ -19,6 +19,19 @@ constexpr int MAX_ORDER = 8;
 // Per-thread message of the last failed call.
 void set_error(const std::string& msg);
 
+// Device memory through an allocator of tci_context_opts (hipMalloc /
+// hipFree when its callbacks are NULL).  dev_alloc returns nullptr on failure.
+void* dev_alloc(const tci_allocator& al, size_t bytes, hipStream_t s);
+void dev_free(const tci_allocator& al, void* p, size_t bytes, hipStream_t s);
+
+// Status of the exception being handled: every extern "C" entry point is a
+// function-try-block ending in TCI_API_CATCH, so no C++ exception crosses the
+// C ABI (std::bad_alloc -> TCI_ERR_OUT_OF_MEMORY, anything else ->
+// TCI_ERR_INTERNAL, with the message in tci_last_error).
+tci_status status_of_exception() noexcept;
+#define TCI_API_CATCH \
+  catch (...) { return ::tci::status_of_exception(); }
+
 struct Chunk {
   void* ptr = nullptr;
   size_t cap = 0;
@@ -31,6 +44,8 @@ struct Chunk {
 struct Arena {
   std::vector<Chunk> chunks;
   int device = 0;
+  tci_allocator al{};            // the owning context's allocator
+  const hipStream_t* stream = nullptr;   // the owning context's stream
   void reset() {
     for (auto& c : chunks) c.used = 0;
   }
@@ -63,6 +78,9 @@ struct tci_context_s {
   hipStream_t stream = nullptr;
   int verbose = 0;
   int precision = TCI_PREC_FP32;  // mixed precision for F32 / C64 contractions
+  int svd_mode = TCI_SVD_PLAIN;   // update composites called with params NULL
+  tci_allocator al{};             // device allocator (NULL callbacks: hipMalloc / hipFree)
+  std::string tune_path;          // grouped-GEMM tile cache file ("" = none)
   tci::Arena arena;
   // recorded HIP graphs of the block-sparse update (owned; see bsparse.cpp)
   std::shared_ptr<void> bs_graphs;
@@ -78,6 +96,7 @@ struct tci_tensor_s {
   void* data = nullptr;
   size_t cap = 0;   // bytes of storage
   bool owns = false;
+  tci_allocator al{};  // allocator of owned storage (copied from the creating context)
   bool empty = false;  // moved-from
 };
 

@@ -320,10 +320,10 @@ tci_status choose_sketch_ranks(tci_context ctx, const tci_update_params& p, int 
 }  // namespace tci
 
 extern "C" tci_status tci_philox_blocks(tci_context ctx, uint64_t seed, uint32_t stream, uint64_t first, int64_t n,
-                                        uint32_t* out) {
+                                        uint32_t* out) try {
   if (!ctx || !out || n < 0) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad arguments");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   if (n == 0) return TCI_OK;
   TCI_CHECK_HIP(tci::philox_blocks(seed, stream, first, n, out, ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH

@@ -249,42 +249,47 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
   return tsvd_vectors(ctx, st, chi, kz, sinv, out);
 }
 
-// trunc_svd of one small matrix (min(m, n) <= JACOBI_MAX_K) by one-sided
-// Jacobi rotations on the matrix itself, so that singular values far below
-// the largest are resolved (the Gram route squares the condition number).
-// Fills the fields of `out` that tci_trunc_svd reads: U (m x k, ld k), Vh
-// (k x n), s, chi and the host copies.
-static tci_status tsvd_small(tci_context ctx, int wdt, int m, int n, const void* theta, const TruncParams& tp,
-                             TsvdOut& out) {
+// trunc_svd of nb small matrices (min(m, n) <= JACOBI_MAX_K, problem b at
+// theta + b*m*n) by one-sided Jacobi rotations on the matrices themselves, so
+// that singular values far below the largest are resolved (the Gram route
+// squares the condition number).  Fills every field of `out` that
+// store_outputs and tci_trunc_svd read: U (m x k per problem, ld k), Vh
+// (k x n), s, sn, chi, total and the host copies, with kmax = kz = k.
+static tci_status tsvd_small(tci_context ctx, int wdt, int nb, int m, int n, const void* theta,
+                             const TruncParams& tp, TsvdOut& out) {
   hipStream_t s = ctx->stream;
   const size_t es = elem_bytes(wdt);
   const int k = std::min(m, n);
-  ARENA(work, char, es * jacobi_work_elems(std::max(m, n), k));
-  ARENA(U, char, es * (size_t)m * k);
-  ARENA(Vh, char, es * (size_t)k * n);
-  ARENA(sraw, double, k);
-  ARENA(sweeps, int, 1);
-  ARENA(total, double, 1);
-  ARENA(partial, double, SUMSQ_PARTIALS);
-  TCI_CHECK_HIP(sumsq_batched(wdt, theta, (long long)m * n, 0, total, partial, 1, s));
-  TCI_CHECK_HIP(jacobi_svd(wdt, theta, n, 0, m, n, work, U, 0, Vh, 0, sraw, 0, sweeps, 1, s));
-  ARENA(chi, int, 1);
-  ARENA(err, double, 1);
-  ARENA(disc, double, 1);
-  ARENA(sv, double, k);
-  ARENA(sinv, double, k);
-  ARENA(sn, double, k);
-  TCI_CHECK_HIP(trunc_select(sraw, k, k, total, tp, chi, err, disc, sv, sinv, sn, k, 1, s, true));
-  int sw = 0;
-  out.chi_h.resize(1); out.err_h.resize(1); out.disc_h.resize(1); out.total_h.resize(1);
-  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), total, sizeof(double), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+  const long long smn = (long long)m * n;
+  ARENA(work, char, es * jacobi_work_elems(std::max(m, n), k) * nb);
+  ARENA(U, char, es * (size_t)m * k * nb);
+  ARENA(Vh, char, es * (size_t)k * n * nb);
+  ARENA(sraw, double, (size_t)k * nb);
+  ARENA(sweeps, int, nb);
+  ARENA(total, double, nb);
+  ARENA(partial, double, (size_t)SUMSQ_PARTIALS * nb);
+  TCI_CHECK_HIP(sumsq_batched(wdt, theta, smn, smn, total, partial, nb, s));
+  TCI_CHECK_HIP(jacobi_svd(wdt, theta, n, smn, m, n, work, U, (long long)m * k, Vh, (long long)k * n, sraw, k, sweeps,
+                           nb, s));
+  ARENA(chi, int, nb);
+  ARENA(err, double, nb);
+  ARENA(disc, double, nb);
+  ARENA(sv, double, (size_t)k * nb);
+  ARENA(sinv, double, (size_t)k * nb);
+  ARENA(sn, double, (size_t)k * nb);
+  TCI_CHECK_HIP(trunc_select(sraw, k, k, total, tp, chi, err, disc, sv, sinv, sn, k, nb, s, true));
+  std::vector<int> sw(nb);
+  out.chi_h.resize(nb); out.err_h.resize(nb); out.disc_h.resize(nb); out.total_h.resize(nb);
+  TCI_CHECK_HIP(hipMemcpyAsync(out.chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.err_h.data(), err, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.disc_h.data(), disc, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(out.total_h.data(), total, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(sw.data(), sweeps, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
   TCI_CHECK_HIP(hipStreamSynchronize(s));
-  if (!std::isfinite(out.total_h[0])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in the matrix");
-  if (sw < 0) TCI_RET(TCI_ERR_NOT_CONVERGED, "Jacobi SVD did not converge in 80 sweeps");
+  for (int b = 0; b < nb; ++b) {
+    if (!std::isfinite(out.total_h[b])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in the matrix");
+    if (sw[b] < 0) TCI_RET(TCI_ERR_NOT_CONVERGED, "Jacobi SVD did not converge in 80 sweeps");
+  }
   out.kmax = k; out.kz = k;
   out.U = U; out.Vh = Vh;
   out.chi = chi; out.s = sv; out.sn = sn; out.total = total;
@@ -338,11 +343,12 @@ static tci_status store_outputs(tci_context ctx, int dt, int wdt, int chil, int 
   const int kz = o.kz;
   ARENA(Ucmp, char, wes * (size_t)m * kz * nb);
   ARENA(Vcmp, char, wes * (size_t)kz * n * nb);
-  const bool right = p.direction == TCI_DIR_RIGHT;
+  const bool right = p.direction == TCI_DIR_RIGHT, left = p.direction == TCI_DIR_LEFT;
+  const bool vidal = p.direction == TCI_DIR_VIDAL;
   TCI_CHECK_HIP(compact_columns(wdt, o.U, kz, (long long)m * kz, Ucmp, (long long)m * kz, m, kz, o.chi,
                                 right ? o.sn : nullptr, o.kmax, nb, s));
   TCI_CHECK_HIP(scale_rows(wdt, o.Vh, (long long)kz * n, Vcmp, (long long)kz * n, n, kz, o.chi,
-                           right ? nullptr : o.sn, o.kmax, nb, s));
+                           left ? o.sn : nullptr, o.kmax, nb, s));
   for (int i = 0; i < nb; ++i) {
     const int g = idx[i];
     const int64_t chi = o.chi_h[i];
@@ -352,6 +358,13 @@ static tci_status store_outputs(tci_context ctx, int dt, int wdt, int chil, int 
     TCI_TRY(ensure_shape(ctx, s_out[g], F64, 1, ssh));
     TCI_TRY(store_as(ctx, wdt, Ucmp + wes * (size_t)m * kz * i, A_out[g]));
     TCI_TRY(store_as(ctx, wdt, Vcmp + wes * (size_t)kz * n * i, B_out[g]));
+    if (vidal) {
+      // Gamma_A = diag(1/lambda_l) U, Gamma_B = V^H diag(1/lambda_r)
+      TCI_CHECK_HIP(inv_scale_axis(dt, A_out[g]->data, (long long)chil * d * chi, (long long)d * chi, chil,
+                                   static_cast<const double*>(p.lambda_left[g]->data), s));
+      TCI_CHECK_HIP(inv_scale_axis(dt, B_out[g]->data, chi * d * (long long)chir, 1, chir,
+                                   static_cast<const double*>(p.lambda_right[g]->data), s));
+    }
     TCI_CHECK_HIP(hipMemcpyAsync(s_out[g]->data, o.sn + (size_t)o.kmax * i, sizeof(double) * chi,
                                  hipMemcpyDeviceToDevice, s));
     if (infos) {
@@ -380,6 +393,32 @@ static tci_status gather(tci_context ctx, int dt, const void* src, long long str
     TCI_CHECK_HIP(hipMemcpyAsync(dst + es * stride * i, static_cast<const char*>(src) + es * stride * idx[i],
                                  es * stride, hipMemcpyDeviceToDevice, ctx->stream));
   *out = dst;
+  return TCI_OK;
+}
+
+// Direction and Vidal weights of an update batch: lambda_left[i] / lambda_right[i]
+// F64 vectors of chil / chir finite positive entries (checked on the host).
+static tci_status check_direction(tci_context ctx, const tci_update_params& p, int nupd, int64_t chil,
+                                  int64_t chir) {
+  if (p.direction != TCI_DIR_LEFT && p.direction != TCI_DIR_RIGHT && p.direction != TCI_DIR_VIDAL)
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad direction");
+  if (p.direction != TCI_DIR_VIDAL) return TCI_OK;
+  if (!p.lambda_left || !p.lambda_right) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "TCI_DIR_VIDAL needs lambda_left/right");
+  std::vector<double> h;
+  for (int i = 0; i < nupd; ++i) {
+    for (int side = 0; side < 2; ++side) {
+      const tci_tensor l = side ? p.lambda_right[i] : p.lambda_left[i];
+      const int64_t want = side ? chir : chil;
+      if (!l || l->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null Vidal weight tensor");
+      if (l->dtype != TCI_F64 || l->order != 1 || l->shape[0] != want)
+        TCI_RET(TCI_ERR_SHAPE, "Vidal weights must be F64 vectors of the outer bond dimensions");
+      h.resize((size_t)want);
+      TCI_CHECK_HIP(hipMemcpyAsync(h.data(), l->data, sizeof(double) * want, hipMemcpyDeviceToHost, ctx->stream));
+      TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+      for (double x : h)
+        if (!(x > 0.0) || !std::isfinite(x)) TCI_RET(TCI_ERR_NUMERIC, "Vidal weights must be finite and positive");
+    }
+  }
   return TCI_OK;
 }
 
@@ -463,7 +502,8 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
     const void* hi = thw;
     if ((int)plain_idx.size() != nb) TCI_TRY(gather(ctx, wdt, thw, smn, plain_idx, &hi));
     TsvdOut o;
-    TCI_TRY(tsvd_run(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
+    if (ng <= JACOBI_MAX_K) TCI_TRY(tsvd_small(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
+    else TCI_TRY(tsvd_run(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
     TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, plain_idx, p, A_out, s_out, B_out, infos, nullptr,
                           p.svd_mode != TCI_SVD_PLAIN, &kvec));
   }
@@ -478,7 +518,7 @@ extern "C" {
 
 tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s, tci_tensor vdag,
                          double* trunc_err, int64_t chi_min, int64_t chi_max, double target_trunc_err,
-                         double s_min) {
+                         double s_min) try {
   if (!ctx || !a || !u || !s || !vdag) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   if (a->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "moved-from tensor");
   if (chi_min < 1 || chi_max < 1 || chi_min > chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
@@ -494,8 +534,24 @@ tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u
   TruncParams tp{(int)std::min<int64_t>(chi_min, kap), (int)std::min<int64_t>(chi_max, kap), target_trunc_err, s_min};
   if (tp.chi_min > tp.chi_max) tp.chi_min = tp.chi_max;
   TsvdOut o;
-  if (kap <= JACOBI_MAX_K) TCI_TRY(tsvd_small(ctx, wdt, (int)rows, (int)cols, w, tp, o));
-  else TCI_TRY(tsvd_run(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
+  bool done = false;
+  // Context svd mode RANDOMIZED: sketch of rank chi_max + 64 (q = 2), kept
+  // when the discarded weight meets the target and the residual certificate
+  // holds; otherwise the plain truncated SVD below decides.
+  const int k_sk = (int)std::min<int64_t>(kap, 32 * ((tp.chi_max + 64 + 31) / 32));
+  if (ctx->svd_mode == TCI_SVD_RANDOMIZED && kap > JACOBI_MAX_K && target_trunc_err > 0.0 && k_sk < kap) {
+    std::vector<double> resid;
+    const int prec = is_double(a->dtype) ? PREC_FP64 : ctx->precision;
+    TCI_TRY(sketch_run(ctx, a->dtype, wdt, prec, 1, (int)rows, (int)cols, a->data, w, tp, {k_sk}, 2, 0, {0u}, o,
+                       resid));
+    done = o.err_h[0] <= target_trunc_err && resid[0] <= 1e-7;
+    tr.info += done ? " randomized k=" + std::to_string(k_sk) : " randomized k=" + std::to_string(k_sk) + " fallback";
+  }
+  if (!done) {
+    o = TsvdOut{};
+    if (kap <= JACOBI_MAX_K) TCI_TRY(tsvd_small(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
+    else TCI_TRY(tsvd_run(ctx, wdt, 1, (int)rows, (int)cols, w, tp, o));
+  }
   const int chi = o.chi_h[0];
   // outputs
   int64_t ushape[MAX_ORDER + 1];
@@ -522,15 +578,15 @@ tci_status tci_trunc_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   if (trunc_err) *trunc_err = o.err_h[0];
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s, tci_tensor vdag) {
+tci_status tci_svd(tci_context ctx, tci_tensor a, int k_rows, tci_tensor u, tci_tensor s, tci_tensor vdag) try {
   if (!a) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   int64_t rows, cols;
   TCI_TRY(matricize(a, k_rows, rows, cols));
   const int64_t kap = std::min(rows, cols);
   return tci_trunc_svd(ctx, a, k_rows, u, s, vdag, nullptr, kap, kap, 0.0, 0.0);
-}
+} TCI_API_CATCH
 
 // Thin QR of the m x k (m >= k) working-precision matrix at w: Y (m x k)
 // receives Q and R (k x k) the triangular factor.  Two Cholesky-QR passes,
@@ -561,7 +617,7 @@ static tci_status qr_core(tci_context ctx, int wdt, int m, int k, const void* w,
   return TCI_OK;
 }
 
-tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r) {
+tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_tensor r) try {
   if (!ctx || !a || !q || !r) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   int64_t rows, cols;
@@ -587,7 +643,7 @@ tci_status tci_qr(tci_context ctx, tci_tensor a, int k_rows, tci_tensor q, tci_t
   TCI_TRY(store_as(ctx, wdt, R, r));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // Conjugate transpose of a rows x cols working-precision matrix.
 static tci_status conj_transpose(tci_context ctx, int wdt, const void* in, int rows, int cols, void* out) {
@@ -598,7 +654,7 @@ static tci_status conj_transpose(tci_context ctx, int wdt, const void* in, int r
   return TCI_OK;
 }
 
-tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_tensor q) {
+tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_tensor q) try {
   if (!ctx || !a || !l || !q) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   int64_t rows, cols;
@@ -634,13 +690,13 @@ tci_status tci_lq(tci_context ctx, tci_tensor a, int k_rows, tci_tensor l, tci_t
   TCI_TRY(store_as(ctx, wdt, Qw, q));
   TCI_CHECK_HIP(hipStreamSynchronize(ctx->stream));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 // Matrix exponential by scaling and squaring with a Taylor polynomial, in
 // FP64 for every dtype: B = A / 2^s with ||B||_F <= 1/2, exp(B) ~ sum_{j <= 18}
 // B^j / j! by Horner's rule (P <- I + B P / j for j = 18 .. 1; truncation
 // below 2^-19 / 19! ~ 1.6e-23 relative), then s squarings.
-tci_status tci_exp(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) {
+tci_status tci_exp(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) try {
   if (!ctx || !in || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   int64_t rows, cols;
@@ -693,9 +749,9 @@ tci_status tci_exp(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) {
   TCI_TRY(store_as(ctx, wdt, P, out));
   TCI_CHECK_HIP(hipStreamSynchronize(st));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) {
+tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor out) try {
   if (!ctx || !in || !out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   int64_t rows, cols;
@@ -735,20 +791,27 @@ tci_status tci_inverse(tci_context ctx, tci_tensor in, int k_rows, tci_tensor ou
   TCI_TRY(store_as(ctx, wdt, res, out));
   TCI_CHECK_HIP(hipStreamSynchronize(st));
   return TCI_OK;
-}
+} TCI_API_CATCH
 
-tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v) {
-  if (!ctx || !a || !w || !v) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+// Spec eigh / eigvalsh: Hermitian eigensolve of the matricised tensor in
+// FP64 (single-precision inputs promoted); v == nullptr skips the vectors.
+static tci_status eigh_core(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v) {
+  if (!ctx || !a || !w) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (a->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "moved-from tensor");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
-  if (a->order != 2 || a->shape[0] != a->shape[1]) TCI_RET(TCI_ERR_SHAPE, "eigh needs a square matrix");
-  if (!is_double(a->dtype)) TCI_RET(TCI_ERR_DTYPE, "eigh supports F64 / C128");
-  Trace tr(ctx, "eigh", std::to_string(a->shape[0]));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  if (rows != cols) TCI_RET(TCI_ERR_SHAPE, "eigh needs a square matricisation (I == J)");
+  Trace tr(ctx, v ? "eigh" : "eigvalsh", std::to_string(rows));
   ctx->arena.reset();
-  const int n = (int)a->shape[0], dt = a->dtype;
+  const int n = (int)rows, odt = a->dtype;
+  int dt;
+  const void* src;
+  TCI_TRY(working_copy(ctx, a, dt, src));
   const size_t es = elem_bytes(dt);
   hipStream_t s = ctx->stream;
   ARENA(G, char, es * (size_t)n * n);
-  TCI_CHECK_HIP(hipMemcpyAsync(G, a->data, es * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(G, src, es * (size_t)n * n, hipMemcpyDeviceToDevice, s));
   ARENA(d, double, n);
   ARENA(e, double, n);
   ARENA(e2, double, n);
@@ -765,48 +828,75 @@ tci_status tci_eigh(tci_context ctx, tci_tensor a, tci_tensor w, tci_tensor v) {
   TCI_CHECK_HIP(tridiagonalize(dt, ta, 1, s));
   ARENA(lam, double, n);
   TCI_CHECK_HIP(tridiag_eigvals_top(d, e, e2, n, n, n, lam, n, 1, s));
-  ARENA(Z, double, (size_t)n * n);
-  ARENA(Z2, double, (size_t)n * n);
-  ARENA(iw, double, (size_t)4 * n * n);
-  TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)n * n, s));
-  TCI_CHECK_HIP(tridiag_invit(d, e, n, n, lam, n, nullptr, n, Z, n, 0, iw, 1, s));
-  TCI_TRY(cholqr2(ctx, F64, 0, Z, n, 0, n, n, Z2, 1));
-  void* Ev = Z;
-  if (is_complex(dt)) {
-    Ev = ctx->arena.get(es * (size_t)n * n);
-    if (!Ev) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
-    TCI_CHECK_HIP(real_to_complex(Z, Ev, (long long)n * n, 0, 0, 1, s));
+  void* Ev = nullptr;
+  if (v) {
+    ARENA(Z, double, (size_t)n * n);
+    ARENA(Z2, double, (size_t)n * n);
+    ARENA(iw, double, (size_t)4 * n * n);
+    TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)n * n, s));
+    TCI_CHECK_HIP(tridiag_invit(d, e, n, n, lam, n, nullptr, n, Z, n, 0, iw, 1, s));
+    TCI_TRY(cholqr2(ctx, F64, 0, Z, n, 0, n, n, Z2, 1));
+    Ev = Z;
+    if (is_complex(dt)) {
+      Ev = ctx->arena.get(es * (size_t)n * n);
+      if (!Ev) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+      TCI_CHECK_HIP(real_to_complex(Z, Ev, (long long)n * n, 0, 0, 1, s));
+    }
+    const size_t tfe = tridiag_backtransform_tf_elems(n);
+    ARENA(Tf, char, es * tfe);
+    ARENA(btw, char, es * tridiag_backtransform_work_elems(n));
+    TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, (long long)tfe, Ev, n, 0, n, btw, 1, s));
+    // ascending order: reverse the descending bisection order
+    TCI_CHECK_HIP(reverse_columns(dt, Ev, n, n, n, s));
+    TCI_CHECK_HIP(gauge_columns(dt, Ev, n, 0, n, n, nullptr, 1, s));
   }
-  const size_t tfe = tridiag_backtransform_tf_elems(n);
-  ARENA(Tf, char, es * tfe);
-  ARENA(btw, char, es * tridiag_backtransform_work_elems(n));
-  TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, (long long)tfe, Ev, n, 0, n, btw, 1, s));
-  // ascending order: reverse the descending bisection order
-  TCI_CHECK_HIP(reverse_columns(dt, Ev, n, n, n, s));
-  TCI_CHECK_HIP(gauge_columns(dt, Ev, n, 0, n, n, nullptr, 1, s));
   std::vector<double> lh(n);
   TCI_CHECK_HIP(hipMemcpyAsync(lh.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   TCI_CHECK_HIP(hipStreamSynchronize(s));
   std::reverse(lh.begin(), lh.end());
-  int64_t wshape[1] = {n}, vshape[2] = {n, n};
-  TCI_TRY(ensure_shape(ctx, w, F64, 1, wshape));
-  TCI_TRY(ensure_shape(ctx, v, dt, 2, vshape));
-  TCI_CHECK_HIP(hipMemcpyAsync(w->data, lh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(v->data, Ev, es * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+  for (double x : lh)
+    if (!std::isfinite(x)) TCI_RET(TCI_ERR_NUMERIC, "non-finite eigenvalues (non-finite input?)");
+  const int rdt = is_double(odt) ? F64 : F32;
+  int64_t wshape[1] = {n};
+  TCI_TRY(ensure_shape(ctx, w, rdt, 1, wshape));
+  ARENA(wd, double, n);
+  TCI_CHECK_HIP(hipMemcpyAsync(wd, lh.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  TCI_TRY(store_as(ctx, F64, wd, w));
+  if (v) {
+    int64_t vshape[MAX_ORDER + 1];
+    for (int i = 0; i < k_rows; ++i) vshape[i] = a->shape[i];
+    vshape[k_rows] = n;
+    TCI_TRY(ensure_shape(ctx, v, odt, k_rows + 1, vshape));
+    TCI_TRY(store_as(ctx, dt, Ev, v));
+  }
   TCI_CHECK_HIP(hipStreamSynchronize(s));
   return TCI_OK;
 }
+
+tci_status tci_eigh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v) try {
+  if (!v) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  return eigh_core(ctx, a, k_rows, w, v);
+} TCI_API_CATCH
+
+tci_status tci_eigvalsh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w) try {
+  return eigh_core(ctx, a, k_rows, w, nullptr);
+} TCI_API_CATCH
 
 // ----------------------------------------------------------------- two-site update
 tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tensor* A, const tci_tensor* B,
                                        const tci_tensor* gates, const tci_update_params* params,
                                        tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out,
-                                       tci_update_info* infos) {
+                                       tci_update_info* infos) try {
   if (!ctx || nupd < 1 || !A || !B || !A_out || !s_out || !B_out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   tci_update_params p;
-  if (params) p = *params;
-  else tci_update_params_default(&p);
+  if (params) {
+    p = *params;
+  } else {
+    tci_update_params_default(&p);
+    p.svd_mode = ctx->svd_mode;
+    if (A[0] && !is_double(A[0]->dtype)) p.precision = ctx->precision;
+  }
   if (p.chi_min < 1 || p.chi_max < 1 || p.chi_min > p.chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
   const tci_tensor a0 = A[0], b0 = B[0];
   if (!a0 || !b0 || a0->order != 3 || b0->order != 3) TCI_RET(TCI_ERR_SHAPE, "A and B must be order 3");
@@ -825,6 +915,7 @@ tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tens
     }
   }
   if (gates && d != 2) TCI_RET(TCI_ERR_UNSUPPORTED, "gates are supported for d = 2");
+  TCI_TRY(check_direction(ctx, p, nupd, chil, chir));
   const int prec = p.precision;
   if (is_double(dt) != (prec == TCI_PREC_FP64))
     TCI_RET(TCI_ERR_DTYPE, "FP64 precision needs F64/C128 tensors, mixed precisions F32/C64");
@@ -882,20 +973,33 @@ tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tens
       TCI_CHECK_HIP(convert(dt, th, wdt, tw, smn * nb, s));
       thw = tw;
     }
-    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, th, thw, p, c0, A_out + c0,
+    tci_update_params pc = p;  // Vidal weights indexed like the outputs of this chunk
+    if (pc.lambda_left) pc.lambda_left += c0;
+    if (pc.lambda_right) pc.lambda_right += c0;
+    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, th, thw, pc, c0, A_out + c0,
                             s_out + c0, B_out + c0, infos ? infos + c0 : nullptr));
     TCI_CHECK_HIP(hipStreamSynchronize(s));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
+
+tci_status tci_two_site_update(tci_context ctx, tci_tensor A, tci_tensor B, tci_tensor gate,
+                               const tci_update_params* params, tci_tensor A_out, tci_tensor s_out, tci_tensor B_out,
+                               tci_update_info* info) try {
+  return tci_two_site_update_batched(ctx, 1, &A, &B, gate ? &gate : nullptr, params, &A_out, &s_out, &B_out, info);
+} TCI_API_CATCH
 
 tci_status tci_split_batched(tci_context ctx, int nupd, const tci_tensor* theta, const tci_update_params* params,
-                             tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos) {
+                             tci_tensor* A_out, tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos) try {
   if (!ctx || nupd < 1 || !theta || !A_out || !s_out || !B_out) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
   TCI_CHECK_HIP(hipSetDevice(ctx->device));
   tci_update_params p;
-  if (params) p = *params;
-  else tci_update_params_default(&p);
+  if (params) {
+    p = *params;
+  } else {
+    tci_update_params_default(&p);
+    p.svd_mode = ctx->svd_mode;
+  }
   if (p.chi_min < 1 || p.chi_max < 1 || p.chi_min > p.chi_max) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "need 1 <= chi_min <= chi_max");
   const tci_tensor t0 = theta[0];
   if (!t0 || t0->order != 4) TCI_RET(TCI_ERR_SHAPE, "theta must be order 4 (chi_l, d, d, chi_r)");
@@ -908,6 +1012,7 @@ tci_status tci_split_batched(tci_context ctx, int nupd, const tci_tensor* theta,
     for (int k = 0; k < 4; ++k)
       if (theta[i]->shape[k] != t0->shape[k]) TCI_RET(TCI_ERR_SHAPE, "all thetas of a batch must have one shape");
   }
+  TCI_TRY(check_direction(ctx, p, nupd, chil, chir));
   Trace tr(ctx, "split_batched", std::to_string(nupd) + " x " + std::to_string(chil) + "," + std::to_string(chir));
   const int wdt = work_dtype(dt);
   const size_t es = elem_bytes(dt), wes = elem_bytes(wdt);
@@ -926,10 +1031,13 @@ tci_status tci_split_batched(tci_context ctx, int nupd, const tci_tensor* theta,
       TCI_CHECK_HIP(convert(dt, tl, wdt, t64, smn * nb, s));
       tw = t64;
     }
-    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, tl, tw, p, c0, A_out + c0, s_out + c0,
+    tci_update_params pc = p;
+    if (pc.lambda_left) pc.lambda_left += c0;
+    if (pc.lambda_right) pc.lambda_right += c0;
+    TCI_TRY(split_and_store(ctx, dt, wdt, nb, (int)chil, (int)d, (int)chir, tl, tw, pc, c0, A_out + c0, s_out + c0,
                             B_out + c0, infos ? infos + c0 : nullptr));
   }
   return TCI_OK;
-}
+} TCI_API_CATCH
 
 }  // extern "C"

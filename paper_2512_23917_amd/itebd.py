@@ -1,24 +1,25 @@
 """Infinite TEBD for the transverse-field Ising chain on the library (the
-application of the paper's App. A, in the Vidal form with inverse singular
-values).
+application of the paper's App. A, in the Vidal form).
 
 Model (Sec. IV, eq. (1)): H = -J sum_i Z_i Z_{i+1} - g sum_i X_i, split into
 bond terms h = -J Z Z - (g/2)(X I + I X).  The imaginary-time gate
 U = exp(-dt h) is symmetric, so contracting either of its index pairs gives
 the same update; the library applies rows = outgoing pair.
 
-Two-site unit cell (Gamma_A, lambda_A, Gamma_B, lambda_B); lambda_A sits on
-the A-B bond, lambda_B on the B-A bond.  One step updates the bond (X, Y)
-with inner weights l_i and outer weights l_o:
+State: a two-site unit cell (Gamma_A, lambda_A, Gamma_B, lambda_B), where
+lambda_A sits on the A-B bond and lambda_B on the B-A bond.  Updating the
+bond (X, Y) with inner weights l_i and outer weights l_o is one two-site
+update of the pair
 
-    theta = diag(l_o) Gamma_X diag(l_i) Gamma_Y diag(l_o)      (chi, 2, 2, chi)
-    theta' = U theta;   U_, s, V^dag = trunc_svd(theta', 2 row bonds)
-    l_i <- s / ||s||;   Gamma_X <- diag(1/l_o) U_;   Gamma_Y <- V^dag diag(1/l_o)
+    A' = diag(l_o) Gamma_X diag(l_i),   B' = Gamma_Y diag(l_o)
 
-first for (A, B), then for (B, A).  Every contraction, the gate and the
-truncated SVD run in the library (FP64); the weights are moved to the host
-only to build the diagonal factors.  The energy per site is the mean over
-the two bonds of <theta|h|theta> / <theta|theta>.
+(so that theta = A' B' carries every weight of the bond's environment): the
+composite forms theta, applies the gate, truncates, renormalises the kept
+values into the new l_i and writes the Vidal factors
+Gamma_X = diag(1/l_o) U and Gamma_Y = V^dag diag(1/l_o) on the device.  The
+weights never leave the device; the bond (A, B) is updated first, then
+(B, A).  The energy per site is the mean over the two bonds of
+<theta|h|theta> / <theta|theta>.
 """
 from __future__ import annotations
 
@@ -48,38 +49,39 @@ class ITEBD:
         up = np.zeros((1, 2, 1))
         up[0, 0, 0] = 1.0
         self.G = [self._t(up), self._t(up)]
-        self.lam = [np.ones(1), np.ones(1)]
+        self.lam = [self._t(np.ones(1)), self._t(np.ones(1))]
         self.h4 = self._t(bond_hamiltonian(g, J).reshape(2, 2, 2, 2))
+        self.params = tci.update_params(chi_min=1, chi_max=chi, target_trunc_err=0.0, s_min=s_min,
+                                        direction=tci.DIR_VIDAL, precision=tci.PREC_FP64)
 
     def _t(self, a: np.ndarray) -> tci.Tensor:
         return tci.Tensor.from_numpy(self.ctx, np.ascontiguousarray(a, dtype=np.float64), tci.F64)
 
-    def _theta(self, X: int) -> tci.Tensor:
+    def _pair(self, X: int):
+        """The bond's site tensors with the environment weights absorbed."""
         Y = 1 - X
         c = self.ctx
-        do, di = self._t(np.diag(self.lam[Y])), self._t(np.diag(self.lam[X]))
-        t = tci.contract(c, do, "ax", self.G[X], "xsm", "asm")
-        t = tci.contract(c, t, "asm", di, "mn", "asn")
-        t = tci.contract(c, t, "asn", self.G[Y], "ntx", "astx")
-        return tci.contract(c, t, "astx", do, "xb", "astb")
+        lo, li = tci.diag(c, self.lam[Y]), tci.diag(c, self.lam[X])
+        a = tci.contract(c, lo, "ax", self.G[X], "xsm", "asm")
+        a = tci.contract(c, a, "asm", li, "mn", "asn")
+        b = tci.contract(c, self.G[Y], "ntx", lo, "xb", "ntb")
+        return a, b
 
     def step(self, gate4: tci.Tensor):
-        c = self.ctx
         for X in (0, 1):
             Y = 1 - X
-            th = tci.contract(c, self._theta(X), "astb", gate4, "uvst", "auvb")
-            u, s, vh, _ = tci.trunc_svd(c, th, 2, 1, self.chi, 0.0, self.s_min)
-            sv = s.numpy().astype(np.float64)
-            self.lam[X] = sv / np.linalg.norm(sv)
-            dinv = self._t(np.diag(1.0 / self.lam[Y]))
-            self.G[X] = tci.contract(c, dinv, "ax", u, "xsk", "ask")
-            self.G[Y] = tci.contract(c, vh, "ktx", dinv, "xb", "ktb")
+            a, b = self._pair(X)
+            lam_o = self.lam[Y]
+            A_out, s_out, B_out, _ = tci.two_site_update_batched(self.ctx, [a], [b], [gate4], self.params,
+                                                                 lambda_left=[lam_o], lambda_right=[lam_o])
+            self.G[X], self.lam[X], self.G[Y] = A_out[0], s_out[0], B_out[0]
 
     def energy(self) -> float:
         c = self.ctx
         es = []
         for X in (0, 1):
-            th = self._theta(X)
+            a, b = self._pair(X)
+            th = tci.contract(c, a, "asm", b, "mtb", "astb")
             hth = tci.contract(c, th, "astb", self.h4, "uvst", "auvb")
             num = tci.contract(c, th, "astb", hth, "astb", "").numpy().reshape(-1)[0]
             den = tci.contract(c, th, "astb", th, "astb", "").numpy().reshape(-1)[0]

@@ -21,6 +21,20 @@ The spectra are the exact singular values of the matrices these workloads
 build (theta = U diag(s) V^T with orthogonal U, V); a GPU test checks the
 library's truncated SVD against them.
 
+Spectra from the method's own updates (``make_update_pairs``): the library
+runs two-site updates at chi = 1024, d = 2 whose input bond carries a known
+spectrum (A = U diag(s), B = V^dagger with Haar isometries U, V drawn from a
+pool, s a power law with alpha ~ U[1, 3] or an exponential decay), followed by
+a Haar-random two-site gate; the input is the features of s (the bond's
+spectrum before the update) and the target is log2 of the bond dimension the
+truncation rule keeps for eps with no cap (chi_max = 2048, so the kept chi
+is chi* itself).  The gate spreads the spectrum, so chi* after the update is
+two to four times the chi* of s; this is the workload of the two-site update
+benchmark.
+
+The shipped weights are trained on 50k pairs: 12k from the library's updates
+and the rest from the closed-form sweeps above.
+
 Training: Adam (lr 1e-3), batch 256, 30 epochs, 90/10 train/validation
 split, all on the GPU through ``tci_sketch_train_step`` (hand-written
 forward, backward and Adam kernels).
@@ -119,6 +133,52 @@ def make_pairs(n_samples: int, seed: int, n: int = 2048, chi_max: int = 1024, ep
     return prev, np.asarray(targ)
 
 
+def update_input(rng: np.random.Generator, chi: int, alpha_range=(1.0, 3.0), exp_frac: float = 0.2) -> np.ndarray:
+    """Spectrum of the input bond of one sampled update (unit 2-norm)."""
+    if rng.random() < exp_frac:
+        return exp_decay(chi, 10.0 ** rng.uniform(1.0, 3.0))
+    return power_law(chi, rng.uniform(*alpha_range))
+
+
+def make_update_pairs(ctx, n_samples: int, seed: int, chi: int = 1024, d: int = 2, eps: float = 1e-8,
+                      batch: int = 32, pool: int = 8, alpha_range=(1.0, 3.0), exp_frac: float = 0.2,
+                      log=None):
+    """(input spectra, targets log2 chi*) from the library's own two-site
+    updates: A = U diag(s) (chi, d, chi), B = V^dagger (chi, d, chi), a Haar
+    gate, complex64 storage with split-BF16x3 products and the plain FP64
+    truncated SVD at eps with chi_max = chi d (uncapped), so info.chi = chi*.
+    U, V come from a pool of `pool` Haar isometries each (generated on the
+    host), combined at random per update."""
+    import torch
+    from . import synth
+    rng = np.random.default_rng(seed)
+    dev = ctx.torch_device
+    us = [torch.from_numpy(synth.haar(rng, chi * d, chi)).to(dev, torch.complex64) for _ in range(pool)]
+    vhs = [torch.from_numpy(synth.haar(rng, d * chi, chi).conj().T.copy()).to(dev, torch.complex64)
+           for _ in range(pool)]
+    p = tci.update_params(chi_min=1, chi_max=chi * d, target_trunc_err=eps, direction=tci.DIR_RIGHT,
+                          precision=tci.PREC_BF16X3)
+    prev, targ = [], []
+    while len(targ) < n_samples:
+        nb = min(batch, n_samples - len(targ))
+        A, B, G, sp = [], [], [], []
+        for _ in range(nb):
+            s = update_input(rng, chi, alpha_range, exp_frac)
+            i, j = rng.integers(pool, size=2)
+            sd = torch.as_tensor(s, dtype=torch.float32, device=dev)
+            A.append(tci.Tensor(ctx, (us[i] * sd[None, :]).contiguous(), (chi, d, chi)))
+            B.append(tci.Tensor(ctx, vhs[j], (chi, d, chi)))
+            G.append(tci.Tensor.from_numpy(ctx, synth.haar_gate(rng).astype(np.complex64), tci.C64))
+            sp.append(s)
+        _, _, _, infos = tci.two_site_update_batched(ctx, A, B, G, p)
+        for s, inf in zip(sp, infos):
+            prev.append(s)
+            targ.append(math.log2(inf.chi))
+        if log is not None:
+            log(f"  update pairs {len(targ)}/{n_samples}")
+    return prev, np.asarray(targ)
+
+
 def features(ctx, spectra, chi_max: int, d: int, eps: float, chunk: int = 2048):
     import torch
     rows = [tci.sketch_features(ctx, spectra[i:i + chunk], chi_max, d, eps) for i in range(0, len(spectra), chunk)]
@@ -166,19 +226,45 @@ def train(ctx, X, T, epochs: int = 30, batch: int = 256, lr: float = 1e-3, seed:
     return m, hist
 
 
+def make_mixed_dataset(ctx, n_samples: int, n_updates: int, seed: int, chi_max: int = 1024, d: int = 2,
+                       eps: float = 1e-8, log=None):
+    """n_updates pairs from the library's updates plus closed-form sweep
+    pairs up to n_samples; features on the GPU."""
+    import torch
+    prev_u, targ_u = make_update_pairs(ctx, n_updates, seed + 1, chi=chi_max, d=d, eps=eps, log=log)
+    X_u = features(ctx, prev_u, chi_max, d, eps)
+    X_c, T_c = make_dataset(ctx, n_samples - n_updates, seed, chi_max=chi_max, d=d, eps=eps)
+    T_u = torch.as_tensor(targ_u, dtype=torch.float32, device=ctx.torch_device)
+    return torch.cat([X_u, X_c], 0), torch.cat([T_u, T_c], 0)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Train the sketch-rank predictor on the GPU")
     ap.add_argument("--samples", type=int, default=50000)
+    ap.add_argument("--update-samples", type=int, default=12000,
+                    help="pairs generated by the library's own two-site updates (the rest: closed-form sweeps)")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args(argv)
+    import time
     ctx = tci.Context(0)
-    X, T = make_dataset(ctx, args.samples, args.seed)
+    t0 = time.time()
+    log = lambda m: print(m, flush=True)
+    X, T = make_mixed_dataset(ctx, args.samples, args.update_samples, args.seed, log=log)
+    log(f"dataset {X.shape[0]} pairs in {time.time() - t0:.1f}s")
     m, hist = train(ctx, X, T, epochs=args.epochs, seed=args.seed)
     m.save(args.out)
-    print(f"samples {args.samples}  epochs {args.epochs}  final train {hist['train'][-1]:.4f}  "
-          f"val {hist['val'][-1]:.4f}  -> {args.out}", flush=True)
+    # held-out pairs from the library's updates: coverage of chi* by the prediction
+    prev, targ = make_update_pairs(ctx, 512, args.seed + 977)
+    y = m.predict(features(ctx, prev, 1024, 2, 1e-8)).cpu().numpy().astype(np.float64)
+    cover = float(np.mean(y >= targ))
+    sketchable = targ <= math.log2(1024)
+    print(f"samples {X.shape[0]}  epochs {args.epochs}  final train {hist['train'][-1]:.4f}  "
+          f"val {hist['val'][-1]:.4f}  held-out update pairs: coverage {cover:.3f}, "
+          f"chi* <= 1024 on {np.mean(sketchable):.3f}, predicted plain on "
+          f"{np.mean(y[~sketchable] > math.log2(1024)) if (~sketchable).any() else float('nan'):.3f} of the rest "
+          f"-> {args.out}", flush=True)
 
 
 if __name__ == "__main__":

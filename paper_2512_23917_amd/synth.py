@@ -112,6 +112,27 @@ def two_site_blocks_from_spectrum(g: np.random.Generator, chi: int, d: int,
     return a, b
 
 
+def isometry_pool(config: int, n_pool: int, rows: int, cols: int, complex_: bool = True) -> list:
+    """n_pool Haar isometries rows x cols from the generator of (config, 0)."""
+    g = rng(config, 0)
+    return [haar(g, rows, cols, complex_) for _ in range(n_pool)]
+
+
+def power_law_update(g: np.random.Generator, us: list, vs: list, chi: int, d: int = 2,
+                     alpha_range=(1.0, 3.0)):
+    """Inputs of one two-site update with a power-law bond: alpha ~ U[alpha_range],
+    s_k ~ k^-alpha (k = 1..chi, unit 2-norm), A = U diag(s) as (chi, d, chi) and
+    B = V^dagger as (chi, d, chi) with U, V drawn from the pools (Haar
+    (chi d) x chi isometries), and a Haar two-site gate.
+    Returns (alpha, s, A, B, gate)."""
+    alpha = float(g.uniform(*alpha_range))
+    s = power_spectrum(chi, alpha)
+    i, j = (int(x) for x in g.integers(len(us), size=2))
+    a = (us[i] * s[None, :]).reshape(chi, d, chi)
+    b = vs[j].conj().T.reshape(chi, d, chi)
+    return alpha, s, a, b, haar_gate(g, d)
+
+
 def gaussian_two_site_blocks(g: np.random.Generator, chi: int, d: int = 2,
                              complex_: bool = True):
     if complex_:

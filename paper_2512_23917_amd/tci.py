@@ -21,10 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libtci_mi355x.so")
 F32, F64, C64, C128 = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 SVD_PLAIN, SVD_RANDOMIZED, SVD_LEARNED = 0, 1, 2
-DIR_LEFT, DIR_RIGHT = 0, 1
+DIR_LEFT, DIR_RIGHT, DIR_VIDAL = 0, 1, 2
 
 STATUS = {0: "OK", 1: "INVALID_ARGUMENT", 2: "SHAPE", 3: "LABEL", 4: "DTYPE", 5: "OUT_OF_MEMORY",
-          6: "DEVICE", 7: "NOT_CONVERGED", 8: "NUMERIC", 9: "UNSUPPORTED"}
+          6: "DEVICE", 7: "NOT_CONVERGED", 8: "NUMERIC", 9: "UNSUPPORTED", 10: "INTERNAL"}
 
 TORCH_OF = {F32: torch.float32, F64: torch.float64, C64: torch.complex64, C128: torch.complex128}
 DTYPE_OF = {v: k for k, v in TORCH_OF.items()}
@@ -45,7 +45,9 @@ class UpdateParams(ctypes.Structure):
                 ("svd_mode", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("cert_tol", ctypes.c_double),
-                ("sketch_model", ctypes.c_void_p), ("prev_spectra", ctypes.POINTER(ctypes.c_void_p))]
+                ("sketch_model", ctypes.c_void_p), ("prev_spectra", ctypes.POINTER(ctypes.c_void_p)),
+                ("lambda_left", ctypes.POINTER(ctypes.c_void_p)),
+                ("lambda_right", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -53,6 +55,19 @@ class UpdateInfo(ctypes.Structure):
                 ("discarded_abs", ctypes.c_double), ("norm2", ctypes.c_double),
                 ("used_fallback", ctypes.c_int32), ("sketch_rank", ctypes.c_int32),
                 ("max_residual", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class ContextOpts(ctypes.Structure):
+    _fields_ = [("allocator", Allocator), ("precision", ctypes.c_int32), ("svd_mode", ctypes.c_int32),
+                ("autotune_cache", ctypes.c_char_p), ("verbosity", ctypes.c_int32)]
 
 
 _lib = None
@@ -71,7 +86,8 @@ def lib():
     sig = {
         "tci_version": (ctypes.c_char_p, []),
         "tci_last_error": (ctypes.c_char_p, []),
-        "tci_create_context": (i32, [P(p), ctypes.c_int, p]),
+        "tci_context_opts_default": (None, [P(ContextOpts)]),
+        "tci_create_context": (i32, [P(p), ctypes.c_int, p, P(ContextOpts)]),
         "tci_destroy_context": (i32, [p]),
         "tci_set_stream": (i32, [p, p]),
         "tci_set_precision": (i32, [p, ctypes.c_int]),
@@ -106,7 +122,8 @@ def lib():
         "tci_svd": (i32, [p, p, ctypes.c_int, p, p, p]),
         "tci_trunc_svd": (i32, [p, p, ctypes.c_int, p, p, p, P(f64), i64, i64, f64, f64]),
         "tci_qr": (i32, [p, p, ctypes.c_int, p, p]),
-        "tci_eigh": (i32, [p, p, p, p]),
+        "tci_eigh": (i32, [p, p, ctypes.c_int, p, p]),
+        "tci_eigvalsh": (i32, [p, p, ctypes.c_int, p]),
         "tci_close": (i32, [p, p, p, f64, P(ctypes.c_int)]),
         "tci_fill": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), p, P(p)]),
         "tci_eye": (i32, [p, ctypes.c_int, i64, P(p)]),
@@ -130,6 +147,7 @@ def lib():
         "tci_update_params_default": (None, [P(UpdateParams)]),
         "tci_two_site_update_batched": (i32, [p, ctypes.c_int, P(p), P(p), P(p), P(UpdateParams),
                                               P(p), P(p), P(p), P(UpdateInfo)]),
+        "tci_two_site_update": (i32, [p, p, p, p, P(UpdateParams), p, p, p, P(UpdateInfo)]),
         "tci_split_batched": (i32, [p, ctypes.c_int, P(p), P(UpdateParams), P(p), P(p), P(p), P(UpdateInfo)]),
         "tci_heff_matvec": (i32, [p, p, p, p, p, p, p]),
         "tci_lanczos_ground": (i32, [p, p, p, p, p, p, ctypes.c_int, P(f64)]),
@@ -182,18 +200,58 @@ def _i32(seq):
 
 
 class Context:
-    """tci_create_context on a torch device, ordered on its current stream."""
+    """tci_create_context on a torch device, ordered on its current stream.
 
-    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+    torch_allocator: the library's device memory (workspace chunks and any
+    storage it allocates) comes from torch's caching allocator through the
+    tci_allocator callbacks, so it shows up in torch's memory statistics and
+    is shared with torch's pool.  precision / svd_mode / autotune_cache /
+    verbosity are the other tci_context_opts fields (None: library default).
+    """
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, torch_allocator: bool = True,
+                 precision: int | None = None, svd_mode: int | None = None, autotune_cache: str | None = None,
+                 verbosity: int | None = None, allocator: tuple | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP library needs an MI355X")
         self.device = device
         self.torch_device = torch.device("cuda", device)
         st = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
         self.stream = st
+        opts = ContextOpts()
+        lib().tci_context_opts_default(ctypes.byref(opts))
+        self._callbacks = None
+        if allocator is not None:                 # (alloc(bytes, stream) -> int, free(ptr, bytes, stream))
+            fa, ff = allocator
+            self._callbacks = (ALLOC_FN(lambda n, s, u: fa(n, s) or None),
+                               FREE_FN(lambda ptr, n, s, u: ff(ptr, n, s)))
+        elif torch_allocator:
+            dev = device
+
+            def _alloc(n, s, u):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(n), dev, torch.cuda.ExternalStream(s, device=dev)
+                                                              if s else torch.cuda.default_stream(dev))
+                except Exception:          # out of memory: the library reports TCI_ERR_OUT_OF_MEMORY
+                    return None
+
+            def _free(ptr, n, s, u):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._callbacks = (ALLOC_FN(_alloc), FREE_FN(_free))
+        if self._callbacks is not None:
+            opts.allocator.alloc, opts.allocator.free = self._callbacks
+        if precision is not None:
+            opts.precision = precision
+        if svd_mode is not None:
+            opts.svd_mode = svd_mode
+        if autotune_cache is not None:
+            opts.autotune_cache = autotune_cache.encode()
+        if verbosity is not None:
+            opts.verbosity = verbosity
         h = ctypes.c_void_p()
-        _check(lib().tci_create_context(ctypes.byref(h), device, ctypes.c_void_p(st.cuda_stream)),
-               "tci_create_context")
+        _check(lib().tci_create_context(ctypes.byref(h), device, ctypes.c_void_p(st.cuda_stream),
+                                        ctypes.byref(opts)), "tci_create_context")
         self.h = h
 
     def set_precision(self, prec: int):
@@ -365,12 +423,24 @@ def qr(ctx: Context, a: Tensor, k_rows: int):
     return q, r
 
 
-def eigh(ctx: Context, a: Tensor):
-    n = a.shape()[0]
-    w = Tensor.empty(ctx, F64, n)
+def _real_of(dt: int) -> int:
+    return F64 if dt in (F64, C128) else F32
+
+
+def eigh(ctx: Context, a: Tensor, k_rows: int = 1):
+    shp = a.shape()
+    n = int(np.prod(shp[:k_rows]))
+    w = Tensor.empty(ctx, _real_of(a.dtype), n)
     v = Tensor.empty(ctx, a.dtype, n * n)
-    _check(lib().tci_eigh(ctx.h, a.h, w.h, v.h), "tci_eigh")
+    _check(lib().tci_eigh(ctx.h, a.h, k_rows, w.h, v.h), "tci_eigh")
     return w, v
+
+
+def eigvalsh(ctx: Context, a: Tensor, k_rows: int = 1):
+    n = int(np.prod(a.shape()[:k_rows]))
+    w = Tensor.empty(ctx, _real_of(a.dtype), n)
+    _check(lib().tci_eigvalsh(ctx.h, a.h, k_rows, w.h), "tci_eigvalsh")
+    return w
 
 
 def close(ctx: Context, a: Tensor, b: Tensor, eps: float) -> bool:
@@ -504,6 +574,26 @@ def _attach_prev(params: UpdateParams, prev):
     return arr
 
 
+def _attach_lambdas(params: UpdateParams, lam_left, lam_right):
+    """Vidal weights (lists of F64 Tensors); the returned arrays must stay alive."""
+    if lam_left is None and lam_right is None:
+        return None
+    al = (ctypes.c_void_p * len(lam_left))(*[x.h.value for x in lam_left])
+    ar = (ctypes.c_void_p * len(lam_right))(*[x.h.value for x in lam_right])
+    params.lambda_left = ctypes.cast(al, ctypes.POINTER(ctypes.c_void_p))
+    params.lambda_right = ctypes.cast(ar, ctypes.POINTER(ctypes.c_void_p))
+    return al, ar
+
+
+def _detach(params: UpdateParams, keep_prev, keep_lam):
+    """Clear pointers that _attach_prev / _attach_lambdas set (their arrays die with the call)."""
+    if keep_prev is not None:
+        params.prev_spectra = None
+    if keep_lam is not None:
+        params.lambda_left = None
+        params.lambda_right = None
+
+
 def update_params(**kw) -> UpdateParams:
     p = UpdateParams()
     lib().tci_update_params_default(ctypes.byref(p))
@@ -513,11 +603,14 @@ def update_params(**kw) -> UpdateParams:
 
 
 def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, params: UpdateParams,
-                            prev_spectra: list | None = None):
+                            prev_spectra: list | None = None, lambda_left: list | None = None,
+                            lambda_right: list | None = None):
     """Returns (A_out, s_out, B_out, infos) lists; outputs are library-sized views.
-    prev_spectra (learned sketch): per update the bond's spectrum before the update."""
+    prev_spectra (learned sketch): per update the bond's spectrum before the update.
+    lambda_left / lambda_right (DIR_VIDAL): per update the outer bond weights."""
     n = len(A)
     keep = _attach_prev(params, prev_spectra)
+    keep_l = _attach_lambdas(params, lambda_left, lambda_right)
     P = ctypes.c_void_p * n
     chil, d, chim = A[0].shape()
     chir = B[0].shape()[2]
@@ -528,17 +621,38 @@ def two_site_update_batched(ctx: Context, A: list, B: list, gates: list | None, 
     s_out = [Tensor.empty(ctx, F64, kap) for _ in range(n)]
     infos = (UpdateInfo * n)()
     g = P(*[x.h.value if x is not None else None for x in gates]) if gates is not None else None
-    _check(lib().tci_two_site_update_batched(ctx.h, n, P(*[x.h.value for x in A]), P(*[x.h.value for x in B]),
-                                             g, ctypes.byref(params), P(*[x.h.value for x in A_out]),
-                                             P(*[x.h.value for x in s_out]), P(*[x.h.value for x in B_out]),
-                                             infos), "tci_two_site_update_batched")
+    try:
+        _check(lib().tci_two_site_update_batched(ctx.h, n, P(*[x.h.value for x in A]), P(*[x.h.value for x in B]),
+                                                 g, ctypes.byref(params), P(*[x.h.value for x in A_out]),
+                                                 P(*[x.h.value for x in s_out]), P(*[x.h.value for x in B_out]),
+                                                 infos), "tci_two_site_update_batched")
+    finally:
+        _detach(params, keep, keep_l)
     return A_out, s_out, B_out, list(infos)
 
 
-def split_batched(ctx: Context, thetas: list, params: UpdateParams, prev_spectra: list | None = None):
+def two_site_update(ctx: Context, A: Tensor, B: Tensor, gate: Tensor | None, params: UpdateParams | None = None):
+    """tci_two_site_update: one update; returns (A_out, s_out, B_out, info)."""
+    chil, d, _ = A.shape()
+    chir = B.shape()[2]
+    kap = min(chil * d, d * chir, params.chi_max if params is not None else chil * d)
+    dt = A.dtype
+    A_out = Tensor.empty(ctx, dt, chil * d * kap)
+    B_out = Tensor.empty(ctx, dt, kap * d * chir)
+    s_out = Tensor.empty(ctx, F64, kap)
+    info = UpdateInfo()
+    _check(lib().tci_two_site_update(ctx.h, A.h, B.h, gate.h if gate is not None else None,
+                                     ctypes.byref(params) if params is not None else None, A_out.h, s_out.h,
+                                     B_out.h, ctypes.byref(info)), "tci_two_site_update")
+    return A_out, s_out, B_out, info
+
+
+def split_batched(ctx: Context, thetas: list, params: UpdateParams, prev_spectra: list | None = None,
+                  lambda_left: list | None = None, lambda_right: list | None = None):
     """trunc_svd + renormalisation + write-back of given (chi_l, d, d, chi_r) tensors."""
     n = len(thetas)
     keep = _attach_prev(params, prev_spectra)
+    keep_l = _attach_lambdas(params, lambda_left, lambda_right)
     P = ctypes.c_void_p * n
     chil, d, _, chir = thetas[0].shape()
     kap = min(chil * d, d * chir, params.chi_max)
@@ -547,9 +661,12 @@ def split_batched(ctx: Context, thetas: list, params: UpdateParams, prev_spectra
     B_out = [Tensor.empty(ctx, dt, kap * d * chir) for _ in range(n)]
     s_out = [Tensor.empty(ctx, F64, kap) for _ in range(n)]
     infos = (UpdateInfo * n)()
-    _check(lib().tci_split_batched(ctx.h, n, P(*[x.h.value for x in thetas]), ctypes.byref(params),
-                                   P(*[x.h.value for x in A_out]), P(*[x.h.value for x in s_out]),
-                                   P(*[x.h.value for x in B_out]), infos), "tci_split_batched")
+    try:
+        _check(lib().tci_split_batched(ctx.h, n, P(*[x.h.value for x in thetas]), ctypes.byref(params),
+                                       P(*[x.h.value for x in A_out]), P(*[x.h.value for x in s_out]),
+                                       P(*[x.h.value for x in B_out]), infos), "tci_split_batched")
+    finally:
+        _detach(params, keep, keep_l)
     return A_out, s_out, B_out, list(infos)
 
 

@@ -20,7 +20,8 @@ def declared_functions():
 def test_header_declares_the_hot_path():
     names = declared_functions()
     for must in ["tci_contract", "tci_trunc_svd", "tci_qr", "tci_transpose", "tci_reshape", "tci_norm",
-                 "tci_two_site_update_batched", "tci_heff_matvec", "tci_lanczos_ground", "tci_create_context"]:
+                 "tci_two_site_update_batched", "tci_heff_matvec", "tci_lanczos_ground", "tci_create_context",
+                 "tci_two_site_update", "tci_eigh", "tci_eigvalsh", "tci_context_opts_default"]:
         assert must in names
 
 
@@ -49,9 +50,65 @@ def test_update_params_defaults():
 
 def test_null_arguments_are_rejected_on_the_host():
     L = tci.lib()
-    assert L.tci_create_context(None, 0, None) == 1      # out NULL -> invalid argument
+    assert L.tci_create_context(None, 0, None, None) == 1      # out NULL -> invalid argument
     assert L.tci_order(None, None, None) == 1
     assert b"null" in L.tci_last_error()
+
+
+def test_context_options_are_checked_on_the_host():
+    """tci_context_opts: defaults, and invalid combinations rejected before
+    any device is touched (so this runs without a GPU)."""
+    L = tci.lib()
+    o = tci.ContextOpts()
+    L.tci_context_opts_default(ctypes.byref(o))
+    assert o.precision == -1 and o.svd_mode == tci.SVD_PLAIN and o.verbosity == -1 and not o.autotune_cache
+    h = ctypes.c_void_p()
+    half = tci.ContextOpts()
+    L.tci_context_opts_default(ctypes.byref(half))
+    keep = tci.ALLOC_FN(lambda n, s, u: None)
+    half.allocator.alloc = keep                    # alloc without free
+    assert L.tci_create_context(ctypes.byref(h), 0, None, ctypes.byref(half)) == 1
+    assert b"allocator" in L.tci_last_error()
+    for field, bad in (("precision", 7), ("svd_mode", tci.SVD_LEARNED), ("verbosity", 3)):
+        o2 = tci.ContextOpts()
+        L.tci_context_opts_default(ctypes.byref(o2))
+        setattr(o2, field, bad)
+        assert L.tci_create_context(ctypes.byref(h), 0, None, ctypes.byref(o2)) == 1, field
+
+
+def test_update_params_vidal_fields():
+    p = tci.update_params(direction=tci.DIR_VIDAL)
+    assert p.direction == 2 and not p.lambda_left and not p.lambda_right
+
+
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = {"tci_update_params": tci.UpdateParams, "tci_update_info": tci.UpdateInfo,
+               "tci_context_opts": tci.ContextOpts, "tci_allocator": tci.Allocator}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", "#include <tci_c.h>", "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    r = subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for ln in filter(None, out):
+        cname, what, val = ln.split()
+        py = structs[cname]
+        got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), (cname, what, got, val)
 
 
 CPP_TYPES_AND_TEMPLATES = r'''
@@ -69,6 +126,9 @@ void instantiate(tci::Context& ctx, Z& a, tci::Tensor<double>& s) {
   tci::trunc_svd(ctx, a, 2, u, s, v, err, 1, 8, 1e-8, 0.0);
   tci::qr(ctx, a, 1, u, v);
   tci::lq(ctx, a, 1, u, v);
+  tci::Tensor<double> w;
+  tci::eigh(ctx, a, 1, w, u);
+  tci::eigvalsh(ctx, a, 1, w);
   tci::contract(ctx, a, {0, 1, 2}, a, {0, 1, 3}, o, {2, 3});
   tci::contract(ctx, a, "ijk", a, "ijl", o, "kl");
   tci::expand(ctx, a, {{0, 1}});

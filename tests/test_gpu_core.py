@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import bf16
 from oracle import mps as omps
 from paper_2512_23917_amd import synth
 
@@ -62,9 +63,12 @@ def test_contract_fp64_matches_oracle(T, ctx, dtype, case):
     assert rel_fro(c, ref) < 1e-13
 
 
-@pytest.mark.parametrize("prec,tol", [("PREC_FP32", 2e-6), ("PREC_BF16X3", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("PREC_FP32", 2e-6), ("PREC_BF16X3", 1e-5)])
 @pytest.mark.parametrize("dtype", ["C64", "F32"])
 def test_contract_mixed_matches_oracle(T, ctx, dtype, prec, tol):
+    """Mixed contractions against the FP64 oracle on the same FP32 operands:
+    <= 1e-5 relative Frobenius, and for split-BF16x3 within twice the error of
+    the split's emulation (exact partial products, FP64 sums)."""
     g = np.random.default_rng(12)
     dt = getattr(T, dtype)
     if dtype == "C64":
@@ -79,7 +83,12 @@ def test_contract_mixed_matches_oracle(T, ctx, dtype, prec, tol):
         c = T.contract(ctx, up(T, ctx, a32, dt), "ik", up(T, ctx, b32, dt), "kj", "ij").numpy()
     finally:
         ctx.set_precision(T.PREC_FP32)
-    assert rel_fro(c, ref) < tol
+    err = rel_fro(c, ref)
+    assert err < tol
+    if prec == "PREC_BF16X3":
+        err_emu = rel_fro(bf16.gemm_x3(a32, b32), ref)
+        print(f"contract {dtype} bf16x3: GPU {err:.3e} emulation {err_emu:.3e}")
+        assert err <= 2 * err_emu, (err, err_emu)
 
 
 def test_contract_alias_and_label_errors(T, ctx):

@@ -11,7 +11,7 @@ from oracle import mps as omps
 from oracle import rsvd as orsvd
 from paper_2512_23917_amd import synth
 
-from gpu_util import rel_fro
+from gpu_util import chi_allowed, rel_fro
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -104,7 +104,8 @@ def test_randomized_mixed_bf16x3_update(T, ctx):
     Ao, so, Bo, inf = T.two_site_update_batched(ctx, [up(T, ctx, c64(a), T.C64)], [up(T, ctx, c64(b), T.C64)],
                                                 [up(T, ctx, c64(gate), T.C64)], p)
     chi_ref = ref["chi"]
-    assert abs(inf[0].chi - chi_ref) <= 2
+    total = float(np.sum(np.abs(ref["theta"]) ** 2))
+    assert chi_allowed(inf[0].chi, chi_ref, ref["s_raw"], total, ref["trunc_err"], 1e-8, 200)
     c = min(inf[0].chi, chi_ref)
     s = so[0].numpy()
     assert np.abs(s[:c] - ref["s"][:c]).max() <= 1e-6 * ref["s"][0]
@@ -159,8 +160,8 @@ def test_features_match_oracle(T, ctx):
 
 def test_learned_update_uses_model_rank(T, ctx):
     """With a model whose output is a constant y, the update uses the sketch
-    rank of the rule k = 32 ceil((2^y 1.1 + 16) / 32) and accepts when the
-    sketch covers chi* (with the rule's oversampling)."""
+    rank of the rule k = 32 ceil((1.5 2^y + 32) / 32) (plain when k > 0.6 n)
+    and accepts when the sketch covers chi* (with the rule's oversampling)."""
     a, b, s_true = _spectrum_theta(256, 3.0, 21)
     theta = np.einsum("asm,mtb->astb", a, b)
     want_chi, _ = oracle.trunc_rule(s_true, 1, 256, 1e-8, 0.0)
