@@ -22,7 +22,7 @@ Algorithm-level oracles live in the sibling modules: ``mps`` (two-site
 update, open-chain sweep), ``dmrg`` (effective Hamiltonian, Lanczos),
 ``rsvd`` (randomized truncated SVD), ``mlp`` (sketch-rank network), ``bf16``
 (split-BF16x3 emulation), ``u1`` (U(1) block-sparse update), ``itebd``,
-``subtensor`` and ``bp``.
+``subtensor``, ``eig`` (general eigendecomposition) and ``bp``.
 """
 from __future__ import annotations
 
