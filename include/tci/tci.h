@@ -219,6 +219,20 @@ OutT fresh(Context& ctx, F&& f) {
 }
 }  // namespace detail
 
+// General right eigendecomposition of the matricised tensor: w ascending by
+// (real, imaginary) part, v {d_0..d_{k-1}, n} with unit-norm columns.
+template <typename TenT>
+void eig(context_handle_t<TenT>& ctx, const TenT& a, const order_t<TenT> num_of_bds_as_row, cplx_ten_t<TenT>& w,
+         cplx_ten_t<TenT>& v) {
+  detail::check(tci_eig(ctx.get(), a.handle(), num_of_bds_as_row, w.out_handle(ctx.get()), v.out_handle(ctx.get())),
+                "tci_eig");
+}
+// Eigenvalues only.
+template <typename TenT>
+void eigvals(context_handle_t<TenT>& ctx, const TenT& a, const order_t<TenT> num_of_bds_as_row, cplx_ten_t<TenT>& w) {
+  detail::check(tci_eigvals(ctx.get(), a.handle(), num_of_bds_as_row, w.out_handle(ctx.get())), "tci_eigvals");
+}
+
 // ---------------------------------------------------------------- miscellaneous (Spec)
 inline std::string version() { return tci_version(); }
 

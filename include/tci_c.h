@@ -429,6 +429,27 @@ tci_status tci_eigh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci
 /* Spec, eigvalsh: the eigenvalues of tci_eigh only (no vectors are formed). */
 tci_status tci_eigvalsh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w);
 
+/* Spec, eig: right eigendecomposition A'V = V diag(w) of the matricised
+ * tensor (first k_rows bonds as rows; I == J required, I <= 1024).
+ * - w: first-order complex tensor of I eigenvalues, sorted by ascending real
+ *   part, then ascending imaginary part, compared as returned (after
+ *   rounding to C64 for single-precision input); the paper fixes no order.
+ * - v: shape {d_0, ..., d_{k-1}, I}; column k (the last bond) is the right
+ *   eigenvector of w[k], scaled to unit 2-norm with its largest-modulus
+ *   entry (the first on exact ties) real and positive.
+ * - w and v are C128 for F64 / C128 input and C64 for F32 / C64 input; the
+ *   arithmetic is complex128 throughout: Householder reduction to Hessenberg
+ *   form, single-shift QR iteration (Wilkinson shifts) to the complex Schur
+ *   form, back substitution for the eigenvectors of the triangular factor.
+ *   The Hessenberg and QR steps run in one workgroup per matrix.
+ * - Synchronous.  Errors: TCI_ERR_INVALID_ARGUMENT (k_rows), TCI_ERR_SHAPE
+ *   (I != J), TCI_ERR_UNSUPPORTED (I > 1024), TCI_ERR_NOT_CONVERGED (more
+ *   than 60 QR sweeps for one eigenvalue), TCI_ERR_NUMERIC (non-finite input). */
+tci_status tci_eig(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v);
+
+/* Spec, eigvals: the eigenvalues of tci_eig only (no vectors are formed). */
+tci_status tci_eigvals(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w);
+
 /* Spec, close: *result = 1 iff max |a - b| <= eps elementwise (same shape
  * and dtype), else 0.  Synchronous. */
 tci_status tci_close(tci_context ctx, tci_tensor a, tci_tensor b, double eps, int* result);
@@ -606,8 +627,9 @@ tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_t
  *    q_t = clamp(log10(s_j/s_0)/16, -1, 0), j = floor((t+1/2)/32 (len-1))]
  * of the bond's previous spectrum s.  The update uses the sketch rank
  * k = 32 ceil((1.5 * 2^y + 32)/32) and the plain truncated SVD when
- * y > log2(chi_max) or k > 0.6 min(m, n) (the sketch would then cost about
- * as much as the plain SVD).  Parameters are FP32, flat: W1 (128x35), b1, W2
+ * y > log2(chi_max) or k > min(m, n) / 4 (the range finder's FP64
+ * orthonormalisations cost O(n k^2): at k = n / 3 a sketch of a 2048 x 2048
+ * complex bond costs about as much as the plain SVD).  Parameters are FP32, flat: W1 (128x35), b1, W2
  * (128x128), b2, W3 (1x128), b3.  All data pointers below are device
  * pointers unless marked host. */
 

@@ -15,7 +15,7 @@ Target: log2 chi*(eps) of the bond after the update.
 Loss: pinball (quantile) loss with tau = 0.9, averaged over the batch:
     rho(u) = max(tau u, (tau - 1) u),  u = target - prediction.
 Sketch rank from a prediction y: k = 32 * ceil((1.5 * 2^y + 32) / 32); the
-plain truncated SVD is used instead when y > log2(chi_max) or k > 0.6 n.  (The
+plain truncated SVD is used instead when y > log2(chi_max) or k > n / 4.  (The
 oversampling follows the randomized-SVD error bound of Halko, Martinsson and
 Tropp: with q power iterations the residual of the kept triplet j scales like
 (s_{k+1}/s_j)^(2q+1), so a slowly decaying spectrum needs k well above chi*.)
@@ -57,7 +57,7 @@ def sketch_rank(y: float, n: int, chi_max: int):
     if y > math.log2(chi_max):
         return None
     k = 32 * math.ceil((2.0 ** y * 1.5 + 32.0) / 32.0)
-    if k > 0.6 * n:
+    if 4 * k > n:
         return None
     return k
 

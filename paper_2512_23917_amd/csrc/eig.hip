@@ -776,7 +776,13 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
 // iterated together with their own factors, and after every solve they are
 // orthonormalised in order against the earlier members (modified
 // Gram-Schmidt), as in LAPACK's stein.
-constexpr double INVIT_CLUSTER_TOL = 1e-11;
+// The threshold sits at about 90 u ||T||: for a larger gap g the vectors of
+// independent solves overlap by at most about u ||T|| / g < 1/90, which the
+// Cholesky-QR2 that follows on all vectors removes.  (Graded spectra, as the
+// Gram matrices of power-law bonds, have consecutive gaps between 1e-14 and
+// 1e-11 of the norm over hundreds of eigenvalues; treating those as one
+// cluster made its serial orthonormalisation dominate the whole update.)
+constexpr double INVIT_CLUSTER_TOL = 1e-14;
 
 __device__ inline double wave_sum_d(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -17,9 +17,11 @@
 #include <vector>
 
 #include "../../include/tci_c.h"
+#include "bf16x3.hpp"
 #include "common.hpp"
 #include "eig.hpp"
 #include "gaussjordan.hpp"
+#include "geig.hpp"
 #include "gemm.hpp"
 #include "jacobi.hpp"
 #include "linalg.hpp"
@@ -51,7 +53,10 @@ static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long
   // (at most two full passes, as in CholeskyQR2).
   hipStream_t s = ctx->stream;
   const size_t es = elem_bytes(wdt);
-  const size_t bytes = es * (size_t)sX * nb;
+  // elements of one problem: the stride, or for a single problem given with
+  // stride 0 the extent of its matrix (m rows, or k rows in row mode, of ldx)
+  const size_t per = sX > 0 ? (size_t)sX : (size_t)(mode == 0 ? m : k) * (size_t)ldx;
+  const size_t bytes = es * per * nb;
   CholWork w{};
   w.G = ctx->arena.get(es * cholqr_work_elems(k) * nb);
   w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
@@ -422,6 +427,101 @@ static tci_status check_direction(tci_context ctx, const tci_update_params& p, i
   return TCI_OK;
 }
 
+// Plain truncated SVD of nb matrices theta (FP64 working type) and the
+// write-back to the output slots gslot[i].  Gram matrices, reductions,
+// eigenvalues and the truncation rule run for the whole batch; the vector
+// stage then runs per group of similar kept chi (ascending chi, the largest
+// at most 5/4 of the smallest), each group on gathered copies of its
+// problems' reduction data, so that no problem's eigenvectors, back-
+// transformation and factor products are padded to the batch's largest chi.
+static tci_status tsvd_store_grouped(tci_context ctx, int dt, int wdt, int nb, int chil, int d, int chir,
+                                     const void* theta, const TruncParams& tp, const std::vector<int>& gslot,
+                                     const tci_update_params& p, tci_tensor* A_out, tci_tensor* s_out,
+                                     tci_tensor* B_out, tci_update_info* infos, bool fallback,
+                                     const std::vector<int>* krank) {
+  hipStream_t s = ctx->stream;
+  const int m = chil * d, n = d * chir, ng = std::min(m, n);
+  const int kmax = std::max(1, std::min(tp.chi_max, ng));
+  TsvdStage st;
+  TCI_TRY(tsvd_eigvals(ctx, wdt, nb, m, n, theta, kmax, st));
+  ARENA(chi, int, nb);
+  ARENA(err, double, nb);
+  ARENA(disc, double, nb);
+  ARENA(sv, double, (size_t)kmax * nb);
+  ARENA(sinv, double, (size_t)kmax * nb);
+  ARENA(sn, double, (size_t)kmax * nb);
+  TCI_CHECK_HIP(trunc_select(st.lam, kmax, kmax, st.total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
+  std::vector<int> chi_h(nb);
+  std::vector<double> err_h(nb), disc_h(nb), total_h(nb);
+  TCI_CHECK_HIP(hipMemcpyAsync(chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(err_h.data(), err, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(disc_h.data(), disc, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(total_h.data(), st.total, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(total_h[b])) TCI_RET(TCI_ERR_NUMERIC, "non-finite entries in theta");
+  std::vector<int> ord(nb);
+  for (int i = 0; i < nb; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return chi_h[x] < chi_h[y] || (chi_h[x] == chi_h[y] && x < y); });
+  const size_t es = elem_bytes(wdt);
+  const long long smn = (long long)m * n, sG = (long long)ng * ng;
+  for (int g0 = 0; g0 < nb;) {
+    int g1 = g0 + 1;
+    while (g1 < nb && 4 * chi_h[ord[g1]] <= 5 * chi_h[ord[g0]]) ++g1;
+    const std::vector<int> loc(ord.begin() + g0, ord.begin() + g1);
+    g0 = g1;
+    const int ngp = (int)loc.size();
+    int kz = 1;
+    for (int i : loc) kz = std::max(kz, chi_h[i]);
+    const std::vector<size_t> mark = ctx->arena.used_state();
+    TsvdOut o;
+    o.kmax = kmax;
+    bool identity = ngp == nb;
+    for (int i = 0; identity && i < ngp; ++i) identity = loc[i] == i;
+    if (identity) {
+      TCI_TRY(tsvd_vectors(ctx, st, chi, kz, sinv, o));
+      o.chi = chi; o.s = sv; o.sn = sn; o.total = st.total;
+    } else {
+      TsvdStage sg = st;
+      sg.nb = ngp;
+      const void* ptr = nullptr;
+      TCI_TRY(gather(ctx, wdt, theta, smn, loc, &ptr));
+      sg.theta = ptr;
+      TCI_TRY(gather(ctx, F64, st.d, ng, loc, &ptr));
+      sg.d = const_cast<double*>(static_cast<const double*>(ptr));
+      TCI_TRY(gather(ctx, F64, st.e, ng, loc, &ptr));
+      sg.e = const_cast<double*>(static_cast<const double*>(ptr));
+      TCI_TRY(gather(ctx, F64, st.lam, kmax, loc, &ptr));
+      sg.lam = const_cast<double*>(static_cast<const double*>(ptr));
+      TCI_TRY(gather(ctx, wdt, st.ta.Vt, sG, loc, &ptr));
+      sg.ta.Vt = const_cast<void*>(ptr);
+      TCI_TRY(gather(ctx, wdt, st.ta.tau, st.ta.stau, loc, &ptr));
+      sg.ta.tau = const_cast<void*>(ptr);
+      TCI_TRY(gather(ctx, F32, chi, 1, loc, &ptr));     // 4-byte elements
+      int* chi_g = const_cast<int*>(static_cast<const int*>(ptr));
+      TCI_TRY(gather(ctx, F64, sinv, kmax, loc, &ptr));
+      const double* sinv_g = static_cast<const double*>(ptr);
+      TCI_TRY(gather(ctx, F64, sn, kmax, loc, &ptr));
+      double* sn_g = const_cast<double*>(static_cast<const double*>(ptr));
+      TCI_TRY(tsvd_vectors(ctx, sg, chi_g, kz, sinv_g, o));
+      o.chi = chi_g; o.sn = sn_g; o.s = nullptr;
+    }
+    std::vector<int> slots;
+    for (int i : loc) {
+      o.chi_h.push_back(chi_h[i]);
+      o.err_h.push_back(err_h[i]);
+      o.disc_h.push_back(disc_h[i]);
+      o.total_h.push_back(total_h[i]);
+      slots.push_back(gslot[i]);
+    }
+    // store_outputs synchronises the stream, so the group's workspace is free after it
+    TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, slots, p, A_out, s_out, B_out, infos, nullptr, fallback,
+                          krank));
+    ctx->arena.restore(mark);
+  }
+  return TCI_OK;
+}
+
 // trunc_svd of nb matrices theta ((chil*d) x (d*chir)): th_lo in the storage
 // dtype dt, thw its FP64 working copy (the same pointer when dt is FP64);
 // plain, randomized or learned per params; then renormalised s and the
@@ -444,17 +544,27 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
       else plain_idx.push_back(i);
     }
   }
-  if (!sk_idx.empty()) {
+  // Sketched problems run in groups of similar rank (ascending k, the
+  // largest at most 5/4 of the smallest), so that no problem's products are
+  // padded far beyond its own rank.
+  std::sort(sk_idx.begin(), sk_idx.end(), [&](int x, int y) { return kvec[x] < kvec[y] || (kvec[x] == kvec[y] && x < y); });
+  for (size_t g0 = 0; g0 < sk_idx.size();) {
+    size_t g1 = g0 + 1;
+    while (g1 < sk_idx.size() && 4 * kvec[sk_idx[g1]] <= 5 * kvec[sk_idx[g0]]) ++g1;
+    std::vector<int> grp(sk_idx.begin() + g0, sk_idx.begin() + g1);
+    g0 = g1;
     const void* lo = th_lo;
     const void* hi = thw;
-    if ((int)sk_idx.size() != nb) {
-      TCI_TRY(gather(ctx, dt, th_lo, smn, sk_idx, &lo));
+    bool identity = (int)grp.size() == nb;
+    for (size_t i = 0; identity && i < grp.size(); ++i) identity = grp[i] == (int)i;
+    if (!identity) {
+      TCI_TRY(gather(ctx, dt, th_lo, smn, grp, &lo));
       hi = lo;
-      if (thw != th_lo) TCI_TRY(gather(ctx, wdt, thw, smn, sk_idx, &hi));
+      if (thw != th_lo) TCI_TRY(gather(ctx, wdt, thw, smn, grp, &hi));
     }
     std::vector<int> ks;
     std::vector<uint32_t> streams;
-    for (int i : sk_idx) {
+    for (int i : grp) {
       ks.push_back(kvec[i]);
       streams.push_back((uint32_t)(first + i));
     }
@@ -462,18 +572,18 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
     std::vector<double> resid;
     const int q = p.power_iters < 0 ? 2 : p.power_iters;
     const int prec = is_double(dt) ? PREC_FP64 : p.precision;
-    TCI_TRY(sketch_run(ctx, dt, wdt, prec, (int)sk_idx.size(), m, n, lo, hi, tp, ks, q, p.seed, streams, o, resid));
+    TCI_TRY(sketch_run(ctx, dt, wdt, prec, (int)grp.size(), m, n, lo, hi, tp, ks, q, p.seed, streams, o, resid));
     const double cert = p.cert_tol > 0 ? p.cert_tol : 1e-7;
     std::vector<int> acc_local, acc_global;
-    for (size_t i = 0; i < sk_idx.size(); ++i) {
+    for (size_t i = 0; i < grp.size(); ++i) {
       if (o.err_h[i] <= p.target_trunc_err && resid[i] <= cert) {
         acc_local.push_back((int)i);
-        acc_global.push_back(sk_idx[i]);
+        acc_global.push_back(grp[i]);
       } else {
-        plain_idx.push_back(sk_idx[i]);
+        plain_idx.push_back(grp[i]);
       }
     }
-    if (acc_local.size() == sk_idx.size()) {
+    if (acc_local.size() == grp.size()) {
       TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, acc_global, p, A_out, s_out, B_out, infos, &resid, false,
                             &kvec));
     } else if (!acc_local.empty()) {
@@ -501,11 +611,15 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
     std::sort(plain_idx.begin(), plain_idx.end());
     const void* hi = thw;
     if ((int)plain_idx.size() != nb) TCI_TRY(gather(ctx, wdt, thw, smn, plain_idx, &hi));
-    TsvdOut o;
-    if (ng <= JACOBI_MAX_K) TCI_TRY(tsvd_small(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
-    else TCI_TRY(tsvd_run(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
-    TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, plain_idx, p, A_out, s_out, B_out, infos, nullptr,
-                          p.svd_mode != TCI_SVD_PLAIN, &kvec));
+    if (ng <= JACOBI_MAX_K) {
+      TsvdOut o;
+      TCI_TRY(tsvd_small(ctx, wdt, (int)plain_idx.size(), m, n, hi, tp, o));
+      TCI_TRY(store_outputs(ctx, dt, wdt, chil, d, chir, o, plain_idx, p, A_out, s_out, B_out, infos, nullptr,
+                            p.svd_mode != TCI_SVD_PLAIN, &kvec));
+    } else {
+      TCI_TRY(tsvd_store_grouped(ctx, dt, wdt, (int)plain_idx.size(), chil, d, chir, hi, tp, plain_idx, p, A_out,
+                                 s_out, B_out, infos, p.svd_mode != TCI_SVD_PLAIN, &kvec));
+    }
   }
   return TCI_OK;
 }
@@ -835,7 +949,7 @@ static tci_status eigh_core(tci_context ctx, tci_tensor a, int k_rows, tci_tenso
     ARENA(iw, double, (size_t)4 * n * n);
     TCI_CHECK_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)n * n, s));
     TCI_CHECK_HIP(tridiag_invit(d, e, n, n, lam, n, nullptr, n, Z, n, 0, iw, 1, s));
-    TCI_TRY(cholqr2(ctx, F64, 0, Z, n, 0, n, n, Z2, 1));
+    TCI_TRY(cholqr2(ctx, F64, 0, Z, n, (long long)n * n, n, n, Z2, 1));
     Ev = Z;
     if (is_complex(dt)) {
       Ev = ctx->arena.get(es * (size_t)n * n);
@@ -880,6 +994,98 @@ tci_status tci_eigh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci
 
 tci_status tci_eigvalsh(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w) try {
   return eigh_core(ctx, a, k_rows, w, nullptr);
+} TCI_API_CATCH
+
+// Spec eig / eigvals: general eigendecomposition of the matricised tensor in
+// complex128 (geig.hip); v == nullptr skips the vectors.  Eigenvalues in
+// ascending order of the real part, then of the imaginary part.
+static tci_status eig_core(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v) {
+  if (!ctx || !a || !w) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  if (a->empty) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "moved-from tensor");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int64_t rows, cols;
+  TCI_TRY(matricize(a, k_rows, rows, cols));
+  if (rows != cols) TCI_RET(TCI_ERR_SHAPE, "eig needs a square matricisation (I == J)");
+  if (rows > GEIG_MAX_N)
+    TCI_RET(TCI_ERR_UNSUPPORTED, "eig / eigvals: matrix order above " + std::to_string(GEIG_MAX_N));
+  Trace tr(ctx, v ? "eig" : "eigvals", std::to_string(rows));
+  ctx->arena.reset();
+  const int n = (int)rows, odt = a->dtype;
+  const int cdt = is_double(odt) ? C128 : C64;   // complex type of the input's precision
+  if (n == 0) {
+    int64_t z[MAX_ORDER + 1] = {0};
+    TCI_TRY(ensure_shape(ctx, w, cdt, 1, z));
+    if (v) {
+      for (int i = 0; i < k_rows; ++i) z[i] = a->shape[i];
+      z[k_rows] = 0;
+      TCI_TRY(ensure_shape(ctx, v, cdt, k_rows + 1, z));
+    }
+    return TCI_OK;
+  }
+  hipStream_t s = ctx->stream;
+  const size_t nn = (size_t)n * n;
+  ARENA(H, cd, nn);
+  ARENA(Q, cd, nn);
+  ARENA(st, int, 1);
+  ARENA(fro, double, 1);
+  ARENA(wd, cd, n);
+  TCI_CHECK_HIP(convert(odt, a->data, C128, H, (long long)nn, s));
+  TCI_CHECK_HIP(geig_schur(H, Q, n, st, fro, s));
+  TCI_CHECK_HIP(geig_diag(H, n, wd, s));
+  int sth = 0;
+  std::vector<cd> wh(n);
+  TCI_CHECK_HIP(hipMemcpyAsync(&sth, st, sizeof(int), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(wh.data(), wd, sizeof(cd) * n, hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  if (sth) TCI_RET(TCI_ERR_NOT_CONVERGED, "eig: the QR iteration did not converge");
+  for (const cd& x : wh)
+    if (!std::isfinite(x.x) || !std::isfinite(x.y)) TCI_RET(TCI_ERR_NUMERIC, "non-finite eigenvalues (non-finite input?)");
+  // order of the returned values: keys rounded to the output precision, so
+  // that the order holds exactly for what the caller reads
+  std::vector<double> kr(n), ki(n);
+  for (int i = 0; i < n; ++i) {
+    kr[i] = cdt == C64 ? (double)(float)wh[i].x : wh[i].x;
+    ki[i] = cdt == C64 ? (double)(float)wh[i].y : wh[i].y;
+  }
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+    return kr[x] < kr[y] || (kr[x] == kr[y] && ki[x] < ki[y]);
+  });
+  std::vector<cd> wo(n);
+  for (int i = 0; i < n; ++i) wo[i] = wh[perm[i]];
+  ARENA(w2, cd, n);
+  TCI_CHECK_HIP(hipMemcpyAsync(w2, wo.data(), sizeof(cd) * n, hipMemcpyHostToDevice, s));
+  int64_t wshape[1] = {n};
+  TCI_TRY(ensure_shape(ctx, w, cdt, 1, wshape));
+  TCI_TRY(store_as(ctx, C128, w2, w));
+  if (v) {
+    ARENA(X, cd, nn);
+    ARENA(V, cd, nn);
+    ARENA(Vo, cd, nn);
+    ARENA(pd, int, n);
+    TCI_CHECK_HIP(geig_triangular_vectors(H, X, n, fro, s));
+    GemmArgs g = gemm_args(n, n, n, OP_N, OP_N, Q, n, X, n, V, n);
+    TCI_CHECK_HIP(gemm(C128, PREC_FP64, g, s));
+    TCI_CHECK_HIP(hipMemcpyAsync(pd, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    TCI_CHECK_HIP(geig_finish(V, pd, n, Vo, s));
+    int64_t vshape[MAX_ORDER + 1];
+    for (int i = 0; i < k_rows; ++i) vshape[i] = a->shape[i];
+    vshape[k_rows] = n;
+    TCI_TRY(ensure_shape(ctx, v, cdt, k_rows + 1, vshape));
+    TCI_TRY(store_as(ctx, C128, Vo, v));
+  }
+  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  return TCI_OK;
+}
+
+tci_status tci_eig(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w, tci_tensor v) try {
+  if (!v) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  return eig_core(ctx, a, k_rows, w, v);
+} TCI_API_CATCH
+
+tci_status tci_eigvals(tci_context ctx, tci_tensor a, int k_rows, tci_tensor w) try {
+  return eig_core(ctx, a, k_rows, w, nullptr);
 } TCI_API_CATCH
 
 // ----------------------------------------------------------------- two-site update
@@ -940,9 +1146,28 @@ tci_status tci_two_site_update_batched(tci_context ctx, int nupd, const tci_tens
     // theta = A . B  (contraction over the shared bond)
     const long long smn = (long long)m * n;
     ARENA(th, char, es * (size_t)smn * nb);
-    {
+    if (prec == PREC_BF16X3) {
+      // split-BF16x3: A and B split once into bf16 hi/lo planes, the batched
+      // product runs on the planes
+      const size_t pa = planes_bytes(dt, m, K), pb = planes_bytes(dt, n, K);
+      ARENA(Ap, char, pa * nb);
+      ARENA(Bp, char, pb * nb);
+      TCI_CHECK_HIP(split_a(dt, OP_N, Ab, K, (long long)szA, m, K, Ap, nb, s));
+      TCI_CHECK_HIP(split_b(dt, OP_N, Bb, n, (long long)szB, K, n, Bp, nb, s));
+      PlaneGemmArgs pg{};
+      pg.m = m; pg.n = n; pg.k = K;
+      pg.Mp = pad_rows(m); pg.Np = pad_rows(n); pg.Kp = pad_k(K);
+      pg.Ap = reinterpret_cast<const __bf16*>(Ap); pg.sAp = (long long)(pa / sizeof(__bf16));
+      pg.Bp = reinterpret_cast<const __bf16*>(Bp); pg.sBp = (long long)(pb / sizeof(__bf16));
+      pg.C = th; pg.ldc = n; pg.sC = smn;
+      pg.alpha_re = 1.0;
+      pg.batch = nb;
+      ProfTag tag("theta");
+      TCI_CHECK_HIP(gemm_planes(dt, pg, s));
+    } else {
       GemmArgs g = gemm_args(m, n, K, OP_N, OP_N, Ab, K, Bb, n, th, n);
       g.sA = (long long)szA; g.sB = (long long)szB; g.sC = smn; g.batch = nb;
+      ProfTag tag("theta");
       TCI_CHECK_HIP(gemm(dt, prec, g, s));
     }
     // gate

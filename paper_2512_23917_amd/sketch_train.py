@@ -7,7 +7,7 @@ where chi* is the bond dimension that the truncation rule keeps when it is
 not capped.  The network predicts the 0.9-quantile of that target (pinball
 loss), and the library turns a prediction y into the sketch rank
 k = 32 ceil((1.5 2^y + 32) / 32), or into the plain truncated SVD when
-y > log2 chi_max or k > 0.6 n.
+y > log2 chi_max or k > n / 4.
 
 Spectra of three families, each with a drifting parameter along a sweep of
 ``length`` bonds (n singular values, normalised to unit 2-norm):
@@ -27,13 +27,15 @@ spectrum (A = U diag(s), B = V^dagger with Haar isometries U, V drawn from a
 pool, s a power law with alpha ~ U[1, 3] or an exponential decay), followed by
 a Haar-random two-site gate; the input is the features of s (the bond's
 spectrum before the update) and the target is log2 of the bond dimension the
-truncation rule keeps for eps with no cap (chi_max = 2048, so the kept chi
-is chi* itself).  The gate spreads the spectrum, so chi* after the update is
-two to four times the chi* of s; this is the workload of the two-site update
-benchmark.
+truncation rule keeps for eps at the cap chi_max = chi: below the cap that
+is chi* itself; where the cap binds (eps missed at chi) the target is
+log2(d chi), a value beyond the cap, so that the network learns to send
+such bonds to the plain SVD (its rank would exceed n / 4 either way).  The
+gate spreads the spectrum, so chi* after the update is two to four times the
+chi* of s; this is the workload of the two-site update benchmark.
 
-The shipped weights are trained on 50k pairs: 12k from the library's updates
-and the rest from the closed-form sweeps above.
+The shipped weights are trained on 50k pairs: 8192 from the library's
+updates and the rest from the closed-form sweeps above.
 
 Training: Adam (lr 1e-3), batch 256, 30 epochs, 90/10 train/validation
 split, all on the GPU through ``tci_sketch_train_step`` (hand-written
@@ -146,9 +148,10 @@ def make_update_pairs(ctx, n_samples: int, seed: int, chi: int = 1024, d: int = 
     """(input spectra, targets log2 chi*) from the library's own two-site
     updates: A = U diag(s) (chi, d, chi), B = V^dagger (chi, d, chi), a Haar
     gate, complex64 storage with split-BF16x3 products and the plain FP64
-    truncated SVD at eps with chi_max = chi d (uncapped), so info.chi = chi*.
-    U, V come from a pool of `pool` Haar isometries each (generated on the
-    host), combined at random per update."""
+    truncated SVD at eps with chi_max = chi: info.chi = chi* below the cap,
+    and the target is log2(chi d) where the cap binds.  U, V come from a
+    pool of `pool` Haar isometries each (generated on the host), combined at
+    random per update."""
     import torch
     from . import synth
     rng = np.random.default_rng(seed)
@@ -156,7 +159,7 @@ def make_update_pairs(ctx, n_samples: int, seed: int, chi: int = 1024, d: int = 
     us = [torch.from_numpy(synth.haar(rng, chi * d, chi)).to(dev, torch.complex64) for _ in range(pool)]
     vhs = [torch.from_numpy(synth.haar(rng, d * chi, chi).conj().T.copy()).to(dev, torch.complex64)
            for _ in range(pool)]
-    p = tci.update_params(chi_min=1, chi_max=chi * d, target_trunc_err=eps, direction=tci.DIR_RIGHT,
+    p = tci.update_params(chi_min=1, chi_max=chi, target_trunc_err=eps, direction=tci.DIR_RIGHT,
                           precision=tci.PREC_BF16X3)
     prev, targ = [], []
     while len(targ) < n_samples:
@@ -173,7 +176,8 @@ def make_update_pairs(ctx, n_samples: int, seed: int, chi: int = 1024, d: int = 
         _, _, _, infos = tci.two_site_update_batched(ctx, A, B, G, p)
         for s, inf in zip(sp, infos):
             prev.append(s)
-            targ.append(math.log2(inf.chi))
+            capped = inf.chi >= chi and inf.trunc_err > eps
+            targ.append(math.log2(chi * d) if capped else math.log2(inf.chi))
         if log is not None:
             log(f"  update pairs {len(targ)}/{n_samples}")
     return prev, np.asarray(targ)
@@ -241,7 +245,7 @@ def make_mixed_dataset(ctx, n_samples: int, n_updates: int, seed: int, chi_max: 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Train the sketch-rank predictor on the GPU")
     ap.add_argument("--samples", type=int, default=50000)
-    ap.add_argument("--update-samples", type=int, default=12000,
+    ap.add_argument("--update-samples", type=int, default=8192,
                     help="pairs generated by the library's own two-site updates (the rest: closed-form sweeps)")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--seed", type=int, default=0)

@@ -124,6 +124,8 @@ def lib():
         "tci_qr": (i32, [p, p, ctypes.c_int, p, p]),
         "tci_eigh": (i32, [p, p, ctypes.c_int, p, p]),
         "tci_eigvalsh": (i32, [p, p, ctypes.c_int, p]),
+        "tci_eig": (i32, [p, p, ctypes.c_int, p, p]),
+        "tci_eigvals": (i32, [p, p, ctypes.c_int, p]),
         "tci_close": (i32, [p, p, p, f64, P(ctypes.c_int)]),
         "tci_fill": (i32, [p, ctypes.c_int, ctypes.c_int, P(i64), p, P(p)]),
         "tci_eye": (i32, [p, ctypes.c_int, i64, P(p)]),
@@ -440,6 +442,26 @@ def eigvalsh(ctx: Context, a: Tensor, k_rows: int = 1):
     n = int(np.prod(a.shape()[:k_rows]))
     w = Tensor.empty(ctx, _real_of(a.dtype), n)
     _check(lib().tci_eigvalsh(ctx.h, a.h, k_rows, w.h), "tci_eigvalsh")
+    return w
+
+
+def _cplx_of(dt: int) -> int:
+    return C128 if dt in (F64, C128) else C64
+
+
+def eig(ctx: Context, a: Tensor, k_rows: int = 1):
+    """tci_eig: (w, v), eigenvalues ascending by (real, imaginary) part."""
+    n = int(np.prod(a.shape()[:k_rows]))
+    w = Tensor.empty(ctx, _cplx_of(a.dtype), n)
+    v = Tensor.empty(ctx, _cplx_of(a.dtype), n * n)
+    _check(lib().tci_eig(ctx.h, a.h, k_rows, w.h, v.h), "tci_eig")
+    return w, v
+
+
+def eigvals(ctx: Context, a: Tensor, k_rows: int = 1):
+    n = int(np.prod(a.shape()[:k_rows]))
+    w = Tensor.empty(ctx, _cplx_of(a.dtype), n)
+    _check(lib().tci_eigvals(ctx.h, a.h, k_rows, w.h), "tci_eigvals")
     return w
 
 

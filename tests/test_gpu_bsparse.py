@@ -121,6 +121,17 @@ def test_full_profile_batch_sampled(T, ctx):
         assert inf[i].chi <= 1024 and np.isfinite(inf[i].trunc_err)
 
 
+@pytest.mark.slow
+def test_chi2048_single_update_reference(T, ctx):
+    """The chi = 2048 profile template as one update (21 outer sectors
+    1,1,1,2,9,30,75,151,246,328,360,..., 22 middle sectors), eps = 1e-8,
+    cap 2048, against the block oracle."""
+    up = make_update(2048, 2048, 2048, 2048)
+    assert [d for _, d in up[0]] == [1, 1, 1, 2, 9, 30, 75, 151, 246, 328, 360, 328, 246, 151, 75, 30, 9, 2, 1, 1, 1]
+    Ao, so, Bo, inf = run_gpu(T, ctx, [up], 1e-8, 2048, 0)
+    check_against_oracle(T, Ao[0], so[0], Bo[0], inf[0], up, 1e-8, 2048, 0)
+
+
 def test_recorded_graph_replays_match_oracle(T, ctx):
     """The same structure four times with different data: the first call runs
     the kernels directly, the second records the first half of the update as

@@ -160,17 +160,17 @@ def test_features_match_oracle(T, ctx):
 
 def test_learned_update_uses_model_rank(T, ctx):
     """With a model whose output is a constant y, the update uses the sketch
-    rank of the rule k = 32 ceil((1.5 2^y + 32) / 32) (plain when k > 0.6 n)
+    rank of the rule k = 32 ceil((1.5 2^y + 32) / 32) (plain when k > n / 4)
     and accepts when the sketch covers chi* (with the rule's oversampling)."""
-    a, b, s_true = _spectrum_theta(256, 3.0, 21)
+    a, b, s_true = _spectrum_theta(512, 3.0, 21)
     theta = np.einsum("asm,mtb->astb", a, b)
-    want_chi, _ = oracle.trunc_rule(s_true, 1, 256, 1e-8, 0.0)
+    want_chi, _ = oracle.trunc_rule(s_true, 1, 512, 1e-8, 0.0)
     m = T.SketchModel(ctx, seed=0)
     p0 = np.zeros(omlp.N_PARAMS, dtype=np.float32)
     y_const = math.log2(want_chi) + 0.5
     p0[-1] = y_const                       # b3: constant prediction
     m.set_params(p0)
-    k_rule = omlp.sketch_rank(y_const, 256, 200)
+    k_rule = omlp.sketch_rank(y_const, 512, 200)
     prev = up(T, ctx, s_true, T.F64)
     p = T.update_params(chi_min=1, chi_max=200, target_trunc_err=1e-8, direction=1, svd_mode=T.SVD_LEARNED,
                         power_iters=2, seed=4)

@@ -63,7 +63,9 @@ def test_features_closed_form():
 def test_sketch_rank_rule():
     assert mlp.sketch_rank(math.log2(100.0), 2048, 1024) == 192   # 150 + 32 = 182 -> 192
     assert mlp.sketch_rank(math.log2(1024.0) + 0.01, 2048, 1024) is None
-    assert mlp.sketch_rank(9.9, 600, 1024) is None                # k = 1472 > 0.6 * 600
+    assert mlp.sketch_rank(9.9, 600, 1024) is None                # k = 1472 > 600 / 4
+    assert mlp.sketch_rank(math.log2(320.0), 2048, 1024) == 512   # 480 + 32 -> 512 = n / 4
+    assert mlp.sketch_rank(math.log2(330.0), 2048, 1024) is None  # 527 -> 544 > n / 4
     assert mlp.sketch_rank(5.0, 2048, 1024) == 96                 # 48 + 32 = 80 -> 96
 
 
