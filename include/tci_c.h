@@ -538,6 +538,29 @@ tci_status tci_split_batched(tci_context ctx, int n, const tci_tensor* theta,
 tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
                            tci_tensor R, tci_tensor x, tci_tensor y);
 
+/* tci_heff_matvec for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same operation, operands, precision and kernels as tci_heff_matvec, but
+ * its workspace (the MPO pair W12, the intermediates X1 and X2 and, in the
+ * split-BF16x3 precision, the operand planes) lives in a fixed device array
+ * of 64 MiB per device, held from library load until the process ends; the
+ * call itself makes no device allocation and no free.
+ * - y must already own or wrap storage for chi_l*d*d*chi_r elements of the
+ *   operands' dtype (TCI_ERR_INVALID_ARGUMENT / TCI_ERR_DTYPE otherwise); its
+ *   shape is set to (chi_l, d, d, chi_r).
+ * - Shapes whose workspace exceeds 64 MiB are rejected with
+ *   TCI_ERR_INVALID_ARGUMENT before any work is queued (for w = 5, d = 2
+ *   and chi_l = chi_r = chi: complex64 in split-BF16x3 and complex128 both
+ *   fit up to chi = 320).
+ * - Every call on one device shares that device's array and leaves its
+ *   contents behind; whatever must start at zero is cleared by a kernel on
+ *   the context stream.  Calls on the same stream are ordered; calls that
+ *   overlap on one device (other streams, other contexts, other threads)
+ *   race on the array and give undefined results.
+ * - Stream-ordered on the context stream; does not synchronise. */
+tci_status tci_heff_matvec_noalloc(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
+                                   tci_tensor R, tci_tensor x, tci_tensor y);
+
 /* Lowest Ritz pair after at most n_matvec matvecs of Lanczos with full
  * re-orthogonalisation (FP64 scalars and vector arithmetic): after the
  * three-term recurrence, one classical Gram-Schmidt pass against the whole

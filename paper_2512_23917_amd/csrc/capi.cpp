@@ -218,6 +218,7 @@ tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream,
   }
   if (device_id < 0 || device_id >= ndev) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "bad device id");
   TCI_CHECK_HIP(hipSetDevice(device_id));
+  TCI_TRY(noalloc_scratch_init(device_id));
   auto* c = new tci_context_s();
   c->device = device_id;
   c->stream = static_cast<hipStream_t>(hip_stream);

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,26 +61,57 @@ static tci_status heff_check(tci_tensor L, tci_tensor W1, tci_tensor W2, tci_ten
   return TCI_OK;
 }
 
+// Bump allocation inside a caller-provided device region (the fixed scratch
+// of the allocation-free matvec); regions are 256-byte aligned like the arena's.
+struct Bump {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* get(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (!base || bytes > cap - used) return nullptr;
+    void* p = base + used;
+    used += bytes;
+    return p;
+  }
+};
+
+static size_t round256(size_t b) { return b == 0 ? 256 : (b + 255) & ~size_t(255); }
+
+// Device bytes that heff_prepare takes for these shapes (W12, X1, X2 and, in
+// the split-BF16x3 precision, the four operand plane sets).
+static size_t heff_workspace_bytes(int dt, int prec, int chil, int chir, int wd, int d) {
+  const size_t es = elem_bytes(dt);
+  const int kw = wd * d * d, dd = d * d;
+  size_t b = round256(es * (size_t)kw * kw) + 2 * round256(es * (size_t)chil * kw * chir);
+  if ((dt == C64 || dt == F32) && prec == PREC_BF16X3)
+    b += round256(planes_bytes(dt, chil * wd, chil)) + round256(planes_bytes(dt, chir, wd * chir)) +
+         round256(planes_bytes(dt, dd * chir, chil)) + round256(planes_bytes(dt, chil * dd, wd * chir));
+  return b;
+}
+
+// ws == nullptr: workspace from the context's arena; otherwise from ws.
 static tci_status heff_prepare(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R, int chil,
-                               int chir, int wd, int d, HeffPlan& p) {
+                               int chir, int wd, int d, HeffPlan& p, Bump* ws = nullptr) {
+  auto get = [&](size_t bytes) -> void* { return ws ? ws->get(bytes) : ctx->arena.get(bytes); };
   p.dt = L->dtype;
   p.prec = is_double(p.dt) ? PREC_FP64 : ctx->precision;
   p.chil = chil; p.chir = chir; p.w = wd; p.d = d;
   p.L = L->data; p.R = R->data;
   const size_t es = elem_bytes(p.dt);
   const int kw = wd * d * d;
-  p.W12 = ctx->arena.get(es * (size_t)kw * kw);
-  p.X1 = ctx->arena.get(es * (size_t)chil * kw * chir);
-  p.X2 = ctx->arena.get(es * (size_t)chil * kw * chir);
+  p.W12 = get(es * (size_t)kw * kw);
+  p.X1 = get(es * (size_t)chil * kw * chir);
+  p.X2 = get(es * (size_t)chil * kw * chir);
   if (!p.W12 || !p.X1 || !p.X2) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "heff workspace");
   TCI_CHECK_HIP(mpo_pair(p.dt, W1->data, W2->data, p.W12, wd, d, ctx->stream));
   p.planes = (p.dt == C64 || p.dt == F32) && p.prec == PREC_BF16X3;
   if (p.planes) {
     const int dd = d * d;
-    p.Lp = ctx->arena.get(planes_bytes(p.dt, chil * wd, chil));
-    p.Rp = ctx->arena.get(planes_bytes(p.dt, chir, wd * chir));
-    p.Xp = ctx->arena.get(planes_bytes(p.dt, dd * chir, chil));
-    p.X2p = ctx->arena.get(planes_bytes(p.dt, chil * dd, wd * chir));
+    p.Lp = get(planes_bytes(p.dt, chil * wd, chil));
+    p.Rp = get(planes_bytes(p.dt, chir, wd * chir));
+    p.Xp = get(planes_bytes(p.dt, dd * chir, chil));
+    p.X2p = get(planes_bytes(p.dt, chil * dd, wd * chir));
     if (!p.Lp || !p.Rp || !p.Xp || !p.X2p) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "heff plane workspace");
     // L' = L[(a,w),a'] as op(A) of the first product; R'^T as op(B) of the last
     TCI_CHECK_HIP(split_a(p.dt, OP_N, L->data, chil, 0, chil * wd, chil, p.Lp, 1, ctx->stream));
@@ -141,6 +173,35 @@ static tci_status heff_apply(tci_context ctx, const HeffPlan& p, const void* x, 
   return TCI_OK;
 }
 
+// Fixed device scratch of the allocation-free matvec.  In host code the
+// array's name is only a host-side stand-in: its device address, one per
+// device, comes from hipGetSymbolAddress at context creation (with that
+// device current) and is the only form in which host code hands the array to
+// kernels.
+static __device__ __align__(256) unsigned char scratch[HEFF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+tci_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "device id beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TCI_OK;
+  void* ptr = nullptr;
+  TCI_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) TCI_RET(TCI_ERR_DEVICE, "hipGetSymbolAddress returned a null scratch address");
+  g_scratch_ptr[device] = ptr;
+  return TCI_OK;
+}
+
+static void* noalloc_scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
 }  // namespace tci
 
 using namespace tci;
@@ -160,6 +221,40 @@ tci_status tci_heff_matvec(tci_context ctx, tci_tensor L, tci_tensor W1, tci_ten
   TCI_TRY(heff_prepare(ctx, L, W1, W2, R, chil, chir, wd, d, p));
   const int64_t ysh[4] = {chil, d, d, chir};
   TCI_TRY(ensure_shape(ctx, y, L->dtype, 4, ysh));
+  TCI_TRY(heff_apply(ctx, p, x->data, y->data));
+  return TCI_OK;
+} TCI_API_CATCH
+
+tci_status tci_heff_matvec_noalloc(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2, tci_tensor R,
+                                   tci_tensor x, tci_tensor y) try {
+  if (!ctx || !y) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "null argument");
+  TCI_CHECK_HIP(hipSetDevice(ctx->device));
+  int chil, chir, wd, d;
+  TCI_TRY(heff_check(L, W1, W2, R, x, chil, chir, wd, d));
+  if (y == x) TCI_RET(TCI_ERR_INVALID_ARGUMENT, "y must not alias x");
+  const int dt = L->dtype;
+  const int prec = is_double(dt) ? PREC_FP64 : ctx->precision;
+  const size_t need = heff_workspace_bytes(dt, prec, chil, chir, wd, d);
+  if (need > HEFF_NOALLOC_SCRATCH_BYTES)
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "heff_matvec_noalloc: these shapes need " + std::to_string(need) +
+                                          " bytes of workspace, above the fixed scratch of " +
+                                          std::to_string(HEFF_NOALLOC_SCRATCH_BYTES) + " bytes");
+  if (y->dtype != dt) TCI_RET(TCI_ERR_DTYPE, "heff_matvec_noalloc: y must have the operands' dtype");
+  const size_t ybytes = (size_t)chil * d * d * chir * elem_bytes(dt);
+  if (y->empty || !y->data || y->cap < ybytes)
+    TCI_RET(TCI_ERR_INVALID_ARGUMENT, "heff_matvec_noalloc: y must hold chi_l*d*d*chi_r elements already");
+  void* ptr = noalloc_scratch_ptr(ctx->device);
+  if (!ptr) TCI_RET(TCI_ERR_DEVICE, "no scratch address for this device (context not created by tci_create_context)");
+  Trace tr(ctx, "heff_matvec_noalloc",
+           ctx->verbose ? std::to_string(chil) + "," + std::to_string(wd) + "," + std::to_string(chir) : std::string());
+  Bump ws;
+  ws.base = static_cast<char*>(ptr);
+  ws.cap = HEFF_NOALLOC_SCRATCH_BYTES;
+  HeffPlan p{};
+  TCI_TRY(heff_prepare(ctx, L, W1, W2, R, chil, chir, wd, d, p, &ws));
+  y->order = 4;
+  y->shape[0] = chil; y->shape[1] = d; y->shape[2] = d; y->shape[3] = chir;
+  y->nlabels = 0;
   TCI_TRY(heff_apply(ctx, p, x->data, y->data));
   return TCI_OK;
 } TCI_API_CATCH

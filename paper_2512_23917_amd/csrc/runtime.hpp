@@ -135,6 +135,13 @@ inline size_t tbytes(const tci_tensor_s* t) { return (size_t)tsize(t) * elem_byt
 // Make `t` an owning (or adequately sized) tensor of the given shape/dtype.
 tci_status ensure_shape(tci_context ctx, tci_tensor t, int dtype, int order, const int64_t* shape);
 
+// Size of the fixed device scratch of tci_heff_matvec_noalloc (per device).
+constexpr size_t HEFF_NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+
+// Looks up, once per device, the device address of that scratch; call with
+// `device` current (tci_create_context does).
+tci_status noalloc_scratch_init(int device);
+
 // Tracer for TCI_VERBOSE (Spec, environment variables).
 struct Trace {
   tci_context ctx;

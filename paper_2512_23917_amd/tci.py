@@ -152,6 +152,7 @@ def lib():
         "tci_two_site_update": (i32, [p, p, p, p, P(UpdateParams), p, p, p, P(UpdateInfo)]),
         "tci_split_batched": (i32, [p, ctypes.c_int, P(p), P(UpdateParams), P(p), P(p), P(p), P(UpdateInfo)]),
         "tci_heff_matvec": (i32, [p, p, p, p, p, p, p]),
+        "tci_heff_matvec_noalloc": (i32, [p, p, p, p, p, p, p]),
         "tci_lanczos_ground": (i32, [p, p, p, p, p, p, ctypes.c_int, P(f64)]),
         "tci_sketch_model_create": (i32, [p, ctypes.c_uint64, P(p)]),
         "tci_sketch_model_destroy": (i32, [p, p]),
@@ -697,6 +698,12 @@ def heff_matvec(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, x: T
     if y is None:
         y = Tensor.empty(ctx, x.dtype, int(np.prod(x.shape())))
     _check(lib().tci_heff_matvec(ctx.h, L.h, W1.h, W2.h, R.h, x.h, y.h), "tci_heff_matvec")
+    return y
+
+
+def heff_matvec_noalloc(ctx: Context, L: Tensor, W1: Tensor, W2: Tensor, R: Tensor, x: Tensor, y: Tensor) -> Tensor:
+    """tci_heff_matvec_noalloc: y must already hold x's number of elements."""
+    _check(lib().tci_heff_matvec_noalloc(ctx.h, L.h, W1.h, W2.h, R.h, x.h, y.h), "tci_heff_matvec_noalloc")
     return y
 
 
