@@ -242,6 +242,11 @@ tci_status tci_create_context(tci_context* out, int device_id, void* hip_stream,
 tci_status tci_destroy_context(tci_context ctx) try {
   TCI_TRY(check_ctx(ctx));
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->aux_ev) (void)hipEventDestroy(ctx->aux_ev);
   ctx->bs_graphs.reset();
   ctx->arena.release();
   tci_status st = TCI_OK;

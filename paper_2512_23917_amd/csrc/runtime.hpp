@@ -84,6 +84,10 @@ struct tci_context_s {
   tci::Arena arena;
   // recorded HIP graphs of the block-sparse update (owned; see bsparse.cpp)
   std::shared_ptr<void> bs_graphs;
+  // second stream (default priority) and an ordering event for work of one
+  // call that overlaps the context stream's; created on first use, owned
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev = nullptr;
   uint32_t magic = 0x7C1C0DE1u;
 };
 

@@ -434,23 +434,49 @@ static tci_status check_direction(tci_context ctx, const tci_update_params& p, i
 // at most 5/4 of the smallest), each group on gathered copies of its
 // problems' reduction data, so that no problem's eigenvectors, back-
 // transformation and factor products are padded to the batch's largest chi.
-static tci_status tsvd_store_grouped(tci_context ctx, int dt, int wdt, int nb, int chil, int d, int chir,
-                                     const void* theta, const TruncParams& tp, const std::vector<int>& gslot,
-                                     const tci_update_params& p, tci_tensor* A_out, tci_tensor* s_out,
-                                     tci_tensor* B_out, tci_update_info* infos, bool fallback,
-                                     const std::vector<int>* krank) {
-  hipStream_t s = ctx->stream;
-  const int m = chil * d, n = d * chir, ng = std::min(m, n);
-  const int kmax = std::max(1, std::min(tp.chi_max, ng));
+// The plain truncated SVD in two halves, so that the first (Gram matrices,
+// reductions, eigenvalues, truncation rule: no host synchronisation) can run
+// on a second stream while other work of the same call proceeds.
+struct PlainPending {
+  int nb = 0, m = 0, n = 0, ng = 0, kmax = 0;
+  const void* theta = nullptr;
   TsvdStage st;
-  TCI_TRY(tsvd_eigvals(ctx, wdt, nb, m, n, theta, kmax, st));
+  int* chi = nullptr;
+  double *err = nullptr, *disc = nullptr, *sv = nullptr, *sinv = nullptr, *sn = nullptr;
+};
+
+static tci_status tsvd_plain_begin(tci_context ctx, int wdt, int nb, int m, int n, const void* theta,
+                                   const TruncParams& tp, PlainPending& pp) {
+  hipStream_t s = ctx->stream;
+  pp.nb = nb; pp.m = m; pp.n = n; pp.ng = std::min(m, n);
+  pp.kmax = std::max(1, std::min(tp.chi_max, pp.ng));
+  pp.theta = theta;
+  const int kmax = pp.kmax;
+  TCI_TRY(tsvd_eigvals(ctx, wdt, nb, m, n, theta, kmax, pp.st));
   ARENA(chi, int, nb);
   ARENA(err, double, nb);
   ARENA(disc, double, nb);
   ARENA(sv, double, (size_t)kmax * nb);
   ARENA(sinv, double, (size_t)kmax * nb);
   ARENA(sn, double, (size_t)kmax * nb);
-  TCI_CHECK_HIP(trunc_select(st.lam, kmax, kmax, st.total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
+  TCI_CHECK_HIP(trunc_select(pp.st.lam, kmax, kmax, pp.st.total, tp, chi, err, disc, sv, sinv, sn, kmax, nb, s));
+  pp.chi = chi; pp.err = err; pp.disc = disc; pp.sv = sv; pp.sinv = sinv; pp.sn = sn;
+  return TCI_OK;
+}
+
+// The vector stage and the write-back of a begun plain batch, on the
+// context stream (the caller has made the begun work visible to it).
+static tci_status tsvd_plain_finish(tci_context ctx, int dt, int wdt, int chil, int d, int chir, const PlainPending& pp,
+                                    const std::vector<int>& gslot, const tci_update_params& p, tci_tensor* A_out,
+                                    tci_tensor* s_out, tci_tensor* B_out, tci_update_info* infos, bool fallback,
+                                    const std::vector<int>* krank) {
+  hipStream_t s = ctx->stream;
+  const int nb = pp.nb, m = pp.m, n = pp.n, ng = pp.ng, kmax = pp.kmax;
+  const void* theta = pp.theta;
+  const TsvdStage& st = pp.st;
+  int* chi = pp.chi;
+  double *sv = pp.sv, *sinv = pp.sinv, *sn = pp.sn;
+  const double *err = pp.err, *disc = pp.disc;
   std::vector<int> chi_h(nb);
   std::vector<double> err_h(nb), disc_h(nb), total_h(nb);
   TCI_CHECK_HIP(hipMemcpyAsync(chi_h.data(), chi, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
@@ -522,6 +548,16 @@ static tci_status tsvd_store_grouped(tci_context ctx, int dt, int wdt, int nb, i
   return TCI_OK;
 }
 
+static tci_status tsvd_store_grouped(tci_context ctx, int dt, int wdt, int nb, int chil, int d, int chir,
+                                     const void* theta, const TruncParams& tp, const std::vector<int>& gslot,
+                                     const tci_update_params& p, tci_tensor* A_out, tci_tensor* s_out,
+                                     tci_tensor* B_out, tci_update_info* infos, bool fallback,
+                                     const std::vector<int>* krank) {
+  PlainPending pp;
+  TCI_TRY(tsvd_plain_begin(ctx, wdt, nb, chil * d, d * chir, theta, tp, pp));
+  return tsvd_plain_finish(ctx, dt, wdt, chil, d, chir, pp, gslot, p, A_out, s_out, B_out, infos, fallback, krank);
+}
+
 // trunc_svd of nb matrices theta ((chil*d) x (d*chir)): th_lo in the storage
 // dtype dt, thw its FP64 working copy (the same pointer when dt is FP64);
 // plain, randomized or learned per params; then renormalised s and the
@@ -543,6 +579,31 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
       if (kvec[i] > 0 && kvec[i] < ng) sk_idx.push_back(i);
       else plain_idx.push_back(i);
     }
+  }
+  // The problems sent to the plain SVD from the start begin their eigenvalue
+  // stage on the second stream, so that their reductions (bound by HBM and
+  // launch latency) overlap the sketches (bound by the FP64 matrix cores).
+  PlainPending early;
+  std::vector<int> early_idx;
+  struct AuxJoin {   // no return leaves work of this call running on the second stream
+    hipStream_t st = nullptr;
+    ~AuxJoin() { if (st) (void)hipStreamSynchronize(st); }
+  } aux_join;
+  if (!plain_idx.empty() && !sk_idx.empty() && ng > JACOBI_MAX_K) {
+    early_idx = plain_idx;
+    plain_idx.clear();
+    const void* hi = thw;
+    if ((int)early_idx.size() != nb) TCI_TRY(gather(ctx, wdt, thw, smn, early_idx, &hi));
+    if (!ctx->aux) TCI_CHECK_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    if (!ctx->aux_ev) TCI_CHECK_HIP(hipEventCreateWithFlags(&ctx->aux_ev, hipEventDisableTiming));
+    TCI_CHECK_HIP(hipEventRecord(ctx->aux_ev, ctx->stream));
+    TCI_CHECK_HIP(hipStreamWaitEvent(ctx->aux, ctx->aux_ev, 0));
+    aux_join.st = ctx->aux;
+    const hipStream_t main_stream = ctx->stream;
+    ctx->stream = ctx->aux;
+    const tci_status sb = tsvd_plain_begin(ctx, wdt, (int)early_idx.size(), m, n, hi, tp, early);
+    ctx->stream = main_stream;
+    TCI_TRY(sb);
   }
   // Sketched problems run in groups of similar rank (ascending k, the
   // largest at most 5/4 of the smallest), so that no problem's products are
@@ -606,6 +667,11 @@ static tci_status split_and_store(tci_context ctx, int dt, int wdt, int nb, int 
                               false, &kvec));
       }
     }
+  }
+  if (!early_idx.empty()) {
+    TCI_CHECK_HIP(hipStreamSynchronize(ctx->aux));
+    TCI_TRY(tsvd_plain_finish(ctx, dt, wdt, chil, d, chir, early, early_idx, p, A_out, s_out, B_out, infos,
+                              p.svd_mode != TCI_SVD_PLAIN, &kvec));
   }
   if (!plain_idx.empty()) {
     std::sort(plain_idx.begin(), plain_idx.end());
