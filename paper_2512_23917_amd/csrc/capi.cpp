@@ -781,6 +781,11 @@ tci_status tci_contract(tci_context ctx, tci_tensor a, const int32_t* la, int na
     if (!Cp) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   }
   GemmArgs g = gemm_args((int)M, (int)N, (int)K, opA, opB, Ap, lda, Bp, ldb, Cp, N);
+  if ((dt == C128 || dt == F64) && K >= 256) {
+    // FP64 products with few output tiles split K (see gemm.hpp)
+    g.kws = ctx->arena.get(GEMM_SPLITK_WS_BYTES);
+    g.kws_bytes = g.kws ? GEMM_SPLITK_WS_BYTES : 0;
+  }
   TCI_CHECK_HIP(gemm(dt, prec_for(ctx, dt), g, ctx->stream));
   if (!(same && !alias)) {
     // C has bonds nat; permute to lc

@@ -589,7 +589,11 @@ __global__ void e2_kernel(const double* e, double* e2, long long sde, int n, int
 
 // Bisection, one lane per wanted eigenvalue (64 per wave): lane j halves its
 // own interval [lo, hi] (count(lo) <= t < count(hi), t the ascending index)
-// until it is at rounding level.  All lanes walk the same Sturm recurrence
+// until it is at rounding level relative to the eigenvalue itself.  Small
+// eigenvalues are resolved to that relative accuracy (more steps than the
+// absolute accuracy of the norm would need) because inverse iteration with
+// shifts only absolutely accurate leaves the vectors of closely spaced small
+// eigenvalues far from orthogonal, which costs a second Cholesky-QR pass.  All lanes walk the same Sturm recurrence
 // over i at their own shift, so the loop is uniform and d, e^2 are read at
 // the same address by every lane.  One evaluation per step and eigenvalue
 // keeps the arithmetic 10x below a 64-point multisection per eigenvalue; the
@@ -658,36 +662,76 @@ __device__ inline double hash_uniform(unsigned b, unsigned j, unsigned i) {
   return ((double)h + 0.5) * (2.0 / 4294967296.0) - 1.0;
 }
 
+// The recurrences below are sequential in i, one lane per eigenvector.  Each
+// pass walks i in blocks of IV_BLK and issues all loads of a block before the
+// block's arithmetic, so that one memory latency is paid per block rather than
+// per step (the stores of a step could alias the next step's loads, which
+// keeps the compiler from moving them ahead by itself).
+constexpr int IV_BLK = 16;
+
 // One solve with the stored factors of column j: z[:, j] <- (T - lam_j)^-1
 // (pre * z[:, j]); returns the factor 1 / max|z| for the next right-hand side.
-__device__ inline double invit_solve(double* z, long ld, int j, int n, const double* du1, const double* du,
+// ru holds the reciprocals of U's diagonal.
+__device__ inline double invit_solve(double* z, long ld, int j, int n, const double* ru, const double* du,
                                      const double* du2, const double* dl, double pre) {
   // forward: b <- L^-1 P b, writing the intermediate into z
   double bi = z[j] * pre;
-  #pragma unroll 8
-  for (int i = 0; i < n - 1; ++i) {
-    const double bn = z[(long)(i + 1) * ld + j] * pre;
-    const double s = dl[(long)i * ld + j];
-    if (fabs(s) >= 4.0) {
-      const double m = s - (s >= 0 ? 4.0 : -4.0);
-      z[(long)i * ld + j] = bn;
-      bi = bi - m * bn;
-    } else {
-      z[(long)i * ld + j] = bi;
-      bi = bn - s * bi;
+  for (int i0 = 0; i0 < n - 1; i0 += IV_BLK) {
+    double zb[IV_BLK], sb[IV_BLK];
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 + u;
+      zb[u] = 0.0;
+      sb[u] = 0.0;
+      if (i < n - 1) {
+        zb[u] = z[(long)(i + 1) * ld + j];
+        sb[u] = dl[(long)i * ld + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 + u;
+      if (i < n - 1) {
+        const double bn = zb[u] * pre;
+        const double sv = sb[u];
+        if (fabs(sv) >= 4.0) {
+          const double m = sv - (sv >= 0 ? 4.0 : -4.0);
+          z[(long)i * ld + j] = bn;
+          bi = bi - m * bn;
+        } else {
+          z[(long)i * ld + j] = bi;
+          bi = bn - sv * bi;
+        }
+      }
     }
   }
   z[(long)(n - 1) * ld + j] = bi;
   // backward: U x = b
   double x1 = 0.0, x2 = 0.0, amax = 0.0;
-  #pragma unroll 8
-  for (int i = n - 1; i >= 0; --i) {
-    const double x = (z[(long)i * ld + j] - du[(long)i * ld + j] * x1 - du2[(long)i * ld + j] * x2) /
-                     du1[(long)i * ld + j];
-    z[(long)i * ld + j] = x;
-    x2 = x1;
-    x1 = x;
-    amax = fmax(amax, fabs(x));
+  for (int i0 = n - 1; i0 >= 0; i0 -= IV_BLK) {
+    double zb[IV_BLK], c1[IV_BLK], c2[IV_BLK], r0[IV_BLK];
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 - u;
+      zb[u] = 0.0; c1[u] = 0.0; c2[u] = 0.0; r0[u] = 0.0;
+      if (i >= 0) {
+        zb[u] = z[(long)i * ld + j];
+        c1[u] = du[(long)i * ld + j];
+        c2[u] = du2[(long)i * ld + j];
+        r0[u] = ru[(long)i * ld + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 - u;
+      if (i >= 0) {
+        const double x = (zb[u] - c1[u] * x1 - c2[u] * x2) * r0[u];
+        z[(long)i * ld + j] = x;
+        x2 = x1;
+        x1 = x;
+        amax = fmax(amax, fabs(x));
+      }
+    }
   }
   return amax > 0.0 ? 1.0 / amax : 1.0;
 }
@@ -695,7 +739,7 @@ __device__ inline double invit_solve(double* z, long ld, int j, int n, const dou
 __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, long long sde, int n,
                                                    const double* lam, long long slam, const int* chi,
                                                    int kmax, double* Z, long long ldz, long long sZ,
-                                                   double* w_du1, double* w_du, double* w_du2,
+                                                   double* w_ru, double* w_du, double* w_du2,
                                                    double* w_dl, long long sw, int batch) {
   const int b = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -704,7 +748,7 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   if (j >= cb) return;
   const double* db = d + b * sde;
   const double* eb = e + b * sde;
-  double* du1 = w_du1 + b * sw;
+  double* ru = w_ru + b * sw;
   double* du = w_du + b * sw;
   double* du2 = w_du2 + b * sw;
   double* dl = w_dl + b * sw;
@@ -717,48 +761,64 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
 
   // Elimination keeps one "active" row (entries a_i, c_i in columns i, i+1)
   // and meets original row i+1 (e_i, d_{i+1} - lam, e_{i+1}).  U row i is
-  // stored as (du1, du, du2); the multiplier goes to dl, offset by +-4 when
-  // the rows were interchanged (|multiplier| <= 1 in both cases).
+  // stored as (1 / pivot, du, du2); the multiplier goes to dl, offset by +-4
+  // when the rows were interchanged (|multiplier| <= 1 in both cases).
   double a_i = db[0] - lamj;       // current diagonal entry of the active row i
   double c_i = (n > 1) ? eb[0] : 0.0;  // super-diagonal of active row
-  #pragma unroll 8
-  for (int i = 0; i < n - 1; ++i) {
-    const double sub = eb[i];                 // entry (i+1, i)
-    const double a_n = db[i + 1] - lamj;      // entry (i+1, i+1)
-    const double c_n = (i + 1 < n - 1) ? eb[i + 1] : 0.0;  // entry (i+1, i+2)
-    if (fabs(a_i) >= fabs(sub)) {
-      double piv = a_i;
-      if (fabs(piv) < tiny) piv = (piv >= 0 ? tiny : -tiny);
-      const double m = sub / piv;
-      du1[(long)i * ld + j] = piv;
-      du[(long)i * ld + j] = c_i;
-      du2[(long)i * ld + j] = 0.0;
-      dl[(long)i * ld + j] = m;
-      a_i = a_n - m * c_i;
-      c_i = c_n;
-    } else {
-      // interchange rows i and i+1
-      const double m = a_i / sub;
-      du1[(long)i * ld + j] = sub;
-      du[(long)i * ld + j] = a_n;
-      du2[(long)i * ld + j] = c_n;
-      dl[(long)i * ld + j] = m + (m >= 0 ? 4.0 : -4.0);  // |stored| >= 4 marks an interchange
-      const double na = c_i - m * a_n;
-      a_i = na;
-      c_i = -m * c_n;
+  for (int i0 = 0; i0 < n - 1; i0 += IV_BLK) {
+    double ev[IV_BLK + 1], dv[IV_BLK];
+#pragma unroll
+    for (int u = 0; u <= IV_BLK; ++u) {
+      const int i = i0 + u;
+      ev[u] = i < n - 1 ? eb[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 + u;
+      dv[u] = i + 1 < n ? db[i + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) {
+      const int i = i0 + u;
+      if (i < n - 1) {
+        const double sub = ev[u];                              // entry (i+1, i)
+        const double a_n = dv[u] - lamj;                       // entry (i+1, i+1)
+        const double c_n = (i + 1 < n - 1) ? ev[u + 1] : 0.0;  // entry (i+1, i+2)
+        if (fabs(a_i) >= fabs(sub)) {
+          double piv = a_i;
+          if (fabs(piv) < tiny) piv = (piv >= 0 ? tiny : -tiny);
+          const double m = sub / piv;
+          ru[(long)i * ld + j] = 1.0 / piv;
+          du[(long)i * ld + j] = c_i;
+          du2[(long)i * ld + j] = 0.0;
+          dl[(long)i * ld + j] = m;
+          a_i = a_n - m * c_i;
+          c_i = c_n;
+        } else {
+          // interchange rows i and i+1
+          const double m = a_i / sub;
+          ru[(long)i * ld + j] = 1.0 / sub;
+          du[(long)i * ld + j] = a_n;
+          du2[(long)i * ld + j] = c_n;
+          dl[(long)i * ld + j] = m + (m >= 0 ? 4.0 : -4.0);  // |stored| >= 4 marks an interchange
+          const double na = c_i - m * a_n;
+          a_i = na;
+          c_i = -m * c_n;
+        }
+      }
     }
   }
   {
     double piv = a_i;
     if (fabs(piv) < tiny) piv = (piv >= 0 ? tiny : -tiny);
-    du1[(long)(n - 1) * ld + j] = piv;
+    ru[(long)(n - 1) * ld + j] = 1.0 / piv;
     du[(long)(n - 1) * ld + j] = 0.0;
     du2[(long)(n - 1) * ld + j] = 0.0;
   }
   // two solves from a pseudo-random start
   for (int i = 0; i < n; ++i) z[(long)i * ld + j] = hash_uniform(b, j, i);
   double scale = 1.0;
-  for (int it = 0; it < 2; ++it) scale = invit_solve(z, ld, j, n, du1, du, du2, dl, scale);
+  for (int it = 0; it < 2; ++it) scale = invit_solve(z, ld, j, n, ru, du, du2, dl, scale);
   // normalise to unit 2-norm (after the last max-scaling)
   double nn = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -766,7 +826,14 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
     nn += x * x;
   }
   const double inv = scale / sqrt(nn);
-  for (int i = 0; i < n; ++i) z[(long)i * ld + j] *= inv;
+  for (int i0 = 0; i0 < n; i0 += IV_BLK) {
+    double zb[IV_BLK];
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u) zb[u] = i0 + u < n ? z[(long)(i0 + u) * ld + j] : 0.0;
+#pragma unroll
+    for (int u = 0; u < IV_BLK; ++u)
+      if (i0 + u < n) z[(long)(i0 + u) * ld + j] = zb[u] * inv;
+  }
 }
 
 // Tight clusters (consecutive eigenvalues closer than INVIT_CLUSTER_TOL of
@@ -792,7 +859,7 @@ __device__ inline double wave_sum_d(double v) {
 __global__ __launch_bounds__(64) void invit_cluster_kernel(const double* d, const double* e, long long sde, int n,
                                                            const double* lam, long long slam, const int* chi,
                                                            int kmax, double* Z, long long ldz, long long sZ,
-                                                           const double* w_du1, const double* w_du,
+                                                           const double* w_ru, const double* w_du,
                                                            const double* w_du2, const double* w_dl, long long sw) {
   const int b = blockIdx.x, lane = threadIdx.x;
   const int cb = chi ? min(chi[b], kmax) : kmax;
@@ -817,7 +884,7 @@ __global__ __launch_bounds__(64) void invit_cluster_kernel(const double* d, cons
         double scale = 1.0;
         for (int it = 0; it < 3; ++it) {
           if (lane < cn)
-            scale = invit_solve(z, ld, m, n, w_du1 + b * sw, w_du + b * sw, w_du2 + b * sw, w_dl + b * sw, scale);
+            scale = invit_solve(z, ld, m, n, w_ru + b * sw, w_du + b * sw, w_du2 + b * sw, w_dl + b * sw, scale);
           __syncthreads();
           // members c0 .. c0+cn-1 in order: apply the pending scale, remove the
           // earlier members of the cluster, normalise
@@ -850,14 +917,14 @@ hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n,
                          double* work, int batch, hipStream_t s) {
   if (kmax <= 0 || batch <= 0) return hipSuccess;
   const long long sw = (long long)n * ldz;  // each workspace array: n x ldz per problem
-  double* du1 = work;
+  double* ru = work;
   double* du = work + sw * batch;
   double* du2 = work + 2 * sw * batch;
   double* dl = work + 3 * sw * batch;
   hipLaunchKernelGGL(invit_kernel, dim3((kmax + 63) / 64, batch), dim3(64), 0, s, d, e, sde, n, lam,
-                     slam, chi, kmax, Z, ldz, sZ, du1, du, du2, dl, sw, batch);
+                     slam, chi, kmax, Z, ldz, sZ, ru, du, du2, dl, sw, batch);
   hipLaunchKernelGGL(invit_cluster_kernel, dim3(batch), dim3(64), 0, s, d, e, sde, n, lam, slam, chi, kmax, Z, ldz,
-                     sZ, du1, du, du2, dl, sw);
+                     sZ, ru, du, du2, dl, sw);
   return hipGetLastError();
 }
 
@@ -921,6 +988,7 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
   char* Sc = Tc + (size_t)ng * BT_GB * BT_GB * es;   // per-problem S of every group after the T factors
   char* W1 = reinterpret_cast<char*>(work);
   char* W2 = W1 + (size_t)batch * BT_GB * kmax * es;
+  char* kws = W2 + (size_t)batch * BT_GB * kmax * es;   // split-K scratch
   const long long sW = (long long)BT_GB * kmax;
   hipError_t err = hipSuccess;
   // S = V_g^H V_g of every group (over rows j0+1 .. n-1; V_g = columns of Vt
@@ -930,6 +998,7 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
     GemmArgs gs = gemm_args(g, g, rows, OP_R, OP_T, V + ((long)j0 * n + j0 + 1) * es, n,
                             V + ((long)j0 * n + j0 + 1) * es, n, Sc + (size_t)grp * BT_GB * BT_GB * es, BT_GB);
     gs.sA = a.sVt; gs.sB = a.sVt; gs.sC = sTf; gs.batch = batch;
+    gs.kws = kws; gs.kws_bytes = GEMM_SPLITK_WS_BYTES;
     err = gemm(dt, PREC_FP64, gs, s);
     if (err != hipSuccess) return err;
   }
@@ -940,6 +1009,7 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
     GemmArgs g1 = gemm_args(g, kmax, rows, OP_R, OP_N, V + ((long)j0 * n + j0 + 1) * es, n,
                             Uc + (long)(j0 + 1) * ldu * es, ldu, W1, kmax);
     g1.sA = a.sVt; g1.sB = sU; g1.sC = sW; g1.batch = batch;
+    g1.kws = kws; g1.kws_bytes = GEMM_SPLITK_WS_BYTES;
     err = gemm(dt, PREC_FP64, g1, s);
     if (err != hipSuccess) return err;
     GemmArgs g2 = gemm_args(g, kmax, g, OP_N, OP_N, Tc + (size_t)grp * BT_GB * BT_GB * es, BT_GB, W1, kmax, W2,
@@ -958,7 +1028,10 @@ static hipError_t backtransform_impl(const TriArgs& a, void* Tf, long long sTf, 
 }
 
 size_t tridiag_backtransform_tf_elems(int n) { return (size_t)2 * std::max(1, bt_groups(n)) * BT_GB * BT_GB; }
-size_t tridiag_backtransform_work_elems(int kmax) { return (size_t)2 * BT_GB * kmax; }
+size_t tridiag_backtransform_work_bytes(int dtype, int kmax, int batch) {
+  const size_t es = dtype == C128 ? sizeof(cd) : sizeof(double);
+  return es * 2 * BT_GB * (size_t)kmax * batch + GEMM_SPLITK_WS_BYTES;
+}
 
 hipError_t tridiag_backtransform(int dtype, const TriArgs& a, void* Tf, long long sTf, void* U,
                                  long long ldu, long long sU, int kmax, void* work, int batch,

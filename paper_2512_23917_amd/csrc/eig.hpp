@@ -41,9 +41,10 @@ hipError_t tridiag_invit(const double* d, const double* e, long long sde, int n,
                          double* work, int batch, hipStream_t s);
 // U[b] (n x kmax, ld ldu, dtype) <- Q U[b].  Tf: per problem
 // tridiag_backtransform_tf_elems(n) elements of dtype (stride sTf); work:
-// batch * tridiag_backtransform_work_elems(kmax) elements of dtype.
+// tridiag_backtransform_work_bytes(dtype, kmax, batch) bytes (the reflector
+// products plus the split-K scratch of the thin products).
 size_t tridiag_backtransform_tf_elems(int n);
-size_t tridiag_backtransform_work_elems(int kmax);
+size_t tridiag_backtransform_work_bytes(int dtype, int kmax, int batch);
 hipError_t tridiag_backtransform(int dtype, const TriArgs& a, void* Tf, long long sTf, void* U,
                                  long long ldu, long long sU, int kmax, void* work, int batch,
                                  hipStream_t s);

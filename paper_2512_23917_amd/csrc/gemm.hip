@@ -165,11 +165,23 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
 
   int tm, tn, b;
   tile_coords(tm, tn, b);
+  // split-K launches carry the chunk index outermost in the batch dimension
+  int split = 0;
+  if (a.ksplit > 1) {
+    split = b / a.batch;
+    b -= split * a.batch;
+  }
   int M, N, K;
   problem_dims(a, b, M, N, K);
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
   if (a.lower_band > 0 && n0 - (m0 + BM - 1) >= a.lower_band) return;
+  int kbeg = 0, kend = K;
+  if (a.ksplit > 1) {
+    const int kc = ((K + a.ksplit - 1) / a.ksplit + BK - 1) / BK * BK;
+    kbeg = min(K, split * kc);
+    kend = min(K, kbeg + kc);
+  }
 
   const T* A = reinterpret_cast<const T*>(a.A) + (long)b * a.sA;
   const T* B = reinterpret_cast<const T*>(a.B) + (long)b * a.sB;
@@ -188,10 +200,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
       if constexpr (CPLX) acc_im[i][j] = d4{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
-    stage_rows_tile<T, double, BM, BK>(A, a.lda, a.opA, M, K, m0, k0, As_re, As_im);
-    stage_cols_tile<T, double, BN, BK>(B, a.ldb, a.opB, N, K, n0, k0, Bs_re, Bs_im);
+    stage_rows_tile<T, double, BM, BK>(A, a.lda, a.opA, M, kend, m0, k0, As_re, As_im);
+    stage_cols_tile<T, double, BN, BK>(B, a.ldb, a.opB, N, kend, n0, k0, Bs_re, Bs_im);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
@@ -218,6 +230,26 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
           }
         }
     }
+  }
+
+  if (a.ksplit > 1) {
+    // raw partial product of this K chunk: slab (split, b), M x N, row-major
+    T* P = reinterpret_cast<T*>(a.kws) + ((long)split * a.batch + b) * (long)M * N;
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+      for (int j = 0; j < FJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
+          const int col = n0 + wn * WN + j * 16 + lr;
+          if (row < M && col < N) {
+            double vi = 0.0;
+            if constexpr (CPLX) vi = acc_im[i][j][r];
+            st(P + (long)row * N + col, acc_re[i][j][r], vi);
+          }
+        }
+    return;
   }
 
   const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
@@ -536,6 +568,46 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Second pass of a split-K launch: C = alpha * diag(rs) (sum of the chunks'
+// partial products, in chunk order) diag(cs) + beta * C, the same epilogue
+// as the single-pass kernel.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs a) {
+  const int b = blockIdx.y, M = a.m, N = a.n;
+  const long long mn = (long long)M * N;
+  const T* P = reinterpret_cast<const T*>(a.kws);
+  T* C = reinterpret_cast<T*>(a.C) + (long)b * a.sC;
+  const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
+  const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
+  const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < mn; e += (long long)gridDim.x * 256) {
+    const int row = (int)(e / N), col = (int)(e % N);
+    double vr = 0.0, vi = 0.0;
+    for (int sp = 0; sp < a.ksplit; ++sp) {
+      double pr, pi;
+      ld(P + ((long long)sp * a.batch + b) * mn + e, pr, pi);
+      vr += pr;
+      vi += pi;
+    }
+    double sc = 1.0;
+    if (rs) sc *= rs[row];
+    if (cs) sc *= cs[col];
+    vr *= sc; vi *= sc;
+    double outr = a.alpha_re * vr - a.alpha_im * vi;
+    double outi = a.alpha_re * vi + a.alpha_im * vr;
+    T* p = C + (long)row * a.ldc + col;
+    if (!beta0) {
+      double cr, ci;
+      ld(p, cr, ci);
+      outr += a.beta_re * cr - a.beta_im * ci;
+      outi += a.beta_re * ci + a.beta_im * cr;
+    }
+    st(p, outr, outi);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
 template <typename K>
@@ -543,6 +615,57 @@ static hipError_t launch(K kern, const GemmArgs& a, int BM, int BN, hipStream_t 
   dim3 grid((a.n + BN - 1) / BN, (a.m + BM - 1) / BM, a.batch);
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
   hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Number of K chunks for an FP64 launch (1 = no split).  Model: the chip runs
+// 256 workgroups per round (one per compute unit), each at SPLITK_CU_RATE; a
+// launch of W equal workgroups takes ceil(W / 256) rounds.  Cutting K into sp
+// chunks multiplies W by sp and divides a round by sp, and adds a reduction
+// pass that writes and reads sp partial slabs.  The cheapest sp wins (by 5%
+// at least), with chunks of SPLITK_MIN_K or more and within the caller's
+// scratch.
+constexpr int SPLITK_MIN_K = 128;
+constexpr int SPLITK_MAX = 32;
+constexpr long long SPLITK_MAX_TILES = 1024;
+constexpr double SPLITK_CU_RATE = 0.3e12;      // FP64 MFMA flop/s of one compute unit
+constexpr double SPLITK_REDUCE_BW = 4.0e12;    // bytes/s of the reduction pass
+constexpr double SPLITK_LAUNCH_S = 5e-6;
+
+static int splitk_chunks(const GemmArgs& a, int BM, int BN, size_t es) {
+  if (!a.kws || a.dims || a.lower_band > 0 || a.k < 2 * SPLITK_MIN_K) return 1;
+  const long long tiles = (long long)((a.n + BN - 1) / BN) * ((a.m + BM - 1) / BM) * a.batch;
+  if (tiles >= SPLITK_MAX_TILES) return 1;
+  const double wg_s = (es == 16 ? 8.0 : 2.0) * BM * BN * (double)a.k / SPLITK_CU_RATE;   // one unsplit tile
+  const double slab = (double)es * a.m * a.n * a.batch;
+  auto rounds = [](long long w) { return (double)((w + 255) / 256); };
+  int best = 1;
+  double best_t = rounds(tiles) * wg_s;
+  const int spmax = std::min<long long>(SPLITK_MAX, a.k / SPLITK_MIN_K);
+  for (int sp = 2; sp <= spmax; ++sp) {
+    if (sp * slab > (double)a.kws_bytes) break;
+    const double t = rounds(tiles * sp) * wg_s / sp + 2.0 * sp * slab / SPLITK_REDUCE_BW + SPLITK_LAUNCH_S;
+    if (t < 0.95 * best_t) {
+      best = sp;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
+template <typename T, int BM, int BN>
+static hipError_t launch_f64(const GemmArgs& a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.ksplit = splitk_chunks(a, BM, BN, sizeof(T));
+  if (a.ksplit <= 1) {
+    a.ksplit = 0;
+    return launch(gemm_f64_kernel<T, BM, BN>, a, BM, BN, s);
+  }
+  dim3 grid((a.n + BN - 1) / BN, (a.m + BM - 1) / BM, a.batch * a.ksplit);
+  hipLaunchKernelGGL((gemm_f64_kernel<T, BM, BN>), grid, dim3(256), 0, s, a);
+  const long long mn = (long long)a.m * a.n;
+  const unsigned gx = (unsigned)std::min<long long>(1024, (mn + 255) / 256);
+  hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(gx, a.batch), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -572,9 +695,9 @@ hipError_t gemm(int dtype, int prec, const GemmArgs& a, hipStream_t s) {
   }
   switch (dtype) {
     case C128:
-      return launch(gemm_f64_kernel<cd, 128, 64>, a, 128, 64, s);
+      return launch_f64<cd, 128, 64>(a, s);
     case F64:
-      return launch(gemm_f64_kernel<double, 128, 128>, a, 128, 128, s);
+      return launch_f64<double, 128, 128>(a, s);
     case C64:
       if (prec == PREC_BF16X3) return launch(gemm_bf16x3_kernel<cf, 64, 64>, a, 64, 64, s);
       return launch(gemm_f32_kernel<cf, 128, 64>, a, 128, 64, s);

@@ -23,7 +23,17 @@ struct GemmArgs {
   // output tiles whose every entry has col - row >= lower_band are skipped
   // and left unchanged (Hermitian results read from the lower triangle).
   int lower_band;
+  // Optional device scratch for the FP64 kernels.  A launch with too few
+  // output tiles to occupy every compute unit cuts K into chunks whose raw
+  // partial products go to kws (FP64, one M x N slab per chunk and problem);
+  // a second pass sums the chunks in order and applies the scales, alpha and
+  // beta.  Null = never split.  Set by the caller; ksplit is set by gemm().
+  void* kws; size_t kws_bytes;
+  int ksplit;
 };
+
+// Scratch that lets any FP64 launch split (see GemmArgs::kws).
+constexpr size_t GEMM_SPLITK_WS_BYTES = (size_t)96 << 20;
 
 inline GemmArgs gemm_args(int m, int n, int k, int opA, int opB, const void* A, long long lda,
                           const void* B, long long ldb, void* C, long long ldc) {

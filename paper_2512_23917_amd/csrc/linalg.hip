@@ -617,10 +617,11 @@ __device__ inline void st2(cd* p, long long i, double r, double im) { p[i] = cd{
 
 // G = Y^H Y (column mode) or Y Y^H (row mode), k x k per problem
 static hipError_t gram_into(int dt, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
-                            int batch, hipStream_t s) {
+                            int batch, hipStream_t s, void* kws, size_t kws_bytes) {
   GemmArgs g = mode == 0 ? gemm_args(k, k, m, OP_C, OP_N, Y, ldy, Y, ldy, G, k)
                          : gemm_args(k, k, m, OP_N, OP_C, Y, ldy, Y, ldy, G, k);
   g.sA = sY; g.sB = sY; g.sC = (long long)k * k; g.batch = batch;
+  g.kws = kws; g.kws_bytes = kws_bytes;
   return gemm(dt, PREC_FP64, g, s);
 }
 
@@ -680,10 +681,10 @@ __global__ void first_order_factor_kernel(T* G, int k) {
 }
 
 hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
-                        double* part, double* out, int batch, hipStream_t s) {
+                        double* part, double* out, int batch, hipStream_t s, void* kws, size_t kws_bytes) {
   if (k <= 0 || m <= 0 || batch <= 0) return hipErrorInvalidValue;
   if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
-  hipError_t e = gram_into(dtype, mode, Y, ldy, sY, m, k, G, batch, s);
+  hipError_t e = gram_into(dtype, mode, Y, ldy, sY, m, k, G, batch, s, kws, kws_bytes);
   if (e != hipSuccess) return e;
   const int np = ORTHO_DEFECT_PARTS;
   if (dtype == C128)
@@ -695,7 +696,7 @@ hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long 
 }
 
 hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
-                                      void* G, void* X, int batch, hipStream_t s) {
+                                      void* G, void* X, int batch, hipStream_t s, void* kws, size_t kws_bytes) {
   if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
   const unsigned gx = (unsigned)std::min<long long>(1024, ((long long)k * k + 255) / 256);
   if (dtype == C128)
@@ -711,6 +712,7 @@ hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long l
   g.sB = mode == 0 ? (long long)k * k : sY;
   g.sC = sY; g.batch = batch;
   g.alpha_re = -1.0; g.beta_re = 1.0;
+  g.kws = kws; g.kws_bytes = kws_bytes;
   return gemm(dtype, PREC_FP64, g, s);
 }
 
@@ -724,7 +726,7 @@ static hipError_t cholqr_impl(int mode, void* Y, long long ldy, long long sY, in
   const long long ldg = k, sG = (long long)k * k;
   hipError_t err = hipSuccess;
   if (!have_gram) {
-    err = gram_into(dt, mode, Y, ldy, sY, m, k, G, batch, s);
+    err = gram_into(dt, mode, Y, ldy, sY, m, k, G, batch, s, w.kws, w.kws_bytes);
     if (err != hipSuccess) return err;
   }
   hipLaunchKernelGGL(diag_copy_kernel<T>, dim3((k + 255) / 256, batch), dim3(256), 0, s, (const T*)G, ldg, sG,
@@ -755,44 +757,66 @@ static hipError_t cholqr_impl(int mode, void* Y, long long ldy, long long sY, in
       if (err != hipSuccess) return err;
     }
   }
-  // triangular solve, block by block; Y is consumed as workspace
+  // triangular solve, block by block; Y is consumed as workspace.  The
+  // updates from earlier blocks are applied per TS_OUTER rows (columns) in one
+  // product of full-height tiles, then per CB block from inside the outer block.
+  constexpr int TS_OUTER = 128;
   char* Yc = reinterpret_cast<char*>(Y);
   char* Qc = reinterpret_cast<char*>(Q);
-  for (int ib = 0; ib < nblk; ++ib) {
-    const int jb = ib * CB, cb = std::min(CB, k - jb);
-    if (mode == 0) {
-      if (jb > 0) {
-        // Y(:, jb) -= Q(:, :jb) R(:jb, jb)
-        GemmArgs a1 = gemm_args(m, cb, jb, OP_N, OP_N, Qc, ldq, G + (long long)jb * es, ldg, Yc + (long long)jb * es, ldy);
-        a1.sA = sQ; a1.sB = sG; a1.sC = sY; a1.batch = batch;
-        a1.alpha_re = -1.0; a1.beta_re = 1.0;
-        err = gemm(dt, PREC_FP64, a1, s);
+  for (int ob = 0; ob < k; ob += TS_OUTER) {
+    const int ocb = std::min(TS_OUTER, k - ob);
+    if (ob > 0) {
+      GemmArgs o = mode == 0
+          // Y(:, ob:ob+ocb) -= Q(:, :ob) R(:ob, ob:ob+ocb)
+          ? gemm_args(m, ocb, ob, OP_N, OP_N, Qc, ldq, G + (long long)ob * es, ldg, Yc + (long long)ob * es, ldy)
+          // X(ob:ob+ocb, :) -= R(:ob, ob:ob+ocb)^H Q(:ob, :)
+          : gemm_args(ocb, m, ob, OP_C, OP_N, G + (long long)ob * es, ldg, Qc, ldq,
+                      Yc + (long long)ob * ldy * es, ldy);
+      o.sA = mode == 0 ? sQ : sG;
+      o.sB = mode == 0 ? sG : sQ;
+      o.sC = sY; o.batch = batch;
+      o.alpha_re = -1.0; o.beta_re = 1.0;
+      o.kws = w.kws; o.kws_bytes = w.kws_bytes;
+      err = gemm(dt, PREC_FP64, o, s);
+      if (err != hipSuccess) return err;
+    }
+    for (int jb = ob; jb < ob + ocb; jb += CB) {
+      const int ib = jb / CB, cb = std::min(CB, k - jb), kin = jb - ob;
+      if (mode == 0) {
+        if (kin > 0) {
+          // Y(:, jb) -= Q(:, ob:jb) R(ob:jb, jb)
+          GemmArgs a1 = gemm_args(m, cb, kin, OP_N, OP_N, Qc + (long long)ob * es, ldq,
+                                  G + ((long long)ob * ldg + jb) * es, ldg, Yc + (long long)jb * es, ldy);
+          a1.sA = sQ; a1.sB = sG; a1.sC = sY; a1.batch = batch;
+          a1.alpha_re = -1.0; a1.beta_re = 1.0;
+          err = gemm(dt, PREC_FP64, a1, s);
+          if (err != hipSuccess) return err;
+        }
+        // Q(:, jb) = Y(:, jb) Rjj^-1, dropped columns zeroed
+        GemmArgs a2 = gemm_args(m, cb, cb, OP_N, OP_N, Yc + (long long)jb * es, ldy, RI + (size_t)ib * CB * CB * es,
+                                CB, Qc + (long long)jb * es, ldq);
+        a2.sA = sY; a2.sB = sRI; a2.sC = sQ; a2.batch = batch;
+        a2.cs = w.mask + jb; a2.s_cs = k;
+        err = gemm(dt, PREC_FP64, a2, s);
+        if (err != hipSuccess) return err;
+      } else {
+        if (kin > 0) {
+          // X(jb, :) -= R(ob:jb, jb)^H Q(ob:jb, :)
+          GemmArgs a1 = gemm_args(cb, m, kin, OP_C, OP_N, G + ((long long)ob * ldg + jb) * es, ldg,
+                                  Qc + (long long)ob * ldq * es, ldq, Yc + (long long)jb * ldy * es, ldy);
+          a1.sA = sG; a1.sB = sQ; a1.sC = sY; a1.batch = batch;
+          a1.alpha_re = -1.0; a1.beta_re = 1.0;
+          err = gemm(dt, PREC_FP64, a1, s);
+          if (err != hipSuccess) return err;
+        }
+        // Q(jb, :) = Rjj^-H X(jb, :), dropped rows zeroed
+        GemmArgs a2 = gemm_args(cb, m, cb, OP_C, OP_N, RI + (size_t)ib * CB * CB * es, CB,
+                                Yc + (long long)jb * ldy * es, ldy, Qc + (long long)jb * ldq * es, ldq);
+        a2.sA = sRI; a2.sB = sY; a2.sC = sQ; a2.batch = batch;
+        a2.rs = w.mask + jb; a2.s_rs = k;
+        err = gemm(dt, PREC_FP64, a2, s);
         if (err != hipSuccess) return err;
       }
-      // Q(:, jb) = Y(:, jb) Rjj^-1, dropped columns zeroed
-      GemmArgs a2 = gemm_args(m, cb, cb, OP_N, OP_N, Yc + (long long)jb * es, ldy, RI + (size_t)ib * CB * CB * es, CB,
-                              Qc + (long long)jb * es, ldq);
-      a2.sA = sY; a2.sB = sRI; a2.sC = sQ; a2.batch = batch;
-      a2.cs = w.mask + jb; a2.s_cs = k;
-      err = gemm(dt, PREC_FP64, a2, s);
-      if (err != hipSuccess) return err;
-    } else {
-      if (jb > 0) {
-        // X(jb, :) -= R(:jb, jb)^H Q(:jb, :)
-        GemmArgs a1 = gemm_args(cb, m, jb, OP_C, OP_N, G + (long long)jb * es, ldg, Qc, ldq,
-                                Yc + (long long)jb * ldy * es, ldy);
-        a1.sA = sG; a1.sB = sQ; a1.sC = sY; a1.batch = batch;
-        a1.alpha_re = -1.0; a1.beta_re = 1.0;
-        err = gemm(dt, PREC_FP64, a1, s);
-        if (err != hipSuccess) return err;
-      }
-      // Q(jb, :) = Rjj^-H X(jb, :), dropped rows zeroed
-      GemmArgs a2 = gemm_args(cb, m, cb, OP_C, OP_N, RI + (size_t)ib * CB * CB * es, CB,
-                              Yc + (long long)jb * ldy * es, ldy, Qc + (long long)jb * ldq * es, ldq);
-      a2.sA = sRI; a2.sB = sY; a2.sC = sQ; a2.batch = batch;
-      a2.rs = w.mask + jb; a2.s_rs = k;
-      err = gemm(dt, PREC_FP64, a2, s);
-      if (err != hipSuccess) return err;
     }
   }
   return hipGetLastError();

@@ -18,6 +18,8 @@ struct CholWork {
   void* RI;       // batch * nblk * 32 * 32 elements
   double* diag0;  // batch * k
   double* mask;   // batch * k
+  void* kws;      // optional split-K scratch of the products (null: none)
+  size_t kws_bytes;
 };
 size_t cholqr_work_elems(int k);  // G + RI elements per problem
 
@@ -63,12 +65,14 @@ hipError_t cholqr(int dtype, int mode, void* Y, long long ldy, long long sY, int
 // non-zero vectors (part: batch * ORTHO_DEFECT_PARTS doubles).  C128 / F64.
 constexpr int ORTHO_DEFECT_PARTS = 64;
 hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k, void* G,
-                        double* part, double* out, int batch, hipStream_t s);
+                        double* part, double* out, int batch, hipStream_t s, void* kws = nullptr,
+                        size_t kws_bytes = 0);
 // Cholesky QR to first order for G = I + E with small E: R = I + M + O(E^2)
 // with M = strict upper triangle of E + diag(E) / 2, so that
 // X = Y - Y M (mode 0) or X = Y - M^H Y (mode 1).  G (from ortho_defect) is
 // overwritten by M; X must hold a copy of Y on entry and must not alias it.
 hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
-                                      void* G, void* X, int batch, hipStream_t s);
+                                      void* G, void* X, int batch, hipStream_t s, void* kws = nullptr,
+                                      size_t kws_bytes = 0);
 
 }  // namespace tci

@@ -35,7 +35,8 @@ namespace tci {
   type* ptr = static_cast<type*>(ctx->arena.get(sizeof(type) * (size_t)(count)));      \
   if (!ptr) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace allocation failed: " #ptr)
 
-static tci_status ortho2(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb) {
+static tci_status ortho2(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb,
+                             void* kws) {
   const size_t es = elem_bytes(wdt);
   void* tmp = ctx->arena.get(es * (size_t)sX * nb);
   CholWork w{};
@@ -44,6 +45,8 @@ static tci_status ortho2(tci_context ctx, int wdt, void* X, long long ld, long l
   w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   if (!tmp || !w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
   w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
+  w.kws = kws;
+  w.kws_bytes = kws ? GEMM_SPLITK_WS_BYTES : 0;
   TCI_CHECK_HIP(cholqr(wdt, 0, X, ld, sX, m, k, tmp, ld, sX, w, 1e-12, nb, ctx->stream));
   TCI_CHECK_HIP(cholqr(wdt, 0, tmp, ld, sX, m, k, X, ld, sX, w, 1e-12, nb, ctx->stream));
   return TCI_OK;
@@ -53,7 +56,8 @@ static tci_status ortho2(tci_context ctx, int wdt, void* X, long long ld, long l
 // where the block only has to stay well conditioned (orthogonality error
 // about u cond(X)^2); the range that the last step hands on is
 // orthonormalised by ortho2.
-static tci_status ortho1(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb) {
+static tci_status ortho1(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb,
+                             void* kws) {
   const size_t es = elem_bytes(wdt);
   void* tmp = ctx->arena.get(es * (size_t)sX * nb);
   CholWork w{};
@@ -62,12 +66,15 @@ static tci_status ortho1(tci_context ctx, int wdt, void* X, long long ld, long l
   w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   if (!tmp || !w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
   w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
+  w.kws = kws;
+  w.kws_bytes = kws ? GEMM_SPLITK_WS_BYTES : 0;
   TCI_CHECK_HIP(cholqr(wdt, 0, X, ld, sX, m, k, tmp, ld, sX, w, 1e-12, nb, ctx->stream));
   TCI_CHECK_HIP(hipMemcpyAsync(X, tmp, es * (size_t)sX * nb, hipMemcpyDeviceToDevice, ctx->stream));
   return TCI_OK;
 }
 
-static tci_status row_ortho2(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb) {
+static tci_status row_ortho2(tci_context ctx, int wdt, void* X, long long ld, long long sX, int m, int k, int nb,
+                             void* kws) {
   const size_t es = elem_bytes(wdt);
   void* tmp = ctx->arena.get(es * (size_t)sX * nb);
   CholWork w{};
@@ -76,6 +83,8 @@ static tci_status row_ortho2(tci_context ctx, int wdt, void* X, long long ld, lo
   w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   if (!tmp || !w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
   w.RI = static_cast<char*>(w.G) + es * (size_t)k * k * nb;
+  w.kws = kws;
+  w.kws_bytes = kws ? GEMM_SPLITK_WS_BYTES : 0;
   TCI_CHECK_HIP(cholqr(wdt, 1, X, ld, sX, m, k, tmp, ld, sX, w, 1e-12, nb, ctx->stream));
   TCI_CHECK_HIP(cholqr(wdt, 1, tmp, ld, sX, m, k, X, ld, sX, w, 1e-12, nb, ctx->stream));
   return TCI_OK;
@@ -106,6 +115,7 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   SK_ARENA(total, double, nb);
   SK_ARENA(partial, double, (size_t)nb * SUMSQ_PARTIALS);
   TCI_CHECK_HIP(sumsq_batched(wdt, th64, smn, smn, total, partial, nb, s));
+  SK_ARENA(kws, char, GEMM_SPLITK_WS_BYTES);   // split-K scratch of the FP64 products
   SK_ARENA(kdev, int, nb);
   SK_ARENA(sdev, uint32_t, nb);
   std::vector<int> kc(nb);
@@ -126,8 +136,8 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     TCI_CHECK_HIP(gemm(dt_lo, prec, g, s));
   }
   TCI_CHECK_HIP(w_from(Ylo, Y64, sY * nb));
-  if (q > 0) TCI_TRY(ortho1(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
-  else TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
+  if (q > 0) TCI_TRY(ortho1(ctx, wdt, Y64, kmax, sY, m, kmax, nb, kws));
+  else TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb, kws));
   // Power iterations in the contraction precision; the last product with
   // theta, and B = Q^H theta, in FP64 so that the Rayleigh-Ritz step sees the
   // sketched subspace without the rounding of the mixed products.
@@ -137,19 +147,20 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     g1.sA = smn; g1.sB = sY; g1.sC = sZ; g1.batch = nb;
     TCI_CHECK_HIP(gemm(dt_lo, prec, g1, s));
     TCI_CHECK_HIP(w_from(Zlo, Z64, sZ * nb));
-    TCI_TRY(ortho1(ctx, wdt, Z64, kmax, sZ, n, kmax, nb));
+    TCI_TRY(ortho1(ctx, wdt, Z64, kmax, sZ, n, kmax, nb, kws));
     if (it + 1 < q) {
       TCI_CHECK_HIP(lo_from(Z64, Zlo, sZ * nb));
       GemmArgs g2 = gemm_args(m, kmax, n, OP_N, OP_N, th_lo, n, Zlo, kmax, Ylo, kmax);
       g2.sA = smn; g2.sB = sZ; g2.sC = sY; g2.batch = nb;
       TCI_CHECK_HIP(gemm(dt_lo, prec, g2, s));
       TCI_CHECK_HIP(w_from(Ylo, Y64, sY * nb));
-      TCI_TRY(ortho1(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
+      TCI_TRY(ortho1(ctx, wdt, Y64, kmax, sY, m, kmax, nb, kws));
     } else {
       GemmArgs g2 = gemm_args(m, kmax, n, OP_N, OP_N, th64, n, Z64, kmax, Y64, kmax);
       g2.sA = smn; g2.sB = sZ; g2.sC = sY; g2.batch = nb;
+      g2.kws = kws; g2.kws_bytes = GEMM_SPLITK_WS_BYTES;
       TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g2, s));
-      TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb));
+      TCI_TRY(ortho2(ctx, wdt, Y64, kmax, sY, m, kmax, nb, kws));
     }
   }
   // B = Q^H theta (FP64), Gram B B^H (FP64)
@@ -158,6 +169,7 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   {
     GemmArgs g = gemm_args(kmax, n, m, OP_C, OP_N, Y64, kmax, th64, n, B64, n);
     g.sA = sY; g.sB = smn; g.sC = sB; g.batch = nb;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   const long long sG = (long long)kmax * kmax;
@@ -165,6 +177,7 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   {
     GemmArgs g = gemm_args(kmax, kmax, n, OP_N, OP_C, B64, n, B64, n, Gk, kmax);
     g.sA = sB; g.sB = sB; g.sC = sG; g.batch = nb;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   // small FP64 eigensolve
@@ -217,6 +230,8 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)kz * nb));
     if (!w.G || !w.diag0 || !w.mask) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
     w.RI = static_cast<char*>(w.G) + sizeof(double) * (size_t)kz * kz * nb;
+    w.kws = kws;
+    w.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(cholqr(F64, 0, Zr, kz, sW, ng, kz, Zr2, kz, sW, w, 1e-12, nb, s));
     TCI_CHECK_HIP(cholqr(F64, 0, Zr2, kz, sW, ng, kz, Zr, kz, sW, w, 1e-12, nb, s));
   }
@@ -228,7 +243,7 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   }
   const size_t tfe = tridiag_backtransform_tf_elems(ng);
   SK_ARENA(Tf, char, ew * tfe * nb);
-  SK_ARENA(btw, char, ew * tridiag_backtransform_work_elems(kz) * nb);
+  SK_ARENA(btw, char, tridiag_backtransform_work_bytes(wdt, kz, nb));
   TCI_CHECK_HIP(tridiag_backtransform(wdt, ta, Tf, (long long)tfe, Wv, kz, sW, kz, btw, nb, s));
   // U = Q W, gauge, V^H = diag(1/s) U^H theta (rows re-orthonormalised)
   const long long sU = (long long)m * kz, sV = (long long)kz * n;
@@ -239,6 +254,7 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
   {
     GemmArgs g = gemm_args(m, kz, kmax, OP_N, OP_N, Y64, kmax, Wv, kz, U, kz);
     g.sA = sY; g.sB = sW; g.sC = sU; g.batch = nb;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   TCI_CHECK_HIP(gauge_columns(wdt, U, kz, sU, m, kz, chi, nb, s));
@@ -246,13 +262,15 @@ tci_status sketch_run(tci_context ctx, int dt_lo, int wdt, int prec, int nb, int
     GemmArgs g = gemm_args(kz, n, m, OP_C, OP_N, U, kz, th64, n, Vh, n);
     g.sA = sU; g.sB = smn; g.sC = sV; g.batch = nb;
     g.rs = sinv; g.s_rs = kk;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
-  TCI_TRY(row_ortho2(ctx, wdt, Vh, n, sV, n, kz, nb));
+  TCI_TRY(row_ortho2(ctx, wdt, Vh, n, sV, n, kz, nb, kws));
   // residual certificate: P = theta V, r_j = || P_j - s_j U_j ||
   {
     GemmArgs g = gemm_args(m, kz, n, OP_N, OP_C, th64, n, Vh, n, P, kz);
     g.sA = smn; g.sB = sV; g.sC = sU; g.batch = nb;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   SK_ARENA(rr, double, (size_t)kk * nb);

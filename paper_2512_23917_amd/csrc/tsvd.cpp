@@ -63,10 +63,12 @@ static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long
   w.diag0 = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   w.mask = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)k * nb));
   double* part = static_cast<double*>(ctx->arena.get(sizeof(double) * ((size_t)nb * ORTHO_DEFECT_PARTS + 1)));
-  if (!w.G || !w.diag0 || !w.mask || !part) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
+  w.kws = ctx->arena.get(GEMM_SPLITK_WS_BYTES);
+  w.kws_bytes = GEMM_SPLITK_WS_BYTES;
+  if (!w.G || !w.diag0 || !w.mask || !part || !w.kws) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
   double* dout = part + (size_t)nb * ORTHO_DEFECT_PARTS;
   auto defect = [&](const void* Y, double& d) -> tci_status {
-    TCI_CHECK_HIP(ortho_defect(wdt, mode, Y, ldx, sX, m, k, w.G, part, dout, nb, s));
+    TCI_CHECK_HIP(ortho_defect(wdt, mode, Y, ldx, sX, m, k, w.G, part, dout, nb, s, w.kws, w.kws_bytes));
     TCI_CHECK_HIP(hipMemcpyAsync(&d, dout, sizeof(double), hipMemcpyDeviceToHost, s));
     TCI_CHECK_HIP(hipStreamSynchronize(s));
     return TCI_OK;
@@ -74,14 +76,14 @@ static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long
   // first-order step from Y (Gram in w.G) into X
   auto finish = [&](const void* Y) -> tci_status {
     TCI_CHECK_HIP(hipMemcpyAsync(X, Y, bytes, hipMemcpyDeviceToDevice, s));
-    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, Y, ldx, sX, m, k, w.G, X, nb, s));
+    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, Y, ldx, sX, m, k, w.G, X, nb, s, w.kws, w.kws_bytes));
     return TCI_OK;
   };
   double d = 0.0;
   TCI_TRY(defect(X, d));
   if (d <= FIRST_ORDER_DEFECT2) {   // X already holds the copy the step updates
     TCI_CHECK_HIP(hipMemcpyAsync(tmp, X, bytes, hipMemcpyDeviceToDevice, s));
-    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, tmp, ldx, sX, m, k, w.G, X, nb, s));
+    TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, tmp, ldx, sX, m, k, w.G, X, nb, s, w.kws, w.kws_bytes));
     return TCI_OK;
   }
   TCI_CHECK_HIP(cholqr(wdt, mode, X, ldx, sX, m, k, tmp, ldx, sX, w, CHOL_DROP_TAU, nb, s, true));
@@ -132,7 +134,7 @@ tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const vo
   ta.G = Gm; ta.ldg = ng; ta.sG = sG;
   ta.d = d; ta.e = e; ta.sde = ng;
   ta.tau = tau; ta.stau = ng;
-  ta.Vt = Vt; ta.sVt = sG;
+  ta.Vt = Vt; ta.sVt = (long long)ng * ng;
   ta.Wp = Wp; ta.sWp = (long long)ng * TRIDIAG_NB;
   ta.y = y; ta.sy = ng;
   ta.sws = (long long)tridiag_ws_bytes(wdt, ng);
@@ -152,7 +154,7 @@ tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const vo
 }
 
 tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, int kz, const double* sinv,
-                        TsvdOut& out) {
+                        TsvdOut& out, double* Zin) {
   hipStream_t s = ctx->stream;
   const int wdt = st.wdt, nb = st.nb, m = st.m, n = st.n, ng = st.ng, kmax = st.kmax;
   const size_t es = elem_bytes(wdt);
@@ -161,12 +163,16 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
   const void* theta = st.theta;
   out.kz = kz;
   // eigenvectors of T (real), orthonormalised
-  ARENA(Z, double, (size_t)ng * kz * nb);
-  ARENA(Z2, double, (size_t)ng * kz * nb);
-  ARENA(iw, double, (size_t)4 * ng * kz * nb);
   const long long sZ = (long long)ng * kz;
-  TCI_CHECK_HIP(zero_fill(Z, sizeof(double) * (size_t)sZ * nb, s));
-  TCI_CHECK_HIP(tridiag_invit(st.d, st.e, ng, ng, st.lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
+  double* Z = Zin;
+  if (!Z) {
+    Z = static_cast<double*>(ctx->arena.get(sizeof(double) * (size_t)sZ * nb));
+    ARENA(iw, double, (size_t)4 * ng * kz * nb);
+    if (!Z) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+    TCI_CHECK_HIP(zero_fill(Z, sizeof(double) * (size_t)sZ * nb, s));
+    TCI_CHECK_HIP(tridiag_invit(st.d, st.e, ng, ng, st.lam, kmax, chi, kz, Z, kz, sZ, iw, nb, s));
+  }
+  ARENA(Z2, double, (size_t)ng * kz * nb);
   {
     ProfTag tag("svd_zqr");
     TCI_TRY(cholqr2(ctx, F64, 0, Z, kz, sZ, ng, kz, Z2, nb));
@@ -182,7 +188,8 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
   }
   const size_t tfe = tridiag_backtransform_tf_elems(ng);
   ARENA(Tf, char, es * tfe * nb);
-  ARENA(btw, char, es * tridiag_backtransform_work_elems(kz) * nb);
+  ARENA(btw, char, tridiag_backtransform_work_bytes(wdt, kz, nb));
+  ARENA(kws, char, GEMM_SPLITK_WS_BYTES);
   {
     ProfTag tag("svd_backtr");
     TCI_CHECK_HIP(tridiag_backtransform(wdt, st.ta, Tf, (long long)tfe, Ev, kz, sZ, kz, btw, nb, s));
@@ -201,6 +208,7 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
     GemmArgs g = gemm_args(m, kz, n, OP_N, OP_N, theta, n, Ev, kz, U, kz);
     g.sA = smn; g.sB = sZ; g.sC = sU; g.batch = nb;
     g.cs = sinv; g.s_cs = kmax;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
     TCI_TRY(cholqr2(ctx, wdt, 0, U, kz, sU, m, kz, Ut, nb));
   }
@@ -214,6 +222,7 @@ tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, in
     GemmArgs g = gemm_args(kz, n, m, OP_C, OP_N, U, kz, theta, n, Vh, n);
     g.sA = sU; g.sB = smn; g.sC = sV; g.batch = nb;
     g.rs = sinv; g.s_rs = kmax;
+    g.kws = kws; g.kws_bytes = GEMM_SPLITK_WS_BYTES;
     TCI_CHECK_HIP(gemm(wdt, PREC_FP64, g, s));
   }
   ProfTag tag_vqr("svd_vqr");
@@ -491,6 +500,19 @@ static tci_status tsvd_plain_finish(tci_context ctx, int dt, int wdt, int chil, 
   std::sort(ord.begin(), ord.end(), [&](int x, int y) { return chi_h[x] < chi_h[y] || (chi_h[x] == chi_h[y] && x < y); });
   const size_t es = elem_bytes(wdt);
   const long long smn = (long long)m * n, sG = (long long)ng * ng;
+  // Inverse iteration of every problem in one launch: its sequential
+  // recurrences make a launch latency-bound, whatever the number of vectors.
+  int kzall = 1;
+  for (int b = 0; b < nb; ++b) kzall = std::max(kzall, chi_h[b]);
+  const long long sZall = (long long)ng * kzall;
+  ARENA(Zall, double, (size_t)sZall * nb);
+  {
+    const std::vector<size_t> before = ctx->arena.used_state();
+    ARENA(iw, double, (size_t)4 * sZall * nb);
+    TCI_CHECK_HIP(zero_fill(Zall, sizeof(double) * (size_t)sZall * nb, s));
+    TCI_CHECK_HIP(tridiag_invit(st.d, st.e, ng, ng, st.lam, kmax, chi, kzall, Zall, kzall, sZall, iw, nb, s));
+    ctx->arena.restore(before);   // iw is dead once the stream has run the launches above
+  }
   for (int g0 = 0; g0 < nb;) {
     int g1 = g0 + 1;
     while (g1 < nb && 4 * chi_h[ord[g1]] <= 5 * chi_h[ord[g0]]) ++g1;
@@ -504,8 +526,17 @@ static tci_status tsvd_plain_finish(tci_context ctx, int dt, int wdt, int chil, 
     o.kmax = kmax;
     bool identity = ngp == nb;
     for (int i = 0; identity && i < ngp; ++i) identity = loc[i] == i;
+    // the group's eigenvectors of T: columns 0 .. kz of its problems' Zall
+    double* Zg = Zall;
+    if (!(identity && kz == kzall)) {
+      ARENA(zg, double, (size_t)ng * kz * ngp);
+      for (int i = 0; i < ngp; ++i)
+        TCI_CHECK_HIP(hipMemcpy2DAsync(zg + (size_t)ng * kz * i, sizeof(double) * kz, Zall + (size_t)sZall * loc[i],
+                                       sizeof(double) * kzall, sizeof(double) * kz, ng, hipMemcpyDeviceToDevice, s));
+      Zg = zg;
+    }
     if (identity) {
-      TCI_TRY(tsvd_vectors(ctx, st, chi, kz, sinv, o));
+      TCI_TRY(tsvd_vectors(ctx, st, chi, kz, sinv, o, Zg));
       o.chi = chi; o.s = sv; o.sn = sn; o.total = st.total;
     } else {
       TsvdStage sg = st;
@@ -529,7 +560,7 @@ static tci_status tsvd_plain_finish(tci_context ctx, int dt, int wdt, int chil, 
       const double* sinv_g = static_cast<const double*>(ptr);
       TCI_TRY(gather(ctx, F64, sn, kmax, loc, &ptr));
       double* sn_g = const_cast<double*>(static_cast<const double*>(ptr));
-      TCI_TRY(tsvd_vectors(ctx, sg, chi_g, kz, sinv_g, o));
+      TCI_TRY(tsvd_vectors(ctx, sg, chi_g, kz, sinv_g, o, Zg));
       o.chi = chi_g; o.sn = sn_g; o.s = nullptr;
     }
     std::vector<int> slots;
@@ -1026,7 +1057,7 @@ static tci_status eigh_core(tci_context ctx, tci_tensor a, int k_rows, tci_tenso
     }
     const size_t tfe = tridiag_backtransform_tf_elems(n);
     ARENA(Tf, char, es * tfe);
-    ARENA(btw, char, es * tridiag_backtransform_work_elems(n));
+    ARENA(btw, char, tridiag_backtransform_work_bytes(dt, n, 1));
     TCI_CHECK_HIP(tridiag_backtransform(dt, ta, Tf, (long long)tfe, Ev, n, 0, n, btw, 1, s));
     // ascending order: reverse the descending bisection order
     TCI_CHECK_HIP(reverse_columns(dt, Ev, n, n, n, s));

@@ -33,7 +33,10 @@ tci_status tsvd_run(tci_context ctx, int wdt, int nb, int m, int n, const void* 
 // block-sparse update truncates across sectors).  tsvd_eigvals: total weight,
 // Gram matrix, tridiagonal reduction and the kmax largest Gram eigenvalues
 // (descending, st.lam, stride kmax).  tsvd_vectors: for chi[b] <= kz kept
-// values with 1/s in sinv (stride kmax), U (m x kz) and V^H (kz x n).
+// values with 1/s in sinv (stride kmax), U (m x kz) and V^H (kz x n).  Zin
+// (optional, device, used as workspace): the tridiagonal eigenvectors of the
+// kept values, as tsvd_vectors would compute them (ng x kz per problem, ld
+// kz); null = compute them here.
 struct TsvdStage {
   int wdt = 0, nb = 0, m = 0, n = 0, ng = 0, kmax = 0;
   bool left = true;
@@ -44,7 +47,7 @@ struct TsvdStage {
 tci_status tsvd_eigvals(tci_context ctx, int wdt, int nb, int m, int n, const void* theta, int kmax,
                         TsvdStage& st);
 tci_status tsvd_vectors(tci_context ctx, const TsvdStage& st, const int* chi, int kz, const double* sinv,
-                        TsvdOut& out);
+                        TsvdOut& out, double* Zin = nullptr);
 
 }  // namespace tci
 

@@ -49,6 +49,11 @@ def cg(g, shape):
     ("ijk", "kjl", "li", dict(i=3, j=4, k=2, l=5)),
     ("ij", "ij", "", dict(i=13, j=7)),
     ("astb", "uvst", "auvb", dict(a=5, s=2, t=2, b=6, u=2, v=2)),
+    # long K over few output tiles: the FP64 kernels split K into chunks
+    ("ik", "kj", "ij", dict(i=64, k=4096, j=64)),    # one tile, 32 chunks
+    ("ki", "jk", "ij", dict(i=37, k=1000, j=70)),    # ragged chunks, both transposed
+    ("ik", "kj", "ij", dict(i=300, k=300, j=20)),    # two chunks
+    ("ij", "ij", "", dict(i=100, j=50)),             # full contraction, K = 5000
 ])
 def test_contract_fp64_matches_oracle(T, ctx, dtype, case):
     la, lb, lc, dims = case
