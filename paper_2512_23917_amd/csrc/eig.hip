@@ -587,23 +587,29 @@ __global__ void e2_kernel(const double* e, double* e2, long long sde, int n, int
   e2[b * sde + i] = v * v;
 }
 
-// Bisection, one lane per wanted eigenvalue (64 per wave): lane j halves its
-// own interval [lo, hi] (count(lo) <= t < count(hi), t the ascending index)
-// until it is at rounding level relative to the eigenvalue itself.  Small
-// eigenvalues are resolved to that relative accuracy (more steps than the
-// absolute accuracy of the norm would need) because inverse iteration with
-// shifts only absolutely accurate leaves the vectors of closely spaced small
-// eigenvalues far from orthogonal, which costs a second Cholesky-QR pass.  All lanes walk the same Sturm recurrence
-// over i at their own shift, so the loop is uniform and d, e^2 are read at
-// the same address by every lane.  One evaluation per step and eigenvalue
-// keeps the arithmetic 10x below a 64-point multisection per eigenvalue; the
-// many independent lanes hide the latency of the division chain.
+// Multisection, BIS_L lanes per wanted eigenvalue (64 / BIS_L per wave):
+// the lanes of eigenvalue j evaluate the Sturm count at the BIS_L interior
+// points that cut its interval [lo, hi] (count(lo) <= t < count(hi), t the
+// ascending index) into BIS_L + 1 equal parts, and all of them move to the
+// part whose ends keep that invariant (the first point whose count exceeds t
+// and the point before it), until the interval is at rounding level
+// relative to the eigenvalue itself.  Small eigenvalues are resolved to that
+// relative accuracy (more steps than the absolute accuracy of the norm would
+// need) because inverse iteration with shifts only absolutely accurate
+// leaves the vectors of closely spaced small eigenvalues far from
+// orthogonal, which costs a second Cholesky-QR pass.  One lane per
+// eigenvalue leaves one wave per SIMD on a 64 x 1024 batch, bound by the
+// latency of the recurrence's division chain; BIS_L = 4 gives four waves per
+// SIMD to interleave and needs about half the rounds (log2 5 bits each).
+constexpr int BIS_L = 4;
+
 __global__ __launch_bounds__(64) void bisect_kernel(const double* d, const double* e, const double* e2,
                                                     long long sde, int n, int kmax, double* lam, long long slam,
                                                     int batch) {
   const int b = blockIdx.y;
   const int lane = threadIdx.x;
-  const int j = blockIdx.x * 64 + lane;
+  const int sub = lane & (BIS_L - 1);
+  const int j = blockIdx.x * (64 / BIS_L) + lane / BIS_L;
   if (b >= batch) return;
   const double* db = d + b * sde;
   const double* eb = e + b * sde;
@@ -624,18 +630,27 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* d, const doubl
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) * 64.0;
   lo -= 4.0 * 2.220446049250313e-16 * scale + pivmin;
   hi += 4.0 * 2.220446049250313e-16 * scale + pivmin;
-  const int t = n - 1 - min(j, kmax - 1);  // ascending index of this lane's eigenvalue
+  const int t = n - 1 - min(j, kmax - 1);  // ascending index of this lane group's eigenvalue
+  const int q0 = lane & ~(BIS_L - 1);      // first lane of the group
   for (int it = 0; it < 128; ++it) {
     const bool done = hi - lo <= 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin;
     if (__ballot(!done) == 0ull) break;
-    const double x = 0.5 * (lo + hi);
+    const double w = (hi - lo) / (BIS_L + 1);
+    const double x = lo + w * (sub + 1);
     const bool below = sturm_count(db, e2b, n, x, pivmin) <= t;
-    if (!done && x > lo && x < hi) {
-      if (below) lo = x;
-      else hi = x;
+    // the group's flags (bit s: count at point s <= t); c = leading points below
+    const unsigned flags = (unsigned)(__ballot(below) >> q0) & ((1u << BIS_L) - 1);
+    const int c = __builtin_ctz(~flags);
+    if (!done) {
+      const double nlo = c > 0 ? lo + w * c : lo;
+      const double nhi = c < BIS_L ? lo + w * (c + 1) : hi;
+      if (nlo >= lo && nhi <= hi && nlo < nhi) {
+        lo = nlo;
+        hi = nhi;
+      }
     }
   }
-  if (j < kmax) lam[b * slam + j] = 0.5 * (lo + hi);
+  if (sub == 0 && j < kmax) lam[b * slam + j] = 0.5 * (lo + hi);
 }
 
 hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, long long sde, int n,
@@ -643,8 +658,8 @@ hipError_t tridiag_eigvals_top(const double* d, const double* e, double* e2, lon
   if (kmax <= 0 || batch <= 0) return hipSuccess;
   const long tot = (long)batch * n;
   hipLaunchKernelGGL(e2_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, e, e2, sde, n, batch);
-  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 63) / 64, batch), dim3(64), 0, s, d, e, e2, sde, n, kmax, lam,
-                     slam, batch);
+  hipLaunchKernelGGL(bisect_kernel, dim3((kmax + 64 / BIS_L - 1) / (64 / BIS_L), batch), dim3(64), 0, s, d, e, e2,
+                     sde, n, kmax, lam, slam, batch);
   return hipGetLastError();
 }
 

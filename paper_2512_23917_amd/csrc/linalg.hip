@@ -695,6 +695,25 @@ hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long 
   return hipGetLastError();
 }
 
+// G <- C = M + N - M M (upper triangular), with M from first_order_factor_kernel
+// in G, P = M^H M and S = M M: N = -(strict upper triangle of P + diag(P) / 2)
+// is the second-order term of the Cholesky factor, R = I + M + N + O(E^3),
+// and R^-1 = I - C + O(E^3).
+template <typename T>
+__global__ void second_order_factor_kernel(T* G, const T* P, const T* S, int k) {
+  const long long off = (long long)blockIdx.y * k * k;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)k * k; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    if (i > j) continue;
+    double mr, mi, pr, pi, sr, si;
+    ld2(G + off, e, mr, mi);
+    ld2(P + off, e, pr, pi);
+    ld2(S + off, e, sr, si);
+    if (i == j) { pr *= 0.5; pi = 0.0; }
+    st2(G + off, e, mr - pr - sr, mi - pi - si);
+  }
+}
+
 hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
                                       void* G, void* X, int batch, hipStream_t s, void* kws, size_t kws_bytes) {
   if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
@@ -710,6 +729,48 @@ hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long l
                          : gemm_args(k, m, k, OP_C, OP_N, G, k, Y, ldy, X, ldy);
   g.sA = mode == 0 ? sY : (long long)k * k;
   g.sB = mode == 0 ? (long long)k * k : sY;
+  g.sC = sY; g.batch = batch;
+  g.alpha_re = -1.0; g.beta_re = 1.0;
+  g.kws = kws; g.kws_bytes = kws_bytes;
+  return gemm(dtype, PREC_FP64, g, s);
+}
+
+hipError_t second_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m,
+                                       int k, void* G, void* PS, void* X, int batch, hipStream_t s, void* kws,
+                                       size_t kws_bytes) {
+  if (k <= 0 || m <= 0 || batch <= 0) return hipSuccess;
+  if (dtype != C128 && dtype != F64) return hipErrorInvalidValue;
+  const size_t es = dtype == C128 ? 16 : 8;
+  const long long kk = (long long)k * k;
+  const unsigned gx = (unsigned)std::min<long long>(1024, (kk + 255) / 256);
+  if (dtype == C128)
+    hipLaunchKernelGGL(first_order_factor_kernel<cd>, dim3(gx, batch), dim3(256), 0, s, (cd*)G, k);
+  else
+    hipLaunchKernelGGL(first_order_factor_kernel<double>, dim3(gx, batch), dim3(256), 0, s, (double*)G, k);
+  char* P = static_cast<char*>(PS);
+  char* S = P + es * (size_t)kk * batch;
+  // P = M^H M, S = M M
+  GemmArgs gp = gemm_args(k, k, k, OP_C, OP_N, G, k, G, k, P, k);
+  gp.sA = kk; gp.sB = kk; gp.sC = kk; gp.batch = batch;
+  gp.kws = kws; gp.kws_bytes = kws_bytes;
+  hipError_t e = gemm(dtype, PREC_FP64, gp, s);
+  if (e != hipSuccess) return e;
+  GemmArgs gs = gemm_args(k, k, k, OP_N, OP_N, G, k, G, k, S, k);
+  gs.sA = kk; gs.sB = kk; gs.sC = kk; gs.batch = batch;
+  gs.kws = kws; gs.kws_bytes = kws_bytes;
+  e = gemm(dtype, PREC_FP64, gs, s);
+  if (e != hipSuccess) return e;
+  if (dtype == C128)
+    hipLaunchKernelGGL(second_order_factor_kernel<cd>, dim3(gx, batch), dim3(256), 0, s, (cd*)G, (const cd*)P,
+                       (const cd*)S, k);
+  else
+    hipLaunchKernelGGL(second_order_factor_kernel<double>, dim3(gx, batch), dim3(256), 0, s, (double*)G,
+                       (const double*)P, (const double*)S, k);
+  // column mode: X = Y - Y C; row mode: X = Y - C^H Y (X holds Y on entry)
+  GemmArgs g = mode == 0 ? gemm_args(m, k, k, OP_N, OP_N, Y, ldy, G, k, X, ldy)
+                         : gemm_args(k, m, k, OP_C, OP_N, G, k, Y, ldy, X, ldy);
+  g.sA = mode == 0 ? sY : kk;
+  g.sB = mode == 0 ? kk : sY;
   g.sC = sY; g.batch = batch;
   g.alpha_re = -1.0; g.beta_re = 1.0;
   g.kws = kws; g.kws_bytes = kws_bytes;

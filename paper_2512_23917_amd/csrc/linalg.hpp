@@ -74,5 +74,12 @@ hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long 
 hipError_t first_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m, int k,
                                       void* G, void* X, int batch, hipStream_t s, void* kws = nullptr,
                                       size_t kws_bytes = 0);
+// The same to second order: R = I + M + N + O(E^3) with N = -(strict upper
+// triangle of M^H M + diag(M^H M) / 2), R^-1 = I - C + O(E^3), C = M + N - M M;
+// X = Y - Y C (mode 0) or Y - C^H Y (mode 1).  PS: workspace of 2 batch k x k
+// matrices.  Leaves an orthogonality defect of order ||E||^3.
+hipError_t second_order_orthonormalise(int dtype, int mode, const void* Y, long long ldy, long long sY, int m,
+                                       int k, void* G, void* PS, void* X, int batch, hipStream_t s,
+                                       void* kws = nullptr, size_t kws_bytes = 0);
 
 }  // namespace tci

@@ -44,6 +44,11 @@ static int work_dtype(int dt) { return dt == C64 ? C128 : dt == F32 ? F64 : dt; 
 // Squared Frobenius bound on ||G - I|| below which one first-order Cholesky-QR
 // step leaves an orthogonality defect of order ||G - I||^2, below rounding.
 static constexpr double FIRST_ORDER_DEFECT2 = 1e-16;
+// The same for one second-order step (defect of order ||G - I||^3): V^H =
+// diag(1/s) U^H theta arrives with squared defects of 1e-14 .. 1e-11 on
+// power-law bonds, which the second-order step takes in place of a full
+// Cholesky-QR pass and a first-order step.
+static constexpr double SECOND_ORDER_DEFECT2 = 1e-10;
 
 static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long ldx, long long sX, int m,
                           int k, void* tmp, int nb) {
@@ -84,6 +89,14 @@ static tci_status cholqr2(tci_context ctx, int wdt, int mode, void* X, long long
   if (d <= FIRST_ORDER_DEFECT2) {   // X already holds the copy the step updates
     TCI_CHECK_HIP(hipMemcpyAsync(tmp, X, bytes, hipMemcpyDeviceToDevice, s));
     TCI_CHECK_HIP(first_order_orthonormalise(wdt, mode, tmp, ldx, sX, m, k, w.G, X, nb, s, w.kws, w.kws_bytes));
+    return TCI_OK;
+  }
+  if (d <= SECOND_ORDER_DEFECT2) {
+    void* ps = ctx->arena.get(es * (size_t)k * k * nb * 2);
+    if (!ps) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "cholqr workspace");
+    TCI_CHECK_HIP(hipMemcpyAsync(tmp, X, bytes, hipMemcpyDeviceToDevice, s));
+    TCI_CHECK_HIP(second_order_orthonormalise(wdt, mode, tmp, ldx, sX, m, k, w.G, ps, X, nb, s, w.kws,
+                                              w.kws_bytes));
     return TCI_OK;
   }
   TCI_CHECK_HIP(cholqr(wdt, mode, X, ldx, sX, m, k, tmp, ldx, sX, w, CHOL_DROP_TAU, nb, s, true));

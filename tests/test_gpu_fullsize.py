@@ -255,3 +255,43 @@ def test_split_batch_of_64_matches_single_problems(T, ctx, dt):
         resid2 = np.linalg.norm(th - rec) ** 2
         assert resid2 == pytest.approx(inf[k].discarded_abs, rel=1e-6 if dt == "C128" else 1e-4)
         assert np.sum(sn ** 2) == pytest.approx(1.0, rel=1e-12)
+
+
+def test_headline_batch_learned_matches_plain_fp64(T, ctx):
+    """The headline batch (64 TEBD updates at chi = 1024, power-law bonds, Haar
+    gates) through the learned + mixed path, which reduces the problems the
+    network sends to the plain SVD on the second stream and sketches the
+    rest, against the plain FP64 path on the same inputs: kept singular
+    values at 1e-6 of s_1, chi under the threshold rule, and the truncated
+    reconstruction A'.B' at the mixed bar (1e-5)."""
+    import bench
+    from paper_2512_23917_amd import sketch_train
+    host = bench.headline_inputs(64, 1024)
+    ins_m = bench.upload_headline(T, ctx, host, T.C64)
+    ins_p = bench.upload_headline(T, ctx, host, T.C128)
+    model = T.SketchModel(ctx, path=sketch_train.DEFAULT_WEIGHTS)
+    pm = T.update_params(chi_min=1, chi_max=1024, target_trunc_err=1e-8, direction=T.DIR_RIGHT,
+                         precision=T.PREC_BF16X3, svd_mode=T.SVD_LEARNED, power_iters=2, seed=1)
+    pm.sketch_model = model.h.value
+    Am, sm, Bm, im = T.two_site_update_batched(ctx, *ins_m[:3], pm, prev_spectra=ins_m[3])
+    pp = T.update_params(chi_min=1, chi_max=1024, target_trunc_err=1e-8, direction=T.DIR_RIGHT,
+                         precision=T.PREC_FP64)
+    Ap, sp, Bp, ip = T.two_site_update_batched(ctx, *ins_p[:3], pp)
+    plain = sum(1 for i in im if i.sketch_rank == 0 or i.used_fallback)
+    print(f"learned batch: {plain} plain, {64 - plain} sketched", flush=True)
+    assert plain >= 12 and plain < 64          # the second-stream batch and the sketches both ran
+    for u in range(64):
+        i_m, i_p = im[u], ip[u]
+        s_p = sp[u].numpy()
+        kept_p = i_p.norm2 - i_p.discarded_abs
+        s_raw = s_p * math.sqrt(kept_p)
+        assert chi_allowed(i_m.chi, i_p.chi, s_raw, i_p.norm2, i_p.trunc_err, 1e-8, 1024), (u, i_m.chi, i_p.chi)
+        c = min(i_m.chi, i_p.chi)
+        s_m = sm[u].numpy()
+        assert np.abs(s_m[:c] - s_p[:c]).max() <= 1e-6 * s_p[0], u
+        am = Am[u].numpy().reshape(-1, i_m.chi)[:, :c].astype(np.complex128)
+        bm = Bm[u].numpy().reshape(i_m.chi, -1)[:c].astype(np.complex128)
+        ap = Ap[u].numpy().reshape(-1, i_p.chi)[:, :c]
+        bp = Bp[u].numpy().reshape(i_p.chi, -1)[:c]
+        assert rel_fro(am @ bm, ap @ bp) <= 1e-5, u
+    model.close()
