@@ -46,7 +46,8 @@ KERNEL_OF_CLASS = {  # kernel that carries each profiling class
     "hemv": ("tri_colC_kernel<cd,32>", "paper_2512_23917_amd/csrc/eig.hip"),
 }
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
-                 ("traffic_gemm_planes_c64_chi1024.txt", "traffic_gemm_f64_c128_tebd_chi1024.txt")]
+                 ("traffic_gemm_planes_c64_chi1024.txt", "traffic_gemm_f64_c128_tebd_chi1024.txt",
+                  "traffic_hemv_c128_tebd_chi1024.txt")]
 
 PEAKS = {  # MI355X published dense peaks
     "c128_fp64": (78.6e12, "TFLOP/s", "mfma"),
