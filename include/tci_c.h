@@ -570,7 +570,14 @@ tci_status tci_heff_matvec_noalloc(tci_context ctx, tci_tensor L, tci_tensor W1,
  * Ritz value.  For F32/C64 operands the matvecs run in the context's mixed
  * precision.  The Krylov vectors are stored in FP64 (complex128), except for
  * C64 operands, where they are stored in complex64 (the operand precision of
- * their matvec) and combined in FP64.  Synchronous. */
+ * their matvec) and combined in FP64.  The Krylov scalars, the second-pass
+ * decision and the breakdown test (beta <= 1e-13 max|T|, after which the
+ * remaining steps do no work) stay on the device; the call waits for the
+ * device once, at its end, to return the energy.  TCI_ERR_NUMERIC when
+ * theta_inout has a zero or non-finite norm or the Ritz vector is not finite;
+ * theta_inout is then left unchanged.  At verbosity >= 1 the call's log line
+ * gives the order of T (krylov=), the number of second Gram-Schmidt passes
+ * (reorth=) and its host synchronisations (host_syncs=).  Synchronous. */
 tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_tensor W2,
                               tci_tensor R, tci_tensor theta_inout, int n_matvec, double* energy);
 

@@ -197,6 +197,132 @@ tci_status noalloc_scratch_init(int device) {
   return TCI_OK;
 }
 
+// Krylov state of the Lanczos solve, kept on the device so that the
+// recurrence runs without host round trips (doubles):
+//   [LZ_ALPHA, +32) alpha_j   [LZ_BETA, +32) beta_j
+//   LZ_TMAX  running max of |alpha| and beta (scale of the breakdown test)
+//   LZ_STOP  1 after an invariant subspace was found (later steps are void)
+//   LZ_M     number of recorded alpha (the order of T)
+//   LZ_FLAG  1 when the step needs the second Gram-Schmidt pass
+//   LZ_B2    ||w||^2 after the first pass, LZ_RB2 after the second
+//   LZ_SCALE complex factor of the next basis vector: 1/||theta|| for v_0,
+//            1/beta_j after step j (0 after a breakdown); at the end the
+//            phase and normalisation of psi
+//   LZ_NREORTH count of second passes
+//   LZ_START 1 when theta has a finite nonzero norm, LZ_VALID 1 when the
+//            Ritz vector is finite and nonzero (theta is written only then)
+enum {
+  LZ_ALPHA = 0, LZ_BETA = 32, LZ_TMAX = 64, LZ_STOP, LZ_M, LZ_FLAG, LZ_B2, LZ_RB2,
+  LZ_SCALE = 72, LZ_NREORTH = 74, LZ_START, LZ_VALID, LZ_WORDS = 80
+};
+
+// Clears the state and sets the factor that normalises the start vector
+// (zero when its squared norm n2 is zero or not finite).
+__global__ void lz_init_kernel(double* k, const double* n2) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < LZ_WORDS; ++i) k[i] = 0.0;
+  const double n0 = sqrt(*n2);
+  const bool ok = n0 > 0.0 && isfinite(n0);
+  k[LZ_START] = ok ? 1.0 : 0.0;
+  k[LZ_SCALE] = ok ? 1.0 / n0 : 0.0;
+}
+
+// After the first Gram-Schmidt pass of step j: record alpha_j = Re coef[0],
+// take ||w||^2 and the projections c = coef[128 ..) of the pass, and ask for
+// a second pass when it removed more than half of the norm, ||w||^2 < ||c||^2
+// (Daniel, Gragg, Kaufman and Stewart, 1976).
+__global__ void lz_decide_kernel(double* k, const double* coef, int j) {
+  if (threadIdx.x != 0) return;
+  if (k[LZ_STOP] != 0.0) {
+    k[LZ_FLAG] = 0.0;
+    return;
+  }
+  const double a = coef[0];
+  k[LZ_ALPHA + j] = a;
+  k[LZ_M] = j + 1;
+  k[LZ_TMAX] = fmax(k[LZ_TMAX], fabs(a));
+  const double* c1 = coef + 128;
+  double cn2 = 0.0;
+  for (int q = 0; q < 2 * (j + 1); ++q) cn2 += c1[q] * c1[q];
+  const double b2 = c1[2 * (j + 1)];
+  k[LZ_B2] = b2;
+  k[LZ_FLAG] = b2 < cn2 ? 1.0 : 0.0;
+}
+
+// beta_j = ||w|| after the passes; stop when it falls below 1e-13 of the
+// largest entry of T seen so far (the Krylov space is invariant).
+__global__ void lz_beta_kernel(double* k, int j) {
+  if (threadIdx.x != 0) return;
+  k[LZ_SCALE + 1] = 0.0;
+  if (k[LZ_STOP] != 0.0) {
+    k[LZ_SCALE] = 0.0;
+    return;
+  }
+  const bool second = k[LZ_FLAG] != 0.0;
+  if (second) k[LZ_NREORTH] += 1.0;
+  const double b = sqrt(second ? k[LZ_RB2] : k[LZ_B2]);
+  const double tmax = fmax(k[LZ_TMAX], b);
+  k[LZ_TMAX] = tmax;
+  if (b <= 1e-13 * tmax) {
+    k[LZ_STOP] = 1.0;
+    k[LZ_SCALE] = 0.0;
+  } else {
+    k[LZ_BETA + j] = b;
+    k[LZ_SCALE] = 1.0 / b;
+  }
+}
+
+// Last step: its residual enters neither T nor psi, only alpha_j is kept.
+__global__ void lz_last_kernel(double* k, const double* coef, int j) {
+  if (threadIdx.x != 0 || k[LZ_STOP] != 0.0) return;
+  const double a = coef[0];
+  k[LZ_ALPHA + j] = a;
+  k[LZ_M] = j + 1;
+  k[LZ_TMAX] = fmax(k[LZ_TMAX], fabs(a));
+}
+
+// -T as (d, e) of order n for the top-eigenpair solver, and zeroed
+// eigenvector storage.  T has order m <= n (m < n after a breakdown); the
+// remaining n - m diagonal entries are set to -4 max|T|, below every
+// eigenvalue of -T (Gershgorin: |alpha|, beta <= max|T|), with zero coupling,
+// so the top eigenpair is the one of the order-m block.  The Krylov vectors
+// beyond m are zero, so the padding never reaches psi.
+__global__ void lz_tridiag_kernel(const double* k, int n, double* d, double* e, double* z) {
+  const int m = (int)k[LZ_M];
+  const double pad = -4.0 * k[LZ_TMAX];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    d[i] = i < m ? -k[LZ_ALPHA + i] : (i < n ? pad : 0.0);
+    e[i] = i + 1 < m ? -k[LZ_BETA + i] : 0.0;
+    z[i] = 0.0;
+  }
+}
+
+// complex coefficients (z_i, 0) of psi = sum_i z_i v_i
+__global__ void lz_coef_kernel(const double* z, int m, double* c) {
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    c[2 * i] = z[i];
+    c[2 * i + 1] = 0.0;
+  }
+}
+
+// Factor that normalises psi and makes <theta, psi> real and positive:
+// conj(ov) / (|ov| ||psi||), or 1 / ||psi|| when the overlap vanishes.
+__global__ void lz_phase_kernel(double* k, const double* pn2, const double* ov) {
+  if (threadIdx.x != 0) return;
+  const double pn = sqrt(*pn2);
+  const double om = hypot(ov[0], ov[1]);
+  if (om > 0.0) {
+    k[LZ_SCALE] = ov[0] / om / pn;
+    k[LZ_SCALE + 1] = -ov[1] / om / pn;
+  } else {
+    k[LZ_SCALE] = 1.0 / pn;
+    k[LZ_SCALE + 1] = 0.0;
+  }
+  const bool ok = k[LZ_START] != 0.0 && pn > 0.0 && isfinite(pn) && isfinite(k[LZ_SCALE]) &&
+                  isfinite(k[LZ_SCALE + 1]);
+  k[LZ_VALID] = ok ? 1.0 : 0.0;
+}
+
 static void* noalloc_scratch_ptr(int device) {
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   return (device >= 0 && device < MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
@@ -289,22 +415,20 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   double* part = static_cast<double*>(ctx->arena.get(sizeof(double) * MULTIDOT_PARTIAL_DOUBLES));
   double* coef = static_cast<double*>(ctx->arena.get(sizeof(double) * 3 * 128));
   double* nrm = static_cast<double*>(ctx->arena.get(sizeof(double) * (SUMSQ_PARTIALS + 1)));
-  if (!basis || !w || !th || !xin || !yout || !part || !coef || !nrm) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
+  double* kst = static_cast<double*>(ctx->arena.get(sizeof(double) * LZ_WORDS));
+  if (!basis || !w || !th || !xin || !yout || !part || !coef || !nrm || !kst)
+    TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
   TCI_CHECK_HIP(convert(dt, theta->data, C128, th, N, s));
-  auto norm2 = [&](const cd* v, double& out) -> tci_status {
-    TCI_CHECK_HIP(sumsq_batched(C128, v, N, 0, nrm + SUMSQ_PARTIALS, nrm, 1, s));
-    TCI_CHECK_HIP(hipMemcpyAsync(&out, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
-    TCI_CHECK_HIP(hipStreamSynchronize(s));
-    return TCI_OK;
-  };
-  double n0 = 0.0;
-  TCI_TRY(norm2(th, n0));
-  n0 = std::sqrt(n0);
-  if (!(n0 > 0.0) || !std::isfinite(n0)) TCI_RET(TCI_ERR_NUMERIC, "starting vector has zero or non-finite norm");
-  if (c64) TCI_CHECK_HIP(scale_to_c64(th, 1.0 / n0, 0.0, basis, N, s));
-  else TCI_CHECK_HIP(scale_copy(th, 1.0 / n0, 0.0, basis, N, s));
-  std::vector<double> alpha, beta;
-  double tmax = 0.0;
+  TCI_CHECK_HIP(sumsq_batched(C128, th, N, 0, nrm + SUMSQ_PARTIALS, nrm, 1, s));
+  hipLaunchKernelGGL(lz_init_kernel, dim3(1), dim3(64), 0, s, kst, nrm + SUMSQ_PARTIALS);
+  TCI_CHECK_HIP(hipGetLastError());
+  if (c64) TCI_CHECK_HIP(scale_to_c64_dev(th, kst + LZ_SCALE, basis, N, s));
+  else TCI_CHECK_HIP(scale_copy_dev(th, kst + LZ_SCALE, basis, N, s));
+  // The whole solve is queued without waiting for the device: alpha, beta,
+  // the reorthogonalisation decision, the breakdown test and the final
+  // scaling live in kst, and the host reads them once, at the end.  After a
+  // breakdown (or from a zero start vector) the remaining steps run on zero
+  // vectors and record nothing.
   for (int j = 0; j < n_matvec; ++j) {
     const void* vj = basis + ves * (size_t)N * j;
     // w = H v_j (in the operands' dtype / precision)
@@ -322,62 +446,41 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
       TCI_CHECK_HIP(multidot(vj, 1, w, N, part, coef, s));
     }
     if (j == n_matvec - 1) {   // the last residual enters neither T nor psi
-      double hc[2];
-      TCI_CHECK_HIP(hipMemcpyAsync(hc, coef, sizeof(hc), hipMemcpyDeviceToHost, s));
-      TCI_CHECK_HIP(hipStreamSynchronize(s));
-      alpha.push_back(hc[0]);
+      hipLaunchKernelGGL(lz_last_kernel, dim3(1), dim3(64), 0, s, kst, coef, j);
+      TCI_CHECK_HIP(hipGetLastError());
       break;
     }
     // w -= alpha v_j + beta_{j-1} v_{j-1}, then classical Gram-Schmidt
     // against v_0..v_j.  The first sweep subtracts the three-term part and
     // forms c = V^H w; the second subtracts V c and returns ||w||^2.  A second
     // Gram-Schmidt pass (one more dot sweep and one more subtraction sweep)
-    // runs only when the first removed more than half of the norm,
-    // ||w_after||^2 < ||c||^2 (the criterion of Daniel, Gragg, Kaufman and
-    // Stewart, 1976, with ||w_before||^2 = ||w_after||^2 + ||c||^2); in exact
-    // arithmetic the second pass subtracts zero.
-    std::vector<double> c1(2 * (j + 1) + 1, 0.0), hc(2, 0.0);
+    // is launched every step but does its work only when the device decided
+    // that the first removed more than half of the norm; in exact arithmetic
+    // it subtracts zero.
     // bytes of one stored basis vector and of the working vector
     const double vbytes = (double)ves * (double)N, wbytes = (double)sizeof(cd) * (double)N;
     ProfTag tag("lanczos");
     {
       ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "sweep_dot");
-      TCI_CHECK_HIP(three_term_multidot(basis, j + 1, coef, j > 0 ? beta[j - 1] : 0.0, w, N, part, coef + 128, s, vdt));
+      TCI_CHECK_HIP(three_term_multidot(basis, j + 1, coef, j > 0 ? kst + LZ_BETA + j - 1 : nullptr, w, N, part,
+                                        coef + 128, s, vdt));
     }
     {
       ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "sweep_axpy");
       TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 128, -1.0, w, N, part, coef + 128 + 2 * (j + 1), s, vdt));
     }
-    TCI_CHECK_HIP(hipMemcpyAsync(hc.data(), coef, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-    TCI_CHECK_HIP(hipMemcpyAsync(c1.data(), coef + 128, sizeof(double) * c1.size(), hipMemcpyDeviceToHost, s));
-    TCI_CHECK_HIP(hipStreamSynchronize(s));
-    const double a = hc[0];
-    alpha.push_back(a);
-    tmax = std::max(tmax, std::fabs(a));
-    double b2 = c1[2 * (j + 1)], cn2 = 0.0;
-    for (int q = 0; q < 2 * (j + 1); ++q) cn2 += c1[q] * c1[q];
-    if (b2 < cn2) {
-      {
-        ProfScope ps(s, vbytes * (j + 1) + wbytes, "reorth2_dot");
-        TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef + 256, s, vdt));
-      }
-      {
-        ProfScope ps(s, vbytes * (j + 1) + 2 * wbytes, "reorth2_axpy");
-        TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, nrm + SUMSQ_PARTIALS, s, vdt));
-      }
-      TCI_CHECK_HIP(hipMemcpyAsync(&b2, nrm + SUMSQ_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, s));
-      TCI_CHECK_HIP(hipStreamSynchronize(s));
-    }
-    const double b = std::sqrt(b2);
-    tmax = std::max(tmax, b);
-    if (b <= 1e-13 * tmax) break;
-    beta.push_back(b);
+    hipLaunchKernelGGL(lz_decide_kernel, dim3(1), dim3(64), 0, s, kst, coef, j);
+    TCI_CHECK_HIP(hipGetLastError());
+    TCI_CHECK_HIP(multidot(basis, j + 1, w, N, part, coef + 256, s, vdt, kst + LZ_FLAG));
+    TCI_CHECK_HIP(multiaxpy_norm2(basis, j + 1, coef + 256, -1.0, w, N, part, kst + LZ_RB2, s, vdt, kst + LZ_FLAG));
+    hipLaunchKernelGGL(lz_beta_kernel, dim3(1), dim3(64), 0, s, kst, j);
+    TCI_CHECK_HIP(hipGetLastError());
     void* vnext = basis + ves * (size_t)N * (j + 1);
-    if (c64) TCI_CHECK_HIP(scale_to_c64(w, 1.0 / b, 0.0, vnext, N, s));
-    else TCI_CHECK_HIP(scale_copy(w, 1.0 / b, 0.0, vnext, N, s));
+    if (c64) TCI_CHECK_HIP(scale_to_c64_dev(w, kst + LZ_SCALE, vnext, N, s));
+    else TCI_CHECK_HIP(scale_copy_dev(w, kst + LZ_SCALE, vnext, N, s));
   }
-  const int m = (int)alpha.size();
   // lowest eigenpair of T = tridiag(alpha, beta): top eigenpair of -T on the device
+  const int n = n_matvec;
   double* dd = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
   double* ee = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
   double* e2 = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
@@ -385,46 +488,38 @@ tci_status tci_lanczos_ground(tci_context ctx, tci_tensor L, tci_tensor W1, tci_
   double* z = static_cast<double*>(ctx->arena.get(sizeof(double) * 64));
   double* iw = static_cast<double*>(ctx->arena.get(sizeof(double) * 4 * 64));
   if (!dd || !ee || !e2 || !lam || !z || !iw) TCI_RET(TCI_ERR_OUT_OF_MEMORY, "workspace");
-  std::vector<double> hd(m), he(std::max(m, 1), 0.0);
-  for (int i = 0; i < m; ++i) hd[i] = -alpha[i];
-  for (int i = 0; i + 1 < m; ++i) he[i] = -beta[i];
-  TCI_CHECK_HIP(hipMemcpyAsync(dd, hd.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(ee, he.data(), sizeof(double) * he.size(), hipMemcpyHostToDevice, s));
-  TCI_CHECK_HIP(tridiag_eigvals_top(dd, ee, e2, m, m, 1, lam, 1, 1, s));
-  TCI_CHECK_HIP(hipMemsetAsync(z, 0, sizeof(double) * m, s));
-  TCI_CHECK_HIP(tridiag_invit(dd, ee, m, m, lam, 1, nullptr, 1, z, 1, 0, iw, 1, s));
-  std::vector<double> hz(m);
-  double hl = 0.0;
-  TCI_CHECK_HIP(hipMemcpyAsync(hz.data(), z, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(&hl, lam, sizeof(double), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipStreamSynchronize(s));
-  // psi = sum_i y_i v_i
-  std::vector<double> cy(2 * m, 0.0);
-  for (int i = 0; i < m; ++i) cy[2 * i] = hz[i];
+  hipLaunchKernelGGL(lz_tridiag_kernel, dim3(1), dim3(64), 0, s, kst, n, dd, ee, z);
+  TCI_CHECK_HIP(hipGetLastError());
+  TCI_CHECK_HIP(tridiag_eigvals_top(dd, ee, e2, n, n, 1, lam, 1, 1, s));
+  TCI_CHECK_HIP(tridiag_invit(dd, ee, n, n, lam, 1, nullptr, 1, z, 1, 0, iw, 1, s));
+  // psi = sum_i z_i v_i
+  hipLaunchKernelGGL(lz_coef_kernel, dim3(1), dim3(64), 0, s, z, n, coef);
+  TCI_CHECK_HIP(hipGetLastError());
   TCI_CHECK_HIP(hipMemsetAsync(w, 0, sizeof(cd) * (size_t)N, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(coef, cy.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, s));
-  TCI_CHECK_HIP(multiaxpy(basis, m, coef, 1.0, w, N, s, vdt));
-  double pn2 = 0.0;
-  TCI_TRY(norm2(w, pn2));
-  const double pn = std::sqrt(pn2);
-  // phase: <theta, psi> real positive
-  double ov[2];
-  TCI_CHECK_HIP(multidot(th, 1, w, N, part, coef, s));
-  TCI_CHECK_HIP(hipMemcpyAsync(ov, coef, sizeof(ov), hipMemcpyDeviceToHost, s));
-  TCI_CHECK_HIP(hipStreamSynchronize(s));
-  const double om = std::hypot(ov[0], ov[1]);
-  double pr = 1.0 / pn, pi = 0.0;
-  if (om > 0.0) {
-    pr = ov[0] / om / pn;
-    pi = -ov[1] / om / pn;
-  }
+  TCI_CHECK_HIP(multiaxpy(basis, n, coef, 1.0, w, N, s, vdt));
+  TCI_CHECK_HIP(sumsq_batched(C128, w, N, 0, nrm + SUMSQ_PARTIALS, nrm, 1, s));
+  // normalise, with the phase that makes <theta, psi> real and positive;
+  // theta is left as it was when the solve failed (th still holds its
+  // complex128 copy then)
+  TCI_CHECK_HIP(multidot(th, 1, w, N, part, coef + 256, s));
+  hipLaunchKernelGGL(lz_phase_kernel, dim3(1), dim3(64), 0, s, kst, nrm + SUMSQ_PARTIALS, coef + 256);
+  TCI_CHECK_HIP(hipGetLastError());
   if (c64) {
-    TCI_CHECK_HIP(scale_to_c64(w, pr, pi, theta->data, N, s));
+    TCI_CHECK_HIP(scale_to_c64_dev(w, kst + LZ_SCALE, theta->data, N, s, kst + LZ_VALID));
   } else {
-    TCI_CHECK_HIP(scale_copy(w, pr, pi, th, N, s));
+    TCI_CHECK_HIP(scale_copy_dev(w, kst + LZ_SCALE, th, N, s, kst + LZ_VALID));
     TCI_CHECK_HIP(convert(C128, th, dt, theta->data, N, s));
   }
-  TCI_CHECK_HIP(hipStreamSynchronize(s));
+  double hk[LZ_WORDS], hl = 0.0;
+  TCI_CHECK_HIP(hipMemcpyAsync(hk, kst, sizeof(hk), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipMemcpyAsync(&hl, lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  TCI_CHECK_HIP(hipStreamSynchronize(s));   // the solve's only host synchronisation
+  if (ctx->verbose > 0)
+    tr.info += " krylov=" + std::to_string((int)hk[LZ_M]) + " reorth=" + std::to_string((int)hk[LZ_NREORTH]) +
+               " host_syncs=1";
+  if (hk[LZ_START] == 0.0) TCI_RET(TCI_ERR_NUMERIC, "starting vector has zero or non-finite norm");
+  if (hk[LZ_VALID] == 0.0 || !std::isfinite(hl) || !std::isfinite(hk[LZ_TMAX]))
+    TCI_RET(TCI_ERR_NUMERIC, "Lanczos recurrence produced a non-finite or zero Ritz vector");
   *energy = -hl;
   return TCI_OK;
 } TCI_API_CATCH

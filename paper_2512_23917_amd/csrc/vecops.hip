@@ -186,7 +186,8 @@ __device__ inline void ldv2(const cf* p, cd& a, cd& b) {
 // NV is a compile-time bound on nv so that the accumulators stay in registers.
 template <int NV, typename VT>
 __global__ __launch_bounds__(256) void multidot_partial_kernel(const VT* V, int nv, const cd* w, long long n,
-                                                               double* partial) {
+                                                               double* partial, const double* gate) {
+  if (gate && *gate == 0.0) return;   // the pass is switched off on the device
   __shared__ double sh[4][2 * NV];
   double accr[NV], acci[NV];
 #pragma unroll
@@ -232,7 +233,9 @@ __global__ __launch_bounds__(256) void multidot_partial_kernel(const VT* V, int 
 }
 
 // One workgroup per coefficient q: fixed-order sums of the block partials.
-__global__ __launch_bounds__(256) void multidot_final_kernel(const double* partial, int nparts, int nv, double* out) {
+__global__ __launch_bounds__(256) void multidot_final_kernel(const double* partial, int nparts, int nv, double* out,
+                                                             const double* gate = nullptr) {
+  if (gate && *gate == 0.0) return;
   __shared__ double sr[256], si[256];
   const int q = blockIdx.x, t = threadIdx.x;
   double ar = 0.0, ai = 0.0;
@@ -257,10 +260,11 @@ static unsigned md_grid(long long n) {
 // Launch tables with one instantiation per basis size (1..MD_MAXV), so that
 // each kernel holds exactly the registers its basis needs.
 template <typename VT>
-using MdLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const cd*, long long, double*);
+using MdLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const cd*, long long, double*, const double*);
 template <int NV, typename VT>
-void md_launch(unsigned g, hipStream_t s, const VT* V, int nv, const cd* w, long long n, double* partial) {
-  hipLaunchKernelGGL((multidot_partial_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, w, n, partial);
+void md_launch(unsigned g, hipStream_t s, const VT* V, int nv, const cd* w, long long n, double* partial,
+               const double* gate) {
+  hipLaunchKernelGGL((multidot_partial_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, w, n, partial, gate);
 }
 template <typename VT, int... I>
 constexpr std::array<MdLaunch<VT>, sizeof...(I)> md_make(std::integer_sequence<int, I...>) {
@@ -273,14 +277,14 @@ static const std::array<MdLaunch<VT>, MD_MAXV>& md_table() {
 }
 
 hipError_t multidot(const void* V, int nv, const void* w, long long n, double* partial, double* out,
-                    hipStream_t s, int vdt) {
+                    hipStream_t s, int vdt, const double* gate) {
   if (nv <= 0) return hipSuccess;
   if (nv > MD_MAXV || (vdt != C128 && vdt != C64)) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
   const cd* wc = (const cd*)w;
-  if (vdt == C64) md_table<cf>()[nv - 1](g, s, (const cf*)V, nv, wc, n, partial);
-  else md_table<cd>()[nv - 1](g, s, (const cd*)V, nv, wc, n, partial);
-  hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out);
+  if (vdt == C64) md_table<cf>()[nv - 1](g, s, (const cf*)V, nv, wc, n, partial, gate);
+  else md_table<cd>()[nv - 1](g, s, (const cd*)V, nv, wc, n, partial, gate);
+  hipLaunchKernelGGL(multidot_final_kernel, dim3(nv), dim3(256), 0, s, partial, (int)g, nv, out, gate);
   return hipGetLastError();
 }
 
@@ -336,7 +340,8 @@ hipError_t scale_to_c64(const void* x, double sr, double si, void* out, long lon
 // w += sign * sum_q c_q v_q; with nrm_part, block b also stores its part of ||w||^2.
 template <int NV, typename VT>
 __global__ __launch_bounds__(256) void multiaxpy_kernel(const VT* V, int nv, const double* c, double sign, cd* w,
-                                                        long long n, double* nrm_part) {
+                                                        long long n, double* nrm_part, const double* gate) {
+  if (gate && *gate == 0.0) return;   // the pass is switched off on the device
   __shared__ double sh[4];
   double cr[NV], ci[NV];
 #pragma unroll
@@ -384,7 +389,9 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(const VT* V, int nv, con
   }
 }
 
-__global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int nparts, double* out) {
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int nparts, double* out,
+                                                        const double* gate) {
+  if (gate && *gate == 0.0) return;
   __shared__ double sh[256];
   const int t = threadIdx.x;
   double a = 0.0;
@@ -399,11 +406,12 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const double* part, int 
 }
 
 template <typename VT>
-using MaLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const double*, double, cd*, long long, double*);
+using MaLaunch = void (*)(unsigned, hipStream_t, const VT*, int, const double*, double, cd*, long long, double*,
+                          const double*);
 template <int NV, typename VT>
 void ma_launch(unsigned g, hipStream_t s, const VT* V, int nv, const double* c, double sign, cd* w, long long n,
-               double* nrm_part) {
-  hipLaunchKernelGGL((multiaxpy_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, nrm_part);
+               double* nrm_part, const double* gate) {
+  hipLaunchKernelGGL((multiaxpy_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, nv, c, sign, w, n, nrm_part, gate);
 }
 template <typename VT, int... I>
 constexpr std::array<MaLaunch<VT>, sizeof...(I)> ma_make(std::integer_sequence<int, I...>) {
@@ -416,12 +424,12 @@ static const std::array<MaLaunch<VT>, MD_MAXV>& ma_table() {
 }
 
 static hipError_t multiaxpy_launch(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                                   double* nrm_part, hipStream_t s, int vdt) {
+                                   double* nrm_part, hipStream_t s, int vdt, const double* gate = nullptr) {
   if (vdt != C128 && vdt != C64) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
   cd* wc = (cd*)w;
-  if (vdt == C64) ma_table<cf>()[nv - 1](g, s, (const cf*)V, nv, c, sign, wc, n, nrm_part);
-  else ma_table<cd>()[nv - 1](g, s, (const cd*)V, nv, c, sign, wc, n, nrm_part);
+  if (vdt == C64) ma_table<cf>()[nv - 1](g, s, (const cf*)V, nv, c, sign, wc, n, nrm_part, gate);
+  else ma_table<cd>()[nv - 1](g, s, (const cd*)V, nv, c, sign, wc, n, nrm_part, gate);
   return hipGetLastError();
 }
 
@@ -438,10 +446,11 @@ hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* 
 // layout).  Only the two recurrence vectors are held across the update; the
 // others are streamed once for their dot.
 template <int NV, typename VT>
-__global__ __launch_bounds__(256) void three_term_dot_kernel(const VT* V, const double* palpha, double beta, cd* w,
-                                                             long long n, double* partial) {
+__global__ __launch_bounds__(256) void three_term_dot_kernel(const VT* V, const double* palpha, const double* pbeta,
+                                                             cd* w, long long n, double* partial) {
   __shared__ double sh[4][2 * NV];
   const double alpha = *palpha;
+  const double beta = pbeta ? *pbeta : 0.0;
   double accr[NV], acci[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
@@ -514,9 +523,9 @@ __global__ __launch_bounds__(256) void three_term_dot_kernel(const VT* V, const 
 }
 
 template <typename VT>
-using TtLaunch = void (*)(unsigned, hipStream_t, const VT*, const double*, double, cd*, long long, double*);
+using TtLaunch = void (*)(unsigned, hipStream_t, const VT*, const double*, const double*, cd*, long long, double*);
 template <int NV, typename VT>
-void tt_launch(unsigned g, hipStream_t s, const VT* V, const double* alpha, double beta, cd* w, long long n,
+void tt_launch(unsigned g, hipStream_t s, const VT* V, const double* alpha, const double* beta, cd* w, long long n,
                double* partial) {
   hipLaunchKernelGGL((three_term_dot_kernel<NV, VT>), dim3(g), dim3(256), 0, s, V, alpha, beta, w, n, partial);
 }
@@ -530,7 +539,7 @@ static const std::array<TtLaunch<VT>, MD_MAXV>& tt_table() {
   return t;
 }
 
-hipError_t three_term_multidot(const void* V, int nv, const double* alpha, double beta, void* w, long long n,
+hipError_t three_term_multidot(const void* V, int nv, const double* alpha, const double* beta, void* w, long long n,
                                double* partial, double* out, hipStream_t s, int vdt) {
   if (nv <= 0 || nv > MD_MAXV || (vdt != C128 && vdt != C64)) return hipErrorInvalidValue;
   const unsigned g = md_grid(n);
@@ -541,11 +550,11 @@ hipError_t three_term_multidot(const void* V, int nv, const double* alpha, doubl
 }
 
 hipError_t multiaxpy_norm2(const void* V, int nv, const double* c, double sign, void* w, long long n,
-                           double* partial, double* out, hipStream_t s, int vdt) {
+                           double* partial, double* out, hipStream_t s, int vdt, const double* gate) {
   if (nv <= 0 || nv > MD_MAXV) return hipErrorInvalidValue;
-  hipError_t e = multiaxpy_launch(V, nv, c, sign, w, n, partial, s, vdt);
+  hipError_t e = multiaxpy_launch(V, nv, c, sign, w, n, partial, s, vdt, gate);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, partial, (int)md_grid(n), out);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, partial, (int)md_grid(n), out, gate);
   return hipGetLastError();
 }
 
@@ -555,6 +564,37 @@ __global__ void scale_copy_kernel(const cd* x, double sr, double si, cd* w, long
     const cd v = x[i];
     w[i] = cd{sr * v.x - si * v.y, sr * v.y + si * v.x};
   }
+}
+
+// The same with the factor (ps[0] + i ps[1]) read on the device.
+__global__ void scale_copy_dev_kernel(const cd* x, const double* ps, cd* w, long long n, const double* gate) {
+  if (gate && *gate == 0.0) return;
+  const double sr = ps[0], si = ps[1];
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cd v = x[i];
+    w[i] = cd{sr * v.x - si * v.y, sr * v.y + si * v.x};
+  }
+}
+__global__ void scale_to_c64_dev_kernel(const cd* x, const double* ps, cf* out, long long n, const double* gate) {
+  if (gate && *gate == 0.0) return;
+  const double sr = ps[0], si = ps[1];
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cd a = x[i];
+    out[i] = cf{(float)(sr * a.x - si * a.y), (float)(sr * a.y + si * a.x)};
+  }
+}
+
+hipError_t scale_copy_dev(const void* x, const double* ps, void* w, long long n, hipStream_t s,
+                          const double* gate) {
+  hipLaunchKernelGGL(scale_copy_dev_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, ps, (cd*)w, n, gate);
+  return hipGetLastError();
+}
+
+hipError_t scale_to_c64_dev(const void* x, const double* ps, void* out, long long n, hipStream_t s,
+                            const double* gate) {
+  hipLaunchKernelGGL(scale_to_c64_dev_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const cd*)x, ps, (cf*)out, n,
+                     gate);
+  return hipGetLastError();
 }
 
 hipError_t scale_copy(const void* x, double sr, double si, void* w, long long n, hipStream_t s) {

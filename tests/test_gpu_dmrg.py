@@ -182,12 +182,14 @@ def test_dmrg_update_pipeline_matches_oracle(T, ctx):
     assert rel_fro(rec, np.einsum("asm,mtb->astb", u * sn[None, None, :], vh)) < 1e-8
 
 
-def test_lanczos_second_gram_schmidt_pass(T, ctx):
+def test_lanczos_second_gram_schmidt_pass(T, capfd):
     """Non-Hermitian environments on a 16-dimensional space: the residual of
     the three-term recurrence keeps large components along the older Krylov
     vectors, so the first Gram-Schmidt pass removes most of its norm and the
-    conditional second pass runs.  The result must still equal the oracle's,
-    which always takes two passes (the same quantities in exact arithmetic)."""
+    conditional second pass runs (the device takes that decision; the call
+    reports how often at verbosity 1).  The result must still equal the
+    oracle's, which always takes two passes (the same quantities in exact
+    arithmetic)."""
     g = synth.rng(2, 4242)
     chi = 2
     left = synth.complex_gaussian(g, (chi, 5, chi))
@@ -196,16 +198,82 @@ def test_lanczos_second_gram_schmidt_pass(T, ctx):
     x = synth.complex_gaussian(g, (chi, 2, 2, chi))
     mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
     e_ref, psi_ref, _, _ = odmrg.lanczos_ground(mv, x, n_matvec=15)
-    th = up(T, ctx, x, T.C128)
-    T.profile_enable(ctx, True)
-    try:
-        e = T.lanczos_ground(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
-                             up(T, ctx, right, T.C128), th, 15)
-        second = T.profile_query(ctx, "lanczos:reorth2_dot")[0]
-        first = T.profile_query(ctx, "lanczos:sweep_dot")[0]
-    finally:
-        T.profile_enable(ctx, False)
-    assert first >= 1
-    assert second >= 1
+    e, psi, fields = lanczos_logged(T, capfd, left, w, right, x, 15)
+    assert 1 <= fields["krylov"] <= 15
+    assert fields["reorth"] >= 1
+    assert fields["host_syncs"] == 1
     assert e == pytest.approx(e_ref, rel=1e-9)
-    assert rel_fro(th.numpy(), psi_ref) < 1e-7
+    assert rel_fro(psi, psi_ref) < 1e-7
+
+
+def lanczos_logged(T, capfd, left, w, right, x, nmv):
+    """Runs the solve on a verbosity-1 context; returns (energy, psi, fields
+    of the call's log line)."""
+    c = T.Context(0, verbosity=1)
+    try:
+        th = up(T, c, x, T.C128)
+        capfd.readouterr()
+        e = T.lanczos_ground(c, up(T, c, left, T.C128), up(T, c, w, T.C128), up(T, c, w, T.C128),
+                             up(T, c, right, T.C128), th, nmv)
+        psi = th.numpy()
+        del th
+    finally:
+        c.close()
+    err = capfd.readouterr().err
+    line = [l for l in err.splitlines() if l.startswith("TCI_VERBOSE: lanczos_ground")]
+    assert len(line) == 1, err
+    fields = dict(f.split("=") for f in line[0].split() if f.count("=") == 1 and not f.startswith("m="))
+    return e, psi, {k: int(v) for k, v in fields.items()}
+
+
+def test_lanczos_breakdown_matches_oracle(T, capfd):
+    """Trivial environments reduce H_eff to the two-site Heisenberg bond, whose
+    two distinct eigenvalues (-3/4 and 1/4) make the Krylov space of any start
+    vector at most two-dimensional: beta_1 vanishes and the recurrence stops
+    after the second matvec although ten were allowed.  The device decides the
+    breakdown on its own; T has the oracle's order, the energy is -3/4 and the
+    Ritz vector the oracle's.  One host synchronisation per solve."""
+    left, right = synth.trivial_environments()
+    w = synth.heisenberg_mpo()
+    x = synth.complex_gaussian(synth.rng(2, 31), (1, 2, 2, 1))
+    mv = lambda v: odmrg.heff_apply(left, w, w, right, v)
+    e_ref, psi_ref, alphas, _ = odmrg.lanczos_ground(mv, x, n_matvec=10)
+    e, psi, f = lanczos_logged(T, capfd, left, w, right, x, 10)
+    assert f["krylov"] == len(alphas) == 2
+    assert f["host_syncs"] == 1
+    assert e == pytest.approx(-0.75, abs=1e-13)
+    assert e == pytest.approx(e_ref, abs=1e-13)
+    assert rel_fro(psi, psi_ref) < 1e-12
+
+
+def test_lanczos_eigenvector_start(T, capfd):
+    """Started at the singlet (an eigenvector), the first residual is zero:
+    T is the single entry -3/4 and theta comes back as the singlet."""
+    left, right = synth.trivial_environments()
+    w = synth.heisenberg_mpo()
+    x = np.zeros((1, 2, 2, 1), dtype=np.complex128)
+    x[0, 0, 1, 0], x[0, 1, 0, 0] = 1 / np.sqrt(2), -1 / np.sqrt(2)
+    e, psi, f = lanczos_logged(T, capfd, left, w, right, x, 20)
+    assert f["krylov"] == 1
+    assert e == pytest.approx(-0.75, abs=1e-15)
+    np.testing.assert_allclose(psi, x, atol=1e-15)
+
+
+@pytest.mark.parametrize("bad", ["zero", "nan"])
+def test_lanczos_bad_start_vector(T, ctx, bad):
+    """A start vector with zero or non-finite norm is reported as
+    TCI_ERR_NUMERIC after the queued solve, and theta is left as it was."""
+    left, w, right, x = env(3, 55)
+    x = np.zeros_like(x) if bad == "zero" else x.copy()
+    if bad == "nan":
+        x[1, 0, 1, 2] = np.nan
+    th = up(T, ctx, x, T.C128)
+    with pytest.raises(T.TciError) as ei:
+        T.lanczos_ground(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                         up(T, ctx, right, T.C128), th, 12)
+    assert T.STATUS[ei.value.status] == "NUMERIC"
+    np.testing.assert_array_equal(th.numpy(), x)
+    # the context is usable afterwards
+    e = T.lanczos_ground(ctx, up(T, ctx, left, T.C128), up(T, ctx, w, T.C128), up(T, ctx, w, T.C128),
+                         up(T, ctx, right, T.C128), up(T, ctx, env(3, 55)[3], T.C128), 12)
+    assert np.isfinite(e)
