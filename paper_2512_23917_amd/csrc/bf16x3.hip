@@ -30,7 +30,6 @@ namespace tci {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 constexpr int XBM = 128, XBN = 128, XBK = 32;
 
@@ -119,7 +118,8 @@ hipError_t split_planes(int dtype, const void* src, long long ld, long long ssrc
 // registers and two waves share each SIMD: one wave's LDS and global-load
 // waits are covered by the other's matrix work.  Staging: each plane tile is
 // 128 rows x 32 k = 8 KB = 512 chunks of 16 bytes; thread t moves chunk t of
-// every plane of both operands.
+// every plane of both operands, straight from global memory into LDS
+// (global_load_lds, no staging registers), one k tile ahead.
 // ---------------------------------------------------------------------------
 constexpr int XWM = 64, XWN = 32;   // wave tile
 template <bool CPLX>
@@ -165,32 +165,32 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
       acc_ii[i][j] = f4v{0, 0, 0, 0};
     }
 
-  // chunk t: row t >> 2, k chunk t & 3
+  // Global -> LDS without registers: each wave moves rows 16 wid .. 16 wid + 15
+  // of every plane tile, lane l writing the 16 bytes at l * 16 of that
+  // 1 KB block (row 16 wid + l / 4, chunk position l & 3), so it loads the
+  // k chunk that the swizzle puts there, (l & 3) ^ swz(row).
   const int srow = t >> 2, skc = t & 3;
-  const int sko = 8 * (skc ^ (((srow >> 1) ^ (srow >> 2)) & 3));
-  u4v ra[NP], rb[NP];
-  auto fetch = [&](int k0) {
+  const int gk = 8 * (skc ^ (((srow >> 1) ^ (srow >> 2)) & 3));
+  typedef __attribute__((address_space(3))) void lds_void;
+  typedef __attribute__((address_space(1))) void glb_void;
+  const __bf16* ga = A + (long long)(m0 + srow) * a.Kp + gk;
+  const __bf16* gb = B + (long long)(n0 + srow) * a.Kp + gk;
+  auto issue = [&](int k0, int st) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      ra[p] = *reinterpret_cast<const u4v*>(A + p * pa + (long long)(m0 + srow) * a.Kp + k0 + skc * 8);
-      rb[p] = *reinterpret_cast<const u4v*>(B + p * pb + (long long)(n0 + srow) * a.Kp + k0 + skc * 8);
-    }
-  };
-  auto stash = [&](int st) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      *reinterpret_cast<u4v*>(&As[st][p][srow][sko]) = ra[p];
-      *reinterpret_cast<u4v*>(&Bs[st][p][srow][sko]) = rb[p];
+      __builtin_amdgcn_global_load_lds((glb_void*)(ga + p * pa + k0), (lds_void*)&As[st][p][16 * wid][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((glb_void*)(gb + p * pb + k0), (lds_void*)&Bs[st][p][16 * wid][0], 16, 0, 0);
     }
   };
 
   const int nk = a.Kp / XBK;
-  fetch(0);
-  stash(0);
-  __syncthreads();
+  issue(0, 0);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
+    // tile kt has landed for every wave (the barrier waits for this wave's
+    // loads), and every wave is done reading the other buffer
+    __syncthreads();
     bf8v fa[NP][IM], fb[NP][JN];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -201,9 +201,9 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
       for (int j = 0; j < JN; ++j)
         fb[p][j] = *reinterpret_cast<const bf8v*>(&Bs[cur][p][wn * XWN + j * 16 + lr][rd]);
     }
-    // the next tile's global loads go out after this step's fragment reads,
-    // so that the first matrix instructions do not wait behind them
-    if (more) fetch((kt + 1) * XBK);
+    // the next tile's loads go out after this step's fragment reads (the
+    // compiler waits for those reads before issuing them)
+    if (more) issue((kt + 1) * XBK, cur ^ 1);
 #pragma unroll
     for (int i = 0; i < IM; ++i) {
 #pragma unroll
@@ -224,8 +224,6 @@ __global__ __launch_bounds__(512) void gemm_planes_kernel(PlaneGemmArgs a) {
         }
       }
     }
-    if (more) stash(cur ^ 1);
-    __syncthreads();
   }
 
   // epilogue: C = alpha * acc + beta * C (rows 4*(l/16)+r, column l%16 of each block)
