@@ -58,6 +58,10 @@ __device__ inline void st(cd* p, double re, double im) { *p = cd{re, im}; }
 __device__ inline void st(float* p, float re, float) { *p = re; }
 __device__ inline void st(cf* p, float re, float im) { *p = cf{re, im}; }
 
+// Zeros that out-of-range tile elements are loaded from, so that the loads
+// need no select afterwards (device code reads it; nothing writes it).
+__device__ double g_zero_elem[4] = {0.0, 0.0, 0.0, 0.0};
+
 // ---------------------------------------------------------------------------
 // Staging: a BM x BK tile of op(A) and a BK x BN tile of op(B) are read from
 // global memory (each thread 8 consecutive elements along the contiguous
@@ -78,8 +82,8 @@ __device__ inline void stage_rows_tile(const T* __restrict__ A, long lda, int op
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int gk = k0 + kk0 + e;
-      R vr = 0, vi = 0;
-      if (gm < M && gk < K) ld(A + (long)gm * lda + gk, vr, vi);
+      R vr, vi;
+      ld((gm < M && gk < K) ? A + (long)gm * lda + gk : reinterpret_cast<const T*>(g_zero_elem), vr, vi);
       re[kk0 + e][r] = vr;
       im[kk0 + e][r] = sgn * vi;
     }
@@ -92,8 +96,8 @@ __device__ inline void stage_rows_tile(const T* __restrict__ A, long lda, int op
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int gm = m0 + r0 + e;
-      R vr = 0, vi = 0;
-      if (gm < M && gk < K) ld(A + (long)gk * lda + gm, vr, vi);
+      R vr, vi;
+      ld((gm < M && gk < K) ? A + (long)gk * lda + gm : reinterpret_cast<const T*>(g_zero_elem), vr, vi);
       re[kk][r0 + e] = vr;
       im[kk][r0 + e] = sgn * vi;
     }
@@ -115,8 +119,8 @@ __device__ inline void stage_cols_tile(const T* __restrict__ B, long ldb, int op
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int gn = n0 + c0 + e;
-      R vr = 0, vi = 0;
-      if (gn < N && gk < K) ld(B + (long)gk * ldb + gn, vr, vi);
+      R vr, vi;
+      ld((gn < N && gk < K) ? B + (long)gk * ldb + gn : reinterpret_cast<const T*>(g_zero_elem), vr, vi);
       re[kk][c0 + e] = vr;
       im[kk][c0 + e] = sgn * vi;
     }
@@ -129,13 +133,118 @@ __device__ inline void stage_cols_tile(const T* __restrict__ B, long ldb, int op
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int gk = k0 + kk0 + e;
-      R vr = 0, vi = 0;
-      if (gn < N && gk < K) ld(B + (long)gn * ldb + gk, vr, vi);
+      R vr, vi;
+      ld((gn < N && gk < K) ? B + (long)gn * ldb + gk : reinterpret_cast<const T*>(g_zero_elem), vr, vi);
       re[kk0 + e][c] = vr;
       im[kk0 + e][c] = sgn * vi;
     }
   }
 }
+
+// The same staging split in two halves, so that the global loads of the next
+// k tile are in flight while the current one is multiplied.  load() only
+// issues the loads (out-of-range elements read zeros); store() applies the
+// conjugation sign and writes LDS, so nothing waits on the loads before the
+// products.
+template <typename T, typename R, int ROWS, int BK>
+struct RowsStage {
+  static constexpr int PER = ROWS * BK / 256;
+  R re[PER], im[PER];
+  __device__ inline void load(const T* __restrict__ A, long lda, int op, int M, int K, int m0, int k0) {
+    const int t = threadIdx.x;
+    const T* zero = reinterpret_cast<const T*>(g_zero_elem);
+    if (op == OP_N || op == OP_R) {
+      constexpr int TPR = BK / PER;
+      const int r = t / TPR, kk0 = (t % TPR) * PER;
+      const int gm = m0 + r;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int gk = k0 + kk0 + e;
+        ld((gm < M && gk < K) ? A + (long)gm * lda + gk : zero, re[e], im[e]);
+      }
+    } else {
+      constexpr int TPK = ROWS / PER;
+      const int kk = t / TPK, r0 = (t % TPK) * PER;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int gm = m0 + r0 + e;
+        ld((gm < M && gk < K) ? A + (long)gk * lda + gm : zero, re[e], im[e]);
+      }
+    }
+  }
+  __device__ inline void store(int op, R (*sre)[ROWS + 2], R (*sim)[ROWS + 2]) const {
+    const int t = threadIdx.x;
+    const R sgn = (op == OP_R || op == OP_C) ? R(-1) : R(1);
+    if (op == OP_N || op == OP_R) {
+      constexpr int TPR = BK / PER;
+      const int r = t / TPR, kk0 = (t % TPR) * PER;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        sre[kk0 + e][r] = re[e];
+        sim[kk0 + e][r] = sgn * im[e];
+      }
+    } else {
+      constexpr int TPK = ROWS / PER;
+      const int kk = t / TPK, r0 = (t % TPK) * PER;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        sre[kk][r0 + e] = re[e];
+        sim[kk][r0 + e] = sgn * im[e];
+      }
+    }
+  }
+};
+
+template <typename T, typename R, int COLS, int BK>
+struct ColsStage {
+  static constexpr int PER = COLS * BK / 256;
+  R re[PER], im[PER];
+  __device__ inline void load(const T* __restrict__ B, long ldb, int op, int N, int K, int n0, int k0) {
+    const int t = threadIdx.x;
+    const T* zero = reinterpret_cast<const T*>(g_zero_elem);
+    if (op == OP_N || op == OP_R) {
+      constexpr int TPK = COLS / PER;
+      const int kk = t / TPK, c0 = (t % TPK) * PER;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int gn = n0 + c0 + e;
+        ld((gn < N && gk < K) ? B + (long)gk * ldb + gn : zero, re[e], im[e]);
+      }
+    } else {
+      constexpr int TPC = BK / PER;
+      const int c = t / TPC, kk0 = (t % TPC) * PER;
+      const int gn = n0 + c;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int gk = k0 + kk0 + e;
+        ld((gn < N && gk < K) ? B + (long)gn * ldb + gk : zero, re[e], im[e]);
+      }
+    }
+  }
+  __device__ inline void store(int op, R (*sre)[COLS + 2], R (*sim)[COLS + 2]) const {
+    const int t = threadIdx.x;
+    const R sgn = (op == OP_R || op == OP_C) ? R(-1) : R(1);
+    if (op == OP_N || op == OP_R) {
+      constexpr int TPK = COLS / PER;
+      const int kk = t / TPK, c0 = (t % TPK) * PER;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        sre[kk][c0 + e] = re[e];
+        sim[kk][c0 + e] = sgn * im[e];
+      }
+    } else {
+      constexpr int TPC = BK / PER;
+      const int c = t / TPC, kk0 = (t % TPC) * PER;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        sre[kk0 + e][c] = re[e];
+        sim[kk0 + e][c] = sgn * im[e];
+      }
+    }
+  }
+};
 
 __device__ inline void problem_dims(const GemmArgs& a, int b, int& M, int& N, int& K) {
   if (a.dims) {
@@ -152,7 +261,9 @@ __device__ inline void problem_dims(const GemmArgs& a, int b, int& M, int& N, in
 // owns a (BM/2) x (BN/2) sub-tile made of 16x16 MFMA blocks.  For complex T
 // the product uses four real MFMAs per block and k-step (re*re - im*im,
 // re*im + im*re).  f64 16x16x4 output layout: lane l, register r holds
-// row (l/16) + 4r, column l%16 of the block.
+// row (l/16) + 4r, column l%16 of the block.  The loads of k tile t+1 are
+// issued right after tile t is in LDS and land in registers while tile t is
+// multiplied (one LDS buffer, two barriers per tile).
 // ---------------------------------------------------------------------------
 template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
@@ -200,11 +311,22 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
       if constexpr (CPLX) acc_im[i][j] = d4{0, 0, 0, 0};
     }
 
+  // the next k tile is loaded into registers while this one is multiplied
+  RowsStage<T, double, BM, BK> sa;
+  ColsStage<T, double, BN, BK> sb;
+  if (kbeg < kend) {
+    sa.load(A, a.lda, a.opA, M, kend, m0, kbeg);
+    sb.load(B, a.ldb, a.opB, N, kend, n0, kbeg);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
-    stage_rows_tile<T, double, BM, BK>(A, a.lda, a.opA, M, kend, m0, k0, As_re, As_im);
-    stage_cols_tile<T, double, BN, BK>(B, a.ldb, a.opB, N, kend, n0, k0, Bs_re, Bs_im);
+    sa.store(a.opA, As_re, As_im);
+    sb.store(a.opB, Bs_re, Bs_im);
     __syncthreads();
+    if (k0 + BK < kend) {
+      sa.load(A, a.lda, a.opA, M, kend, m0, k0 + BK);
+      sb.load(B, a.ldb, a.opB, N, kend, n0, k0 + BK);
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double fa_re[FI], fa_im[FI], fb_re[FJ], fb_im[FJ];
