@@ -744,11 +744,31 @@ hipError_t tridiagonalize(int dtype, const TriArgs& a, int batch, hipStream_t s)
 // (d, e), j < kmax.  Sturm count: number of negative pivots of the LDL^T
 // factorisation of T - x I equals the number of eigenvalues below x.
 // ---------------------------------------------------------------------------
-__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+// The recurrence is one long dependent chain; d and e2 are the same for every
+// lane of the wave, so they are read in blocks of STURM_BLK entries ahead of
+// their use (one memory wait per block instead of one per step).
+constexpr int STURM_BLK = 16;
+__device__ inline int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x,
+                                  double pivmin) {
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
-  for (int i = 1; i < n; ++i) {
+  int i = 1;
+  for (; i + STURM_BLK <= n; i += STURM_BLK) {
+    double dd[STURM_BLK], ee[STURM_BLK];
+#pragma unroll
+    for (int u = 0; u < STURM_BLK; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i - 1 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < STURM_BLK; ++u) {
+      q = dd[u] - x - ee[u] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+  }
+  for (; i < n; ++i) {
     q = d[i] - x - e2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
