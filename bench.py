@@ -44,6 +44,7 @@ KERNEL_OF_CLASS = {  # kernel that carries each profiling class
     "c64_bf16x3_planes": ("gemm_planes_kernel<true>", "paper_2512_23917_amd/csrc/bf16x3.hip"),
     "c128_fp64": ("gemm_f64_kernel<cd,128,64>", "paper_2512_23917_amd/csrc/gemm.hip"),
     "hemv": ("tri_colC_kernel<cd,32>", "paper_2512_23917_amd/csrc/eig.hip"),
+    "tri_small": ("tri_small_kernel<double>", "paper_2512_23917_amd/csrc/eig.hip"),
 }
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
                  ("traffic_gemm_planes_c64_chi1024.txt", "traffic_gemm_f64_c128_tebd_chi1024.txt",
@@ -64,6 +65,9 @@ PEAKS = {  # MI355X published dense peaks
     "sweep_axpy": (8.0e12, "GB/s", "hbm"),
     "reorth2_dot": (8.0e12, "GB/s", "hbm"),
     "reorth2_axpy": (8.0e12, "GB/s", "hbm"),
+    # one-workgroup reduction of a small matrix: its bytes are the trailing
+    # triangle re-read per column (mostly from L2), priced against HBM
+    "tri_small": (8.0e12, "GB/s", "hbm"),
 }
 HEADLINE_CONFIG = 6       # seed family of the headline batch (seed = 251223917 + 1000 * config + index)
 POOL = 8                  # Haar isometries per side in the headline pool

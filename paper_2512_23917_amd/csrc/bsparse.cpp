@@ -140,13 +140,26 @@ struct BsGraphEntry {
   std::vector<size_t> arena_after;
   std::vector<TsvdStage> stages;
 };
+// Side streams on which the size classes' eigenvalue stages run side by
+// side (each class is a batch of a few hundred small problems, too few
+// workgroups to fill the GPU on its own), with the events that fork them
+// from and join them back to the calling stream; inside a recording the
+// fork and join become edges of the graph.
+constexpr int BS_SIDE_STREAMS = 7;
 struct BsGraphCache {
   hipStream_t cs = nullptr;
+  hipStream_t side[BS_SIDE_STREAMS] = {};
+  hipEvent_t fork = nullptr, join[BS_SIDE_STREAMS] = {};
   std::map<std::vector<long long>, BsGraphEntry> m;
   ~BsGraphCache() {
     for (auto& kv : m)
       if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     if (cs) (void)hipStreamDestroy(cs);
+    for (int k = 0; k < BS_SIDE_STREAMS; ++k) {
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+      if (join[k]) (void)hipEventDestroy(join[k]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
   }
 };
 constexpr size_t BS_GRAPH_MAX_ENTRIES = 16;
@@ -155,6 +168,17 @@ BsGraphCache* bs_cache(tci_context ctx) {
   if (!ctx->bs_graphs)
     ctx->bs_graphs = std::shared_ptr<void>(new BsGraphCache(), [](void* q) { delete static_cast<BsGraphCache*>(q); });
   return static_cast<BsGraphCache*>(ctx->bs_graphs.get());
+}
+
+// Creates the side streams (default priority) and events once per context.
+tci_status bs_side_init(BsGraphCache* gc) {
+  if (gc->fork) return TCI_OK;
+  for (int k = 0; k < BS_SIDE_STREAMS; ++k) {
+    TCI_CHECK_HIP(hipStreamCreateWithFlags(&gc->side[k], hipStreamNonBlocking));
+    TCI_CHECK_HIP(hipEventCreateWithFlags(&gc->join[k], hipEventDisableTiming));
+  }
+  TCI_CHECK_HIP(hipEventCreateWithFlags(&gc->fork, hipEventDisableTiming));
+  return TCI_OK;
 }
 
 // Host form of the truncation rule (Spec, trunc_svd, rules a-c) on the
@@ -463,12 +487,34 @@ tci_status tci_bs_two_site_update_batched(tci_context ctx, int n, const tci_bs_t
   }
 
   // the recordable first half: products, padding, eigenvalue stage
+  // The size classes are independent after the products: class 0 stays on
+  // the calling stream, the others run on side streams forked from it after
+  // the products and joined back before the phase ends.
+  BsGraphCache* sidec = bs_cache(ctx);
+  TCI_TRY(bs_side_init(sidec));
   auto phase1 = [&](hipStream_t s1) -> tci_status {
     TCI_CHECK_HIP(zero_fill(sbuf, sizeof(float) * sec_elems, s1));
     for (int ph = 0; ph < 2; ++ph) TCI_CHECK_HIP(grouped_launch(plan[ph], s1));
-    for (auto& bk : buckets) {
-      TCI_CHECK_HIP(pad_sectors(bk.pd, (int)bk.ids.size(), bk.theta, bk.S, s1));
-      TCI_TRY(tsvd_eigvals(ctx, TCI_F64, (int)bk.ids.size(), bk.S, bk.S, bk.theta, bk.S, bk.stage));
+    const int nside = std::min<int>(BS_SIDE_STREAMS, (int)buckets.size() - 1);
+    if (nside > 0) {
+      TCI_CHECK_HIP(hipEventRecord(sidec->fork, s1));
+      for (int k = 0; k < nside; ++k) TCI_CHECK_HIP(hipStreamWaitEvent(sidec->side[k], sidec->fork, 0));
+    }
+    const hipStream_t saved = ctx->stream;
+    for (size_t bi = 0; bi < buckets.size(); ++bi) {
+      Bucket& bk = buckets[bi];
+      const hipStream_t sb = bi == 0 ? s1 : sidec->side[(bi - 1) % nside];
+      ctx->stream = sb;   // the eigenvalue stage launches on the context stream
+      tci_status r = TCI_OK;
+      const hipError_t he = pad_sectors(bk.pd, (int)bk.ids.size(), bk.theta, bk.S, sb);
+      if (he == hipSuccess) r = tsvd_eigvals(ctx, TCI_F64, (int)bk.ids.size(), bk.S, bk.S, bk.theta, bk.S, bk.stage);
+      ctx->stream = saved;
+      TCI_CHECK_HIP(he);
+      TCI_TRY(r);
+    }
+    for (int k = 0; k < nside; ++k) {
+      TCI_CHECK_HIP(hipEventRecord(sidec->join[k], sidec->side[k]));
+      TCI_CHECK_HIP(hipStreamWaitEvent(s1, sidec->join[k], 0));
     }
     return TCI_OK;
   };

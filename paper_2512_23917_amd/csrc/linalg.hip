@@ -652,15 +652,25 @@ __global__ __launch_bounds__(256) void ortho_defect_kernel(const T* G, int k, do
 }
 
 // out[0] = max over problems of the sum of that problem's nparts partials
-__global__ void ortho_defect_final_kernel(const double* part, int nparts, int batch, double* out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// One thread per problem sums its partials in order (the same sum as a serial
+// pass), then the workgroup takes the maximum.
+__global__ __launch_bounds__(256) void ortho_defect_final_kernel(const double* part, int nparts, int batch,
+                                                                 double* out) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
   double mx = 0.0;
-  for (int b = 0; b < batch; ++b) {
+  for (int b = tid; b < batch; b += 256) {
     double t = 0.0;
     for (int x = 0; x < nparts; ++x) t += part[(long long)b * nparts + x];
     mx = fmax(mx, t);
   }
-  out[0] = mx;
+  red[tid] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = red[0];
 }
 
 // G <- M = strict upper triangle of G + (diag(G) - 1) / 2, lower triangle zero
@@ -691,7 +701,7 @@ hipError_t ortho_defect(int dtype, int mode, const void* Y, long long ldy, long 
     hipLaunchKernelGGL(ortho_defect_kernel<cd>, dim3(np, batch), dim3(256), 0, s, (const cd*)G, k, part);
   else
     hipLaunchKernelGGL(ortho_defect_kernel<double>, dim3(np, batch), dim3(256), 0, s, (const double*)G, k, part);
-  hipLaunchKernelGGL(ortho_defect_final_kernel, dim3(1), dim3(64), 0, s, part, np, batch, out);
+  hipLaunchKernelGGL(ortho_defect_final_kernel, dim3(1), dim3(256), 0, s, part, np, batch, out);
   return hipGetLastError();
 }
 
