@@ -220,8 +220,17 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     // value per thread; the kernel boundary made them visible)
     if (tid < 1 + 2 * NB) {
       const int nwg = tri_chunks(TriWs<T, NB>::nbt(n) - (ifin + 1) / TT);
+      // loads in groups of 8 (one wait per group), sums in chunk order
       T acc = EigT<T>::zero();
-      for (int k = 0; k < nwg; ++k) acc = add(acc, pc_in[(long)k * (1 + 2 * NB) + tid]);
+      int k = 0;
+      for (; k + 8 <= nwg; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pc_in[(long)(k + u) * (1 + 2 * NB) + tid];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = add(acc, v[u]);
+      }
+      for (; k < nwg; ++k) acc = add(acc, pc_in[(long)k * (1 + 2 * NB) + tid]);
       s_fc[tid] = acc;
     }
     __syncthreads();
@@ -244,8 +253,18 @@ __global__ __launch_bounds__(256) void tri_colA_kernel(TriArgs a, int row0, int 
     // w for this thread's row (4 threads share a row: each sums a quarter)
     T acc = EigT<T>::zero();
     if (rv) {
-#pragma unroll 4
-      for (int t = tb0 + part; t < nbt; t += 4)
+      // slots t = tb0 + part, +4, ...: loaded four at a time (every address
+      // is valid), the unused ones dropped, sums in slot order
+      int t = tb0 + part;
+      for (; t + 12 < nbt; t += 16) {
+        T pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv[u] = P[(long)(t + 4 * u) * n + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (tri_slot_used(t + 4 * u, r, tb0)) acc = add(acc, pv[u]);
+      }
+      for (; t < nbt; t += 4)
         if (tri_slot_used(t, r, tb0)) acc = add(acc, P[(long)t * n + r]);
 #pragma unroll 4
       for (int q = part; q < pp; q += 4) {
