@@ -61,6 +61,9 @@ __device__ inline void st(cf* p, float re, float im) { *p = cf{re, im}; }
 // Zeros that out-of-range tile elements are loaded from, so that the loads
 // need no select afterwards (device code reads it; nothing writes it).
 __device__ double g_zero_elem[4] = {0.0, 0.0, 0.0, 0.0};
+// Where the epilogue stores the values of out-of-range tile elements, so that
+// its stores need no branch (never read).
+__device__ double g_sink_elem[4];
 
 // ---------------------------------------------------------------------------
 // Staging: a BM x BK tile of op(A) and a BK x BN tile of op(B) are read from
@@ -377,42 +380,58 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs a) {
   const double* rs = a.rs ? a.rs + (long)b * a.s_rs : nullptr;
   const double* cs = a.cs ? a.cs + (long)b * a.s_cs : nullptr;
   const bool beta0 = (a.beta_re == 0.0 && a.beta_im == 0.0);
-  // one 16-row block row at a time: all of its C loads are issued before
-  // any store, so their latencies overlap (short-K updates are bound by them)
+  // one 16-row block row at a time; the C loads of block row i + 1 are issued
+  // before block row i is stored, so only the first block's load latency is
+  // exposed (short-K updates are bound by it); out-of-range elements read
+  // zeros, so no load sits behind a branch
+  const T* zero = reinterpret_cast<const T*>(g_zero_elem);
+  double c_re[2][FJ][4], c_im[2][FJ][4];
+  auto load_c = [&](int i, double (&cr)[FJ][4], double (&ci)[FJ][4]) {
+#pragma unroll
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
+        const int col = n0 + wn * WN + j * 16 + lr;
+        ld((row < M && col < N) ? C + (long)row * a.ldc + col : zero, cr[j][r], ci[j][r]);
+      }
+  };
+  // row scales of a block row (rows clamped into range: values of rows and
+  // columns outside the problem go to the sink), loaded with its C values
+  double rsv[2][4];
+  auto load_rs = [&](int i, double (&v)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = rs ? rs[min(m0 + wm * WM + i * 16 + lk + 4 * r, M - 1)] : 1.0;
+  };
+  double csv[FJ];
+#pragma unroll
+  for (int j = 0; j < FJ; ++j) csv[j] = cs ? cs[min(n0 + wn * WN + j * 16 + lr, N - 1)] : 1.0;
+  load_rs(0, rsv[0]);
+  if (!beta0) load_c(0, c_re[0], c_im[0]);
 #pragma unroll
   for (int i = 0; i < FI; ++i) {
-    double c_re[FJ][4], c_im[FJ][4];
+    if (i + 1 < FI) {
+      load_rs(i + 1, rsv[(i + 1) & 1]);
+      if (!beta0) load_c(i + 1, c_re[(i + 1) & 1], c_im[(i + 1) & 1]);
+    }
 #pragma unroll
     for (int j = 0; j < FJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
         const int col = n0 + wn * WN + j * 16 + lr;
-        c_re[j][r] = 0.0;
-        c_im[j][r] = 0.0;
-        if (!beta0 && row < M && col < N) ld(C + (long)row * a.ldc + col, c_re[j][r], c_im[j][r]);
-      }
-#pragma unroll
-    for (int j = 0; j < FJ; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
-        const int col = n0 + wn * WN + j * 16 + lr;
-        if (row < M && col < N) {
-          double vr = acc_re[i][j][r], vi = 0.0;
-          if constexpr (CPLX) vi = acc_im[i][j][r];
-          double sc = 1.0;
-          if (rs) sc *= rs[row];
-          if (cs) sc *= cs[col];
-          vr *= sc; vi *= sc;
-          double outr = a.alpha_re * vr - a.alpha_im * vi;
-          double outi = a.alpha_re * vi + a.alpha_im * vr;
-          if (!beta0) {
-            outr += a.beta_re * c_re[j][r] - a.beta_im * c_im[j][r];
-            outi += a.beta_re * c_im[j][r] + a.beta_im * c_re[j][r];
-          }
-          st(C + (long)row * a.ldc + col, outr, outi);
+        double vr = acc_re[i][j][r], vi = 0.0;
+        if constexpr (CPLX) vi = acc_im[i][j][r];
+        const double sc = rsv[i & 1][r] * csv[j];
+        vr *= sc; vi *= sc;
+        double outr = a.alpha_re * vr - a.alpha_im * vi;
+        double outi = a.alpha_re * vi + a.alpha_im * vr;
+        if (!beta0) {
+          const double cr = c_re[i & 1][j][r], ci = c_im[i & 1][j][r];
+          outr += a.beta_re * cr - a.beta_im * ci;
+          outi += a.beta_re * ci + a.beta_im * cr;
         }
+        st((row < M && col < N) ? C + (long)row * a.ldc + col : reinterpret_cast<T*>(g_sink_elem), outr, outi);
       }
   }
 }
