@@ -577,71 +577,63 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < FJ; ++j) { acc_re[i][j] = f4{0, 0, 0, 0}; acc_im[i][j] = f4{0, 0, 0, 0}; }
 
+  // the next k tile is loaded into registers while this one is multiplied;
+  // the split into bf16 planes happens when it is written to LDS
+  RowsStage<T, float, BM, BK> sa;
+  ColsStage<T, float, BN, BK> sb;
+  sa.load(A, a.lda, a.opA, M, K, m0, 0);
+  sb.load(B, a.ldb, a.opB, N, K, n0, 0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
-    // stage op(A): tile (r, kk) -> As[plane][r][kk]
+    // op(A) tile (r, kk) -> As[plane][r][kk]
     {
-      constexpr int PER = BM * BK / 256;
+      constexpr int PER = decltype(sa)::PER;
+      const float sgn = (a.opA == OP_R || a.opA == OP_C) ? -1.f : 1.f;
       if (a.opA == OP_N || a.opA == OP_R) {
         constexpr int TPR = BK / PER;
         const int r = t / TPR, kk0 = (t % TPR) * PER;
-        const int gm = m0 + r;
-        const float sgn = (a.opA == OP_R) ? -1.f : 1.f;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int gk = k0 + kk0 + e;
-          float vr = 0.f, vi = 0.f;
-          if (gm < M && gk < K) ld(A + (long)gm * a.lda + gk, vr, vi);
-          split_bf16(vr, As[0][r][kk0 + e], As[1][r][kk0 + e]);
-          if constexpr (CPLX) split_bf16(sgn * vi, As[2][r][kk0 + e], As[3][r][kk0 + e]);
+          split_bf16(sa.re[e], As[0][r][kk0 + e], As[1][r][kk0 + e]);
+          if constexpr (CPLX) split_bf16(sgn * sa.im[e], As[2][r][kk0 + e], As[3][r][kk0 + e]);
         }
       } else {
         constexpr int TPK = BM / PER;
         const int kk = t / TPK, r0 = (t % TPK) * PER;
-        const int gk = k0 + kk;
-        const float sgn = (a.opA == OP_C) ? -1.f : 1.f;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int gm = m0 + r0 + e;
-          float vr = 0.f, vi = 0.f;
-          if (gm < M && gk < K) ld(A + (long)gk * a.lda + gm, vr, vi);
-          split_bf16(vr, As[0][r0 + e][kk], As[1][r0 + e][kk]);
-          if constexpr (CPLX) split_bf16(sgn * vi, As[2][r0 + e][kk], As[3][r0 + e][kk]);
+          split_bf16(sa.re[e], As[0][r0 + e][kk], As[1][r0 + e][kk]);
+          if constexpr (CPLX) split_bf16(sgn * sa.im[e], As[2][r0 + e][kk], As[3][r0 + e][kk]);
         }
       }
     }
-    // stage op(B): tile (kk, c) -> Bs[plane][c][kk]
+    // op(B) tile (kk, c) -> Bs[plane][c][kk]
     {
-      constexpr int PER = BN * BK / 256;
+      constexpr int PER = decltype(sb)::PER;
+      const float sgn = (a.opB == OP_R || a.opB == OP_C) ? -1.f : 1.f;
       if (a.opB == OP_N || a.opB == OP_R) {
         constexpr int TPK = BN / PER;
         const int kk = t / TPK, c0 = (t % TPK) * PER;
-        const int gk = k0 + kk;
-        const float sgn = (a.opB == OP_R) ? -1.f : 1.f;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int gn = n0 + c0 + e;
-          float vr = 0.f, vi = 0.f;
-          if (gn < N && gk < K) ld(B + (long)gk * a.ldb + gn, vr, vi);
-          split_bf16(vr, Bs[0][c0 + e][kk], Bs[1][c0 + e][kk]);
-          if constexpr (CPLX) split_bf16(sgn * vi, Bs[2][c0 + e][kk], Bs[3][c0 + e][kk]);
+          split_bf16(sb.re[e], Bs[0][c0 + e][kk], Bs[1][c0 + e][kk]);
+          if constexpr (CPLX) split_bf16(sgn * sb.im[e], Bs[2][c0 + e][kk], Bs[3][c0 + e][kk]);
         }
       } else {
         constexpr int TPC = BK / PER;
         const int c = t / TPC, kk0 = (t % TPC) * PER;
-        const int gn = n0 + c;
-        const float sgn = (a.opB == OP_C) ? -1.f : 1.f;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int gk = k0 + kk0 + e;
-          float vr = 0.f, vi = 0.f;
-          if (gn < N && gk < K) ld(B + (long)gn * a.ldb + gk, vr, vi);
-          split_bf16(vr, Bs[0][c][kk0 + e], Bs[1][c][kk0 + e]);
-          if constexpr (CPLX) split_bf16(sgn * vi, Bs[2][c][kk0 + e], Bs[3][c][kk0 + e]);
+          split_bf16(sb.re[e], Bs[0][c][kk0 + e], Bs[1][c][kk0 + e]);
+          if constexpr (CPLX) split_bf16(sgn * sb.im[e], Bs[2][c][kk0 + e], Bs[3][c][kk0 + e]);
         }
       }
     }
     __syncthreads();
+    if (k0 + BK < K) {
+      sa.load(A, a.lda, a.opA, M, K, m0, k0 + BK);
+      sb.load(B, a.ldb, a.opB, N, K, n0, k0 + BK);
+    }
 
     bf8 fa[NPL][FI], fb[NPL][FJ];
 #pragma unroll
