@@ -29,8 +29,8 @@ hipError_t multidot(const void* V, int nv, const void* w, long long n, double* p
 hipError_t multiaxpy(const void* V, int nv, const double* c, double sign, void* w, long long n, hipStream_t s,
                      int vdt = C128);
 // Lanczos recurrence fused with the multidot of its result:
-// w -= alpha v_{nv-1} + beta v_{nv-2} (alpha: one device double; beta
-// ignored for nv = 1), then out[2q], out[2q+1] = <v_q, w> for q < nv
+// w -= alpha v_{nv-1} + beta v_{nv-2} (alpha, beta: device doubles; beta
+// null for zero, ignored for nv = 1), then out[2q], out[2q+1] = <v_q, w> for q < nv
 // (partial: MULTIDOT_PARTIAL_DOUBLES doubles of workspace)
 hipError_t three_term_multidot(const void* V, int nv, const double* alpha, const double* beta, void* w, long long n,
                                double* partial, double* out, hipStream_t s, int vdt = C128);
