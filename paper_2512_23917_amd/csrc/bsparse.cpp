@@ -173,9 +173,9 @@ BsGraphCache* bs_cache(tci_context ctx) {
 // Creates the side streams (default priority) and events once per context.
 tci_status bs_side_init(BsGraphCache* gc) {
   if (gc->fork) return TCI_OK;
-  for (int k = 0; k < BS_SIDE_STREAMS; ++k) {
-    TCI_CHECK_HIP(hipStreamCreateWithFlags(&gc->side[k], hipStreamNonBlocking));
-    TCI_CHECK_HIP(hipEventCreateWithFlags(&gc->join[k], hipEventDisableTiming));
+  for (int k = 0; k < BS_SIDE_STREAMS; ++k) {   // a failed earlier attempt keeps what it made
+    if (!gc->side[k]) TCI_CHECK_HIP(hipStreamCreateWithFlags(&gc->side[k], hipStreamNonBlocking));
+    if (!gc->join[k]) TCI_CHECK_HIP(hipEventCreateWithFlags(&gc->join[k], hipEventDisableTiming));
   }
   TCI_CHECK_HIP(hipEventCreateWithFlags(&gc->fork, hipEventDisableTiming));
   return TCI_OK;
